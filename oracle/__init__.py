@@ -1,0 +1,179 @@
+"""Plain FP64 CPU oracle of the semi-implicit IMEX hSGN step (arXiv 2510.07539).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark may import this package.  It shares no code with the HIP
+library; the C source `hsgn_oracle.c` is compiled here with gcc (no
+-ffast-math, no FMA contraction) into `liboracle.so`.
+
+Python side: ctypes marshalling plus a few helpers that follow the paper's
+definitions directly (no arithmetic of the scheme lives in this file).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hsgn_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OK, ENONPHYS, ENONCOERCIVE, EINVAL = 0, 1, 2, 3
+BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (portable flags, OpenMP over instances)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-label",
+           _SRC, "-o", tmp, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(C.Structure):
+    _fields_ = [("g", C.c_double), ("lam", C.c_double), ("dx", C.c_double),
+                ("cfl", C.c_double), ("mcfl", C.c_double), ("dt_fixed", C.c_double),
+                ("t_end", C.c_double), ("bc", C.c_int), ("has_b", C.c_int)]
+
+
+class StageDbg(C.Structure):
+    _fields_ = [(k, C.POINTER(C.c_double)) for k in
+                ("qd", "md", "Wd", "beta", "S", "phi", "T", "P0", "pt0",
+                 "lo", "di", "up", "rhs", "hbar", "Fq", "Fm", "FW")]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        L.or_stage.restype = C.c_int
+        L.or_stage.argtypes = [C.c_int, C.POINTER(Params), C.c_double, dp] + [dp] * 12 + [C.POINTER(StageDbg)]
+        L.or_dt.restype = C.c_double
+        L.or_dt.argtypes = [C.c_int, C.POINTER(Params), dp, dp, C.c_double]
+        L.or_step.restype = C.c_int
+        L.or_step.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, dp, dp]
+        L.or_run.restype = C.c_int
+        L.or_run.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, dp, C.c_int]
+        L.or_run_batch.restype = C.c_int
+        L.or_run_batch.argtypes = [C.c_int, C.POINTER(C.c_longlong), C.POINTER(Params), dp,
+                                   dp, dp, dp, dp, dp, C.c_int, C.c_int, C.POINTER(C.c_int)]
+        L.or_tridiag.restype = C.c_int
+        L.or_tridiag.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, dp]
+        L.or_gamma.restype = C.c_double
+        L.or_max_threads.restype = C.c_int
+        L.or_tableau.restype = None
+        L.or_tableau.argtypes = [dp]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_params(g=9.81, lam=100.0, dx=1.0, cfl=0.9, mcfl=0.5, dt_fixed=0.0,
+                t_end=0.0, bc=BC_PERIODIC, has_b=0) -> Params:
+    return Params(g, lam, dx, cfl, mcfl, dt_fixed, t_end, int(bc), int(has_b))
+
+
+def gamma() -> float:
+    return lib().or_gamma()
+
+
+def tableau():
+    """(gamma, 1 - c/gamma, c/gamma, 1 - (1-gamma)/gamma, (1-gamma)/gamma) as used."""
+    out = np.empty(5)
+    lib().or_tableau(_p(out))
+    return tuple(out)
+
+
+def max_threads() -> int:
+    return lib().or_max_threads()
+
+
+def _f(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def stage(p: Params, tau, b, UE, Uold, debug=False):
+    """One semi-implicit stage.  UE, Uold: 4-tuples (h, q, m, W).
+    Returns (rc, Unew[, dbg dict])."""
+    n = len(UE[0])
+    UE = [_f(a) for a in UE]
+    Uo = [_f(a) for a in Uold]
+    out = [np.empty(n) for _ in range(4)]
+    bb = _f(b) if b is not None else None
+    dbg = None
+    arrays = {}
+    if debug:
+        for k, _ in StageDbg._fields_:
+            arrays[k] = np.empty(n + 1 if k in ("Fq", "Fm", "FW") else n)
+        dbg = StageDbg(**{k: _p(v) for k, v in arrays.items()})
+    rc = lib().or_stage(n, C.byref(p), float(tau), _p(bb), *[_p(a) for a in UE],
+                        *[_p(a) for a in Uo], *[_p(a) for a in out],
+                        C.byref(dbg) if dbg is not None else None)
+    if debug:
+        return rc, tuple(out), arrays
+    return rc, tuple(out)
+
+
+def dt(p: Params, h, q, t=0.0) -> float:
+    h, q = _f(h), _f(q)
+    return lib().or_dt(len(h), C.byref(p), _p(h), _p(q), float(t))
+
+
+def step(p: Params, b, U, t=0.0):
+    """One IMEX step; returns (rc, Unew, t_new, dt)."""
+    U = [np.array(a, dtype=np.float64, copy=True) for a in U]
+    tt = C.c_double(t)
+    dtt = C.c_double(0.0)
+    bb = _f(b) if b is not None else None
+    rc = lib().or_step(len(U[0]), C.byref(p), _p(bb), *[_p(a) for a in U],
+                       C.pointer(tt), C.pointer(dtt))
+    return rc, tuple(U), tt.value, dtt.value
+
+
+def run(p: Params, b, U, t=0.0, nsteps=1):
+    """nsteps IMEX steps; returns (rc, Unew, t_new)."""
+    U = [np.array(a, dtype=np.float64, copy=True) for a in U]
+    tt = C.c_double(t)
+    bb = _f(b) if b is not None else None
+    rc = lib().or_run(len(U[0]), C.byref(p), _p(bb), *[_p(a) for a in U],
+                      C.pointer(tt), int(nsteps))
+    return rc, tuple(U), tt.value
+
+
+def run_batch(offsets, plist, b, U, t, nsteps, nthreads=0):
+    """Batched instances (OpenMP over instances).  Returns (rc, Unew, t, status)."""
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_inst = len(offs) - 1
+    parr = (Params * n_inst)(*plist)
+    U = [np.array(a, dtype=np.float64, copy=True) for a in U]
+    tt = np.array(t, dtype=np.float64, copy=True).reshape(n_inst)
+    st = np.zeros(n_inst, dtype=np.int32)
+    bb = _f(b) if b is not None else None
+    rc = lib().or_run_batch(n_inst, offs.ctypes.data_as(C.POINTER(C.c_longlong)), parr,
+                            _p(bb), *[_p(a) for a in U], _p(tt), int(nsteps), int(nthreads),
+                            st.ctypes.data_as(C.POINTER(C.c_int)))
+    return rc, tuple(U), tt, st
+
+
+def tridiag(lo, di, up, rhs, cyclic=False):
+    lo, di, up, rhs = _f(lo), _f(di), _f(up), _f(rhs)
+    x = np.empty(len(di))
+    rc = lib().or_tridiag(len(di), int(bool(cyclic)), _p(lo), _p(di), _p(up), _p(rhs), _p(x))
+    return rc, x

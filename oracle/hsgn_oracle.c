@@ -1,0 +1,443 @@
+/*
+ * hsgn_oracle.c -- plain, slow, obviously-correct FP64 CPU oracle of the
+ * semi-implicit (IMEX) hSGN time step of Macca, Boscheri & Ricchiuto,
+ * "Semi-implicit strategies for the Serre-Green-Naghdi equations in
+ * hyperbolic form" (arXiv 2510.07539).
+ *
+ * TEST INFRASTRUCTURE ONLY: it exists to check the HIP library; the product
+ * path never links or calls it.  No blocking, fusion or reordering: every
+ * stage follows the paper's order (explicit convective predictor, exact
+ * relaxation elimination, linearised elliptic problem for the new depth,
+ * back-substitution), one loop per formula.
+ *
+ * Readings of the paper taken here (each is discussed in the design notes):
+ *  - the stage is the fully discrete first-order semi-implicit step of
+ *    Sec. 4.2 (eq. GN_hyp_eq_semi_fully_discrete) with dt -> tau, explicit
+ *    terms and frozen coefficients taken from the explicit stage value U_E,
+ *    "old" values from the implicit combination (Sec. 3.2, eq. tableau);
+ *  - the implicit pressure is differenced in conservative form: the
+ *    linearised pressure P = P0 + beta (hbar - h_E), with the paper's beta
+ *    (Sec. 4.2) and P0 the exact pressure at hbar = h_E, is differenced at
+ *    faces, instead of applying central differences to hbar and h*eta
+ *    separately;
+ *  - the Rusanov speed is max(|u| + sqrt(g h)) over the two face states
+ *    (the paper writes "alpha ~ |u|", which leaves the explicit acoustic
+ *    coupling undamped at rest);
+ *  - with a bed, m = h*eta is stored and its equation carries the exact
+ *    rewrite source -(3/2) q b_x of the h*eta-tilde equation (eq. hSGNb_eq);
+ *    the momentum source (g h + (3/2) p~) b_x is treated implicitly with
+ *    p~ linearised like P; the m-diffusion of the Rusanov flux subtracts the
+ *    face-local lake-at-rest moment so that rest is preserved;
+ *  - boundary conditions: periodic, or transmissive (zero-order copy into
+ *    two ghost cells, zero implicit force at the boundary face).
+ */
+#include "hsgn_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Double Butcher tableau of Sec. 3.2 (eq. tableau): gamma = 1 - 1/sqrt(2),
+ * c = 1/(2 gamma).  Efficient form of the remark after the tableau:
+ *   U_E^(2) = (1 - c/gamma) U^n + (c/gamma) U_I^(1)
+ *   U~      = (1 - (1-gamma)/gamma) U^n + ((1-gamma)/gamma) U_I^(1)
+ * with c/gamma = 3 + 2 sqrt(2) and (1-gamma)/gamma = 1 + sqrt(2). */
+static const double OR_GAMMA = 0.29289321881345247560;
+static const double OR_E0 = -4.82842712474619009760; /* 1 - c/gamma */
+static const double OR_E1 = 5.82842712474619009760;  /* c/gamma */
+static const double OR_T0 = -1.41421356237309504880; /* 1 - (1-gamma)/gamma */
+static const double OR_T1 = 2.41421356237309504880;  /* (1-gamma)/gamma */
+
+double or_gamma(void) { return OR_GAMMA; }
+
+void or_tableau(double* out) {
+  out[0] = OR_GAMMA;
+  out[1] = OR_E0;
+  out[2] = OR_E1;
+  out[3] = OR_T0;
+  out[4] = OR_T1;
+}
+
+int or_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* Cell index with ghosts: periodic wrap or zero-order copy (transmissive). */
+static int gidx(int i, int n, int bc) {
+  if (bc == 0) return ((i % n) + n) % n;
+  if (i < 0) return 0;
+  if (i > n - 1) return n - 1;
+  return i;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Tridiagonal solvers: Thomas, and Sherman-Morrison for the cyclic case.   */
+/* ---------------------------------------------------------------------- */
+static int thomas(int n, const double* lo, const double* di, const double* up,
+                  const double* rhs, double* x) {
+  double* cp = (double*)malloc(sizeof(double) * (size_t)n);
+  double* dp = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!cp || !dp) { free(cp); free(dp); return OR_EINVAL; }
+  cp[0] = up[0] / di[0];
+  dp[0] = rhs[0] / di[0];
+  for (int i = 1; i < n; ++i) {
+    double den = di[i] - lo[i] * cp[i - 1];
+    cp[i] = up[i] / den;
+    dp[i] = (rhs[i] - lo[i] * dp[i - 1]) / den;
+  }
+  x[n - 1] = dp[n - 1];
+  for (int i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+  free(cp);
+  free(dp);
+  return OR_OK;
+}
+
+int or_tridiag(int n, int cyclic, const double* lo, const double* di,
+               const double* up, const double* rhs, double* x) {
+  if (n < 1) return OR_EINVAL;
+  if (n == 1) {
+    double d = di[0] + (cyclic ? lo[0] + up[0] : 0.0);
+    x[0] = rhs[0] / d;
+    return OR_OK;
+  }
+  if (!cyclic || n == 2) {
+    if (!cyclic) return thomas(n, lo, di, up, rhs, x);
+    /* n == 2 cyclic: both couplings hit the other unknown. */
+    double a00 = di[0], a01 = up[0] + lo[0];
+    double a10 = lo[1] + up[1], a11 = di[1];
+    double det = a00 * a11 - a01 * a10;
+    x[0] = (rhs[0] * a11 - a01 * rhs[1]) / det;
+    x[1] = (a00 * rhs[1] - a10 * rhs[0]) / det;
+    return OR_OK;
+  }
+  /* Cyclic: A = B + u v^T with u = (gam, 0..0, up[n-1]),
+   * v = (1, 0..0, lo[0]/gam); B has the corners removed and the two
+   * diagonal ends corrected. */
+  double gam = -di[0];
+  double* dd = (double*)malloc(sizeof(double) * (size_t)n);
+  double* u = (double*)malloc(sizeof(double) * (size_t)n);
+  double* y = (double*)malloc(sizeof(double) * (size_t)n);
+  double* z = (double*)malloc(sizeof(double) * (size_t)n);
+  double* l2 = (double*)malloc(sizeof(double) * (size_t)n);
+  double* u2 = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!dd || !u || !y || !z || !l2 || !u2) {
+    free(dd); free(u); free(y); free(z); free(l2); free(u2);
+    return OR_EINVAL;
+  }
+  for (int i = 0; i < n; ++i) {
+    dd[i] = di[i];
+    u[i] = 0.0;
+    l2[i] = lo[i];
+    u2[i] = up[i];
+  }
+  l2[0] = 0.0;
+  u2[n - 1] = 0.0;
+  dd[0] = di[0] - gam;
+  dd[n - 1] = di[n - 1] - up[n - 1] * lo[0] / gam;
+  u[0] = gam;
+  u[n - 1] = up[n - 1];
+  int rc = thomas(n, l2, dd, u2, rhs, y);
+  if (rc == OR_OK) rc = thomas(n, l2, dd, u2, u, z);
+  if (rc == OR_OK) {
+    double vy = y[0] + lo[0] / gam * y[n - 1];
+    double vz = z[0] + lo[0] / gam * z[n - 1];
+    double f = vy / (1.0 + vz);
+    for (int i = 0; i < n; ++i) x[i] = y[i] - f * z[i];
+  }
+  free(dd); free(u); free(y); free(z); free(l2); free(u2);
+  return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* One semi-implicit stage (Sec. 4.2, eq. GN_hyp_eq_semi_fully_discrete).   */
+/* ---------------------------------------------------------------------- */
+int or_stage(int n, const or_params* p, double tau, const double* bin,
+             const double* hE, const double* qE, const double* mE, const double* WE,
+             const double* ho, const double* qo, const double* mo, const double* Wo,
+             double* hn, double* qn, double* mn, double* Wn, or_stage_dbg* dbg) {
+  if (n < 1 || !p || p->dx <= 0.0) return OR_EINVAL;
+  const int bc = p->bc;
+  const double g = p->g, lam = p->lambda, dx = p->dx;
+  const int useb = p->has_b && bin;
+  int rc = OR_OK;
+
+  size_t nc = (size_t)n, nf = (size_t)n + 1;
+  double* bz = (double*)calloc(nc, sizeof(double));
+  double* Fq = (double*)malloc(nf * sizeof(double));
+  double* Fm = (double*)malloc(nf * sizeof(double));
+  double* FW = (double*)malloc(nf * sizeof(double));
+  double* qd = (double*)malloc(nc * sizeof(double));
+  double* md = (double*)malloc(nc * sizeof(double));
+  double* Wd = (double*)malloc(nc * sizeof(double));
+  double* beta = (double*)malloc(nc * sizeof(double));
+  double* S = (double*)malloc(nc * sizeof(double));
+  double* phi = (double*)malloc(nc * sizeof(double));
+  double* T = (double*)malloc(nc * sizeof(double));
+  double* P0 = (double*)malloc(nc * sizeof(double));
+  double* pt0 = (double*)malloc(nc * sizeof(double));
+  double* gL = (double*)malloc(nf * sizeof(double));
+  double* gR = (double*)malloc(nf * sizeof(double));
+  double* g0 = (double*)malloc(nf * sizeof(double));
+  double* qf = (double*)malloc(nf * sizeof(double));
+  double* lo = (double*)malloc(nc * sizeof(double));
+  double* di = (double*)malloc(nc * sizeof(double));
+  double* up = (double*)malloc(nc * sizeof(double));
+  double* rhs = (double*)malloc(nc * sizeof(double));
+  double* hb = (double*)malloc(nc * sizeof(double));
+  if (!bz || !Fq || !Fm || !FW || !qd || !md || !Wd || !beta || !S || !phi ||
+      !T || !P0 || !pt0 || !gL || !gR || !g0 || !qf || !lo || !di || !up ||
+      !rhs || !hb) {
+    rc = OR_EINVAL;
+    goto done;
+  }
+  const double* b = useb ? bin : bz;
+
+  /* (1) Explicit Rusanov fluxes of q u, m u, W u at every face, from the
+   * unlimited component-wise linear reconstruction of U_E (Sec. 4.1:
+   * slope (v_{i+1} - v_{i-1})/(2 dx), face values v_i +- slope dx/2). */
+  for (int k = 0; k <= n; ++k) {
+    int im1 = gidx(k - 2, n, bc), i0 = gidx(k - 1, n, bc);
+    int i1 = gidx(k, n, bc), i2 = gidx(k + 1, n, bc);
+    /* left state: cell k-1 at its right face; right state: cell k at its
+     * left face. */
+    double hL = hE[i0] + 0.25 * (hE[i1] - hE[im1]);
+    double hR = hE[i1] - 0.25 * (hE[i2] - hE[i0]);
+    double qL = qE[i0] + 0.25 * (qE[i1] - qE[im1]);
+    double qR = qE[i1] - 0.25 * (qE[i2] - qE[i0]);
+    double mL = mE[i0] + 0.25 * (mE[i1] - mE[im1]);
+    double mR = mE[i1] - 0.25 * (mE[i2] - mE[i0]);
+    double WL = WE[i0] + 0.25 * (WE[i1] - WE[im1]);
+    double WR = WE[i1] - 0.25 * (WE[i2] - WE[i0]);
+    if (!(hL > 0.0) || !(hR > 0.0)) rc = OR_ENONPHYS;
+    double uL = qL / hL, uR = qR / hR;
+    double sL = fabs(uL) + sqrt(g * hL), sR = fabs(uR) + sqrt(g * hR);
+    double a = sL > sR ? sL : sR;
+    /* Face-local lake-at-rest moment: mhat_j = (zeta_f - b_j)^2 with
+     * zeta_f the mean free surface of the two face cells, reconstructed
+     * like m; identically zero jump on a flat bed. */
+    double zf = 0.5 * ((hE[i0] + b[i0]) + (hE[i1] + b[i1]));
+    double r_m1 = (zf - b[im1]) * (zf - b[im1]);
+    double r_0 = (zf - b[i0]) * (zf - b[i0]);
+    double r_1 = (zf - b[i1]) * (zf - b[i1]);
+    double r_2 = (zf - b[i2]) * (zf - b[i2]);
+    double mhL = r_0 + 0.25 * (r_1 - r_m1);
+    double mhR = r_1 - 0.25 * (r_2 - r_0);
+    Fq[k] = 0.5 * (qL * uL + qR * uR - a * (qR - qL));
+    FW[k] = 0.5 * (WL * uL + WR * uR - a * (WR - WL));
+    Fm[k] = 0.5 * (mL * uL + mR * uR - a * ((mR - mL) - (mhR - mhL)));
+  }
+
+  /* (2) Convective predictor with the exact relaxation elimination
+   * (Sec. 3.1 eq. hSGN_eq-ustar and eq. b1; Sec. 4.2 first three lines). */
+  for (int i = 0; i < n; ++i) {
+    double dbc = (b[gidx(i + 1, n, bc)] - b[gidx(i - 1, n, bc)]) / (2.0 * dx);
+    Wd[i] = Wo[i] - tau / dx * (FW[i + 1] - FW[i]) + lam * tau;
+    md[i] = mo[i] - tau / dx * (Fm[i + 1] - Fm[i]) - tau * 1.5 * qE[i] * dbc +
+            tau * Wd[i];
+    qd[i] = qo[i] - tau / dx * (Fq[i + 1] - Fq[i]);
+  }
+
+  /* (3) Frozen coefficients at U_E (Sec. 2.2 eq. hSGN_alpha, hSGN_px;
+   * Sec. 4.2 beta_1, beta_2, beta).  P0 is the pressure p(h, m) of
+   * eq. hSGN_p at h = h_E and m = m-dagger / beta_1 (eq. b1 at h = h_E);
+   * phi is d p~/d h of p~ = (lambda/3)(1 - eta/h) along the same
+   * relaxation closure (bed form, eq. hSGNb_eq). */
+  for (int i = 0; i < n; ++i) {
+    double h = hE[i];
+    if (!(h > 0.0)) rc = OR_ENONPHYS;
+    double eta = mE[i] / h;
+    double alpha = -(2.0 * eta / h - 1.0) / (3.0 * h);
+    double c2 = g * h + lam / 3.0 * eta * eta / (h * h);
+    double a2 = c2 - lam * eta * alpha;
+    double beta1 = 1.0 + lam * tau * tau / (h * h);
+    double beta2 = 2.0 * lam * tau * tau / (beta1 * beta1 * h * h * h);
+    beta[i] = a2 + lam * alpha * beta2 * md[i];
+    if (!(beta[i] > 0.0)) rc = rc ? rc : OR_ENONCOERCIVE;
+    double eta0 = md[i] / (beta1 * h);
+    pt0[i] = lam / 3.0 * (1.0 - eta0 / h);
+    P0[i] = 0.5 * g * h * h + eta0 * pt0[i];
+    S[i] = P0[i] - beta[i] * h;
+    double den = h * h + lam * tau * tau;
+    phi[i] = 2.0 * lam / 3.0 * md[i] * h / (den * den);
+    T[i] = pt0[i] - phi[i] * h;
+  }
+
+  /* (4) Implicit face force G = [P_R - P_L + (g/2)(hb_L + hb_R) db
+   * + (3/4)(p~_L + p~_R) db] / dx, affine in hbar:
+   * G = gL hbar_L + gR hbar_R + g0, and face momentum
+   * Q = (q-dagger_L + q-dagger_R)/2 - tau G (Sec. 3.1 eq. hSGN_eq-split-I).
+   * Transmissive boundary faces carry no implicit force and Q = q-dagger of
+   * the boundary cell. */
+  for (int k = 0; k <= n; ++k) {
+    int L = gidx(k - 1, n, bc), R = gidx(k, n, bc);
+    int boundary = (bc != 0) && (k == 0 || k == n);
+    if (boundary) {
+      gL[k] = gR[k] = g0[k] = 0.0;
+      qf[k] = qd[k == 0 ? 0 : n - 1];
+      continue;
+    }
+    double db = b[R] - b[L];
+    gL[k] = (-beta[L] + db * (0.5 * g + 0.75 * phi[L])) / dx;
+    gR[k] = (beta[R] + db * (0.5 * g + 0.75 * phi[R])) / dx;
+    g0[k] = (S[R] - S[L] + 0.75 * db * (T[L] + T[R])) / dx;
+    qf[k] = 0.5 * (qd[L] + qd[R]);
+  }
+
+  /* (5) Mass balance hbar_i = h_old,i - tau/dx (Q_{i+1/2} - Q_{i-1/2}),
+   * collected as rows of the tridiagonal (cyclic if periodic) system. */
+  for (int i = 0; i < n; ++i) {
+    double c = tau * tau / dx;
+    up[i] = -c * gR[i + 1];
+    lo[i] = c * gL[i];
+    di[i] = 1.0 - c * (gL[i + 1] - gR[i]);
+    rhs[i] = ho[i] - tau / dx * (qf[i + 1] - qf[i]) + c * (g0[i + 1] - g0[i]);
+  }
+  {
+    int trc = or_tridiag(n, bc == 0, lo, di, up, rhs, hb);
+    if (trc) rc = trc;
+  }
+
+  /* (6) Back-substitution (Sec. 4.2 last three lines): momentum from the
+   * linearised pressure and bed force, then the relaxation pair with hbar
+   * treated implicitly: m = m-dagger / (1 + lambda tau^2 / hbar^2),
+   * W = W-dagger - lambda tau m / hbar^2. */
+  for (int i = 0; i < n; ++i) {
+    int im = gidx(i - 1, n, bc), ip = gidx(i + 1, n, bc);
+    double Pm = P0[im] + beta[im] * (hb[im] - hE[im]);
+    double Pp = P0[ip] + beta[ip] * (hb[ip] - hE[ip]);
+    double pti = pt0[i] + phi[i] * (hb[i] - hE[i]);
+    double dbc = (b[ip] - b[im]) / (2.0 * dx);
+    double hbi = hb[i];
+    if (!(hbi > 0.0)) rc = OR_ENONPHYS;
+    qn[i] = qd[i] - tau * ((Pp - Pm) / (2.0 * dx) +
+                           0.5 * g * (hb[ip] + hb[im]) * dbc + 1.5 * pti * dbc);
+    mn[i] = md[i] / (1.0 + lam * tau * tau / (hbi * hbi));
+    Wn[i] = Wd[i] - lam * tau * mn[i] / (hbi * hbi);
+    hn[i] = hbi;
+    if (!isfinite(qn[i]) || !isfinite(mn[i]) || !isfinite(Wn[i]) ||
+        !isfinite(hn[i]))
+      rc = OR_ENONPHYS;
+  }
+
+  if (dbg) {
+#define OR_CP(dst, src, cnt) \
+  if (dbg->dst) memcpy(dbg->dst, src, (cnt) * sizeof(double))
+    OR_CP(qd, qd, nc); OR_CP(md, md, nc); OR_CP(Wd, Wd, nc);
+    OR_CP(beta, beta, nc); OR_CP(S, S, nc); OR_CP(phi, phi, nc);
+    OR_CP(T, T, nc); OR_CP(P0, P0, nc); OR_CP(pt0, pt0, nc);
+    OR_CP(lo, lo, nc); OR_CP(di, di, nc); OR_CP(up, up, nc);
+    OR_CP(rhs, rhs, nc); OR_CP(hbar, hb, nc);
+    OR_CP(Fq, Fq, nf); OR_CP(Fm, Fm, nf); OR_CP(FW, FW, nf);
+#undef OR_CP
+  }
+
+done:
+  free(bz); free(Fq); free(Fm); free(FW); free(qd); free(md); free(Wd);
+  free(beta); free(S); free(phi); free(T); free(P0); free(pt0);
+  free(gL); free(gR); free(g0); free(qf); free(lo); free(di); free(up);
+  free(rhs); free(hb);
+  return rc;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Time step (Sec. 5: dt = CFL dx / max speed, then the material CFL cap).  */
+/* The speed is |u| + sqrt(g h): the lambda-independent rule of the remark  */
+/* after the coercivity proposition (Sec. 3.1).                             */
+/* ---------------------------------------------------------------------- */
+double or_dt(int n, const or_params* p, const double* h, const double* q, double t) {
+  double dt;
+  if (p->dt_fixed > 0.0) {
+    dt = p->dt_fixed;
+  } else {
+    double smax = 0.0, umax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double u = fabs(q[i] / h[i]);
+      double s = u + sqrt(p->g * h[i]);
+      if (s > smax) smax = s;
+      if (u > umax) umax = u;
+    }
+    dt = p->cfl * p->dx / smax;
+    if (p->mcfl > 0.0 && umax * dt / p->dx > p->mcfl) dt = p->mcfl * p->dx / umax;
+  }
+  if (p->t_end > 0.0) {
+    if (t >= p->t_end) dt = 0.0;
+    else if (t + dt > p->t_end) dt = p->t_end - t;
+  }
+  return dt;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Two-stage IMEX step (Sec. 3.2, eq. tableau, steps 1-5 + efficient form). */
+/* ---------------------------------------------------------------------- */
+int or_step(int n, const or_params* p, const double* b,
+            double* h, double* q, double* m, double* W, double* t, double* dt_out) {
+  double dt = or_dt(n, p, h, q, *t);
+  if (dt_out) *dt_out = dt;
+  if (!(dt > 0.0)) return OR_OK; /* frozen instance */
+  double tau = OR_GAMMA * dt;
+  size_t nc = (size_t)n;
+  double* buf = (double*)malloc(12 * nc * sizeof(double));
+  if (!buf) return OR_EINVAL;
+  double *h1 = buf, *q1 = buf + nc, *m1 = buf + 2 * nc, *W1 = buf + 3 * nc;
+  double *hE = buf + 4 * nc, *qE = buf + 5 * nc, *mE = buf + 6 * nc, *WE = buf + 7 * nc;
+  double *ht = buf + 8 * nc, *qt = buf + 9 * nc, *mt = buf + 10 * nc, *Wt = buf + 11 * nc;
+
+  /* stage 1: U_E^(1) = U^n, U_I^(1) = U^n + gamma dt H(U_E^(1), U_I^(1)) */
+  int rc = or_stage(n, p, tau, b, h, q, m, W, h, q, m, W, h1, q1, m1, W1, NULL);
+  int rc2 = OR_OK;
+  if (rc == OR_OK) {
+    /* efficient-form combinations */
+    for (size_t i = 0; i < nc; ++i) {
+      hE[i] = OR_E0 * h[i] + OR_E1 * h1[i];
+      qE[i] = OR_E0 * q[i] + OR_E1 * q1[i];
+      mE[i] = OR_E0 * m[i] + OR_E1 * m1[i];
+      WE[i] = OR_E0 * W[i] + OR_E1 * W1[i];
+      ht[i] = OR_T0 * h[i] + OR_T1 * h1[i];
+      qt[i] = OR_T0 * q[i] + OR_T1 * q1[i];
+      mt[i] = OR_T0 * m[i] + OR_T1 * m1[i];
+      Wt[i] = OR_T0 * W[i] + OR_T1 * W1[i];
+    }
+    /* stage 2: U^{n+1} = U_I^(2) = U~ + gamma dt H(U_E^(2), U_I^(2))
+     * (stiffly accurate: the last implicit stage is the new state) */
+    rc2 = or_stage(n, p, tau, b, hE, qE, mE, WE, ht, qt, mt, Wt, h, q, m, W, NULL);
+  }
+  free(buf);
+  *t += dt;
+  return rc ? rc : rc2;
+}
+
+int or_run(int n, const or_params* p, const double* b,
+           double* h, double* q, double* m, double* W, double* t, int nsteps) {
+  for (int s = 0; s < nsteps; ++s) {
+    int rc = or_step(n, p, b, h, q, m, W, t, NULL);
+    if (rc) return rc;
+  }
+  return OR_OK;
+}
+
+int or_run_batch(int n_inst, const long long* offsets, const or_params* p,
+                 const double* b, double* h, double* q, double* m, double* W,
+                 double* t, int nsteps, int nthreads, int* status) {
+  int worst = OR_OK;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) reduction(max : worst)
+#endif
+  for (int j = 0; j < n_inst; ++j) {
+    long long o = offsets[j];
+    int n = (int)(offsets[j + 1] - o);
+    int rc = or_run(n, &p[j], b ? b + o : NULL, h + o, q + o, m + o, W + o,
+                    &t[j], nsteps);
+    if (status) status[j] = rc;
+    if (rc > worst) worst = rc;
+  }
+  (void)nthreads;
+  return worst;
+}

@@ -1,0 +1,228 @@
+"""Seeded synthetic workloads for the hSGN solver (inputs only).
+
+This module holds the initial data of the test problems and nothing of the
+numerical method: closed-form initial states, beds and the seeded random
+draws.  Both the HIP library's tests/benchmark and the CPU oracle read the
+same arrays produced here.
+
+Initial data follow the solitary-wave test of Sec. 6.3 (closed form of the SGN
+solitary wave; eta = h and w = -h u_x at t = 0), so m = h*eta = h^2 and
+W = h*w = -h^2 u_x, sampled at cell centres.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+G = 9.81
+BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+
+
+@dataclass
+class Workload:
+    name: str
+    offsets: np.ndarray            # int64, n_inst + 1
+    g: np.ndarray                  # per-instance parameters (float64)
+    lam: np.ndarray
+    dx: np.ndarray
+    cfl: np.ndarray
+    mcfl: np.ndarray
+    dt_fixed: np.ndarray
+    t_end: np.ndarray
+    bc: np.ndarray                 # int32
+    has_b: np.ndarray              # int32
+    b: np.ndarray | None           # bed, concatenated (None: flat everywhere)
+    h: np.ndarray
+    q: np.ndarray
+    m: np.ndarray
+    W: np.ndarray
+    nsteps: int
+    info: dict = field(default_factory=dict)
+
+    @property
+    def n_inst(self) -> int:
+        return len(self.offsets) - 1
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.offsets[-1])
+
+    def sizes(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+    def state(self):
+        return (self.h, self.q, self.m, self.W)
+
+    def instance(self, j: int):
+        """Slice of instance j: (n, params dict, b, (h, q, m, W))."""
+        o0, o1 = int(self.offsets[j]), int(self.offsets[j + 1])
+        prm = dict(g=float(self.g[j]), lam=float(self.lam[j]), dx=float(self.dx[j]),
+                   cfl=float(self.cfl[j]), mcfl=float(self.mcfl[j]),
+                   dt_fixed=float(self.dt_fixed[j]), t_end=float(self.t_end[j]),
+                   bc=int(self.bc[j]), has_b=int(self.has_b[j]))
+        b = None if (self.b is None or not self.has_b[j]) else self.b[o0:o1].copy()
+        U = tuple(a[o0:o1].copy() for a in self.state())
+        return o1 - o0, prm, b, U
+
+    def subset(self, idx, name=None) -> "Workload":
+        """A new workload made of the instances in idx (same data)."""
+        idx = list(idx)
+        sizes = self.sizes()[idx]
+        offs = np.zeros(len(idx) + 1, dtype=np.int64)
+        offs[1:] = np.cumsum(sizes)
+        cat = lambda a: np.concatenate([a[int(self.offsets[j]):int(self.offsets[j + 1])] for j in idx])
+        per = lambda a: np.ascontiguousarray(a[idx])
+        return Workload(name or (self.name + "-subset"), offs, per(self.g), per(self.lam),
+                        per(self.dx), per(self.cfl), per(self.mcfl), per(self.dt_fixed),
+                        per(self.t_end), per(self.bc), per(self.has_b),
+                        None if self.b is None else cat(self.b),
+                        cat(self.h), cat(self.q), cat(self.m), cat(self.W), self.nsteps,
+                        dict(self.info))
+
+
+def _pack(name, parts, nsteps, info=None) -> Workload:
+    """parts: list of dicts with keys n, g, lam, dx, cfl, mcfl, dt_fixed, t_end,
+    bc, b (array or None), h, q, m, W."""
+    sizes = np.array([p["n"] for p in parts], dtype=np.int64)
+    offs = np.zeros(len(parts) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(sizes)
+    f = lambda k: np.array([p[k] for p in parts], dtype=np.float64)
+    any_b = any(p.get("b") is not None for p in parts)
+    b = None
+    if any_b:
+        b = np.concatenate([p["b"] if p.get("b") is not None else np.zeros(p["n"]) for p in parts])
+    has_b = np.array([1 if p.get("b") is not None else 0 for p in parts], dtype=np.int32)
+    cat = lambda k: np.ascontiguousarray(np.concatenate([p[k] for p in parts]), dtype=np.float64)
+    return Workload(name, offs, f("g"), f("lam"), f("dx"), f("cfl"), f("mcfl"), f("dt_fixed"),
+                    f("t_end"), np.array([p["bc"] for p in parts], dtype=np.int32), has_b, b,
+                    cat("h"), cat("q"), cat("m"), cat("W"), int(nsteps), info or {})
+
+
+# --------------------------------------------------------------------------
+# Closed forms
+# --------------------------------------------------------------------------
+def soliton(x, h0, a, x0, t=0.0, g=G):
+    """SGN solitary wave (Sec. 6.3): h = h0 (1 + eps sech^2(kappa (x - x0 - C t))),
+    u = C (1 - h0/h), C = sqrt(g h0 (1 + eps)), kappa = sqrt(3 eps / (4 h0^2 (1 + eps))).
+    Returns (h, u, u_x) with u_x analytic."""
+    eps = a / h0
+    C = np.sqrt(g * h0 * (1.0 + eps))
+    kap = np.sqrt(3.0 * eps / (4.0 * h0 * h0 * (1.0 + eps)))
+    xi = kap * (x - x0 - C * t)
+    sech2 = 1.0 / np.cosh(xi) ** 2
+    h = h0 * (1.0 + eps * sech2)
+    u = C * (1.0 - h0 / h)
+    hx = -2.0 * h0 * eps * kap * sech2 * np.tanh(xi)
+    ux = C * h0 * hx / (h * h)
+    return h, u, ux
+
+
+def soliton_speed(h0, a, g=G):
+    return float(np.sqrt(g * (h0 + a)))
+
+
+def trapezoid_bar(x, toe, height=0.3, up=1.0 / 20.0, crest=2.0, down=1.0 / 10.0):
+    """Submerged trapezoidal bar: rises from 0 at `toe` with slope `up` to
+    `height`, flat crest of length `crest`, falls with slope `down`."""
+    l_up = height / up
+    l_dn = height / down
+    x1, x2, x3 = toe + l_up, toe + l_up + crest, toe + l_up + crest + l_dn
+    b = np.zeros_like(x)
+    b = np.where((x >= toe) & (x < x1), (x - toe) * up, b)
+    b = np.where((x >= x1) & (x < x2), height, b)
+    b = np.where((x >= x2) & (x < x3), height - (x - x2) * down, b)
+    return b
+
+
+def _part(n, dx, lam, bc, h, u, ux, b=None, cfl=0.9, mcfl=0.5, t_end=0.0, dt_fixed=0.0, g=G):
+    q = h * u
+    return dict(n=int(n), g=g, lam=float(lam), dx=float(dx), cfl=cfl, mcfl=mcfl,
+                dt_fixed=dt_fixed, t_end=t_end, bc=bc, b=b, h=np.ascontiguousarray(h),
+                q=np.ascontiguousarray(q), m=np.ascontiguousarray(h * h),
+                W=np.ascontiguousarray(-h * h * ux))
+
+
+# --------------------------------------------------------------------------
+# The five workloads (sizes as specified; unspecified details are stated)
+# --------------------------------------------------------------------------
+def solitary(N=800, L=200.0, h0=1.0, a=0.2, lam=100.0, x0=None, t_end=10.0, nsteps=None,
+             bc=BC_PERIODIC) -> Workload:
+    """C1: one solitary wave on a flat periodic bed, crest at the domain centre."""
+    dx = L / N
+    x = (np.arange(N) + 0.5) * dx
+    x0 = 0.5 * L if x0 is None else x0
+    h, u, ux = soliton(x, h0, a, x0)
+    ns = nsteps if nsteps is not None else 100000
+    return _pack("solitary", [_part(N, dx, lam, bc, h, u, ux, t_end=t_end)], ns,
+                 dict(h0=h0, a=a, x0=x0, L=L))
+
+
+def dam_break(N=20000, xa=-300.0, xb=300.0, hl=1.8, hr=1.0, width=0.3, lam=1000.0,
+              nsteps=2000) -> Workload:
+    """C2: dispersive dam break, transmissive.  The jump is smoothed with a
+    tanh of half-width `width` (the paper smooths its bores the same way)."""
+    dx = (xb - xa) / N
+    x = xa + (np.arange(N) + 0.5) * dx
+    h = 0.5 * (hl + hr) - 0.5 * (hl - hr) * np.tanh(x / width)
+    z = np.zeros(N)
+    return _pack("dam_break", [_part(N, dx, lam, BC_TRANSMISSIVE, h, z, z)], nsteps,
+                 dict(width=width))
+
+
+def batched_bar(n_inst=4096, seed=3, n_lo=512, n_hi=16384, dx=0.04, h0=0.4,
+                lams=(100.0, 1000.0, 10000.0), nsteps=100) -> Workload:
+    """C3: independent solitary waves over a submerged trapezoidal bar.
+    Draw order from numpy's PCG64 default_rng(seed): N_j, a_j/h0, toe_j/L_j, lambda_j."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.integers(n_lo, n_hi + 1, size=n_inst)
+    amps = rng.uniform(0.05, 0.4, size=n_inst) * h0
+    toes = rng.uniform(0.35, 0.45, size=n_inst)
+    lam_j = rng.choice(np.asarray(lams, dtype=np.float64), size=n_inst)
+    parts = []
+    for j in range(n_inst):
+        N = int(Ns[j])
+        L = N * dx
+        x = (np.arange(N) + 0.5) * dx
+        b = trapezoid_bar(x, toes[j] * L)
+        hs, u, ux = soliton(x, h0, amps[j], 0.2 * L)
+        h = hs - b  # free surface zeta = h0 + soliton excess; depth = zeta - b
+        parts.append(_part(N, dx, lam_j[j], BC_TRANSMISSIVE, h, u, ux, b=b))
+    return _pack("batched_bar", parts, nsteps, dict(seed=seed))
+
+
+def long_periodic(N=1 << 24, dx=0.01, lam=1e4, seed=4, K=16, nsteps=200) -> Workload:
+    """C4: one long periodic mesh, h = 1 + sum_k a_k cos(2 pi k x / L + phi_k),
+    a_k ~ U[0, 0.01], phi_k ~ U[0, 2 pi) drawn in that order from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    ak = rng.uniform(0.0, 0.01, size=K)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=K)
+    L = N * dx
+    x = (np.arange(N) + 0.5) * dx
+    h = np.ones(N)
+    for k in range(K):
+        h += ak[k] * np.cos(2.0 * np.pi * (k + 1) * x / L + ph[k])
+    z = np.zeros(N)
+    return _pack("long_periodic", [_part(N, dx, lam, BC_PERIODIC, h, z, z)], nsteps,
+                 dict(seed=seed))
+
+
+def lake_at_rest(N=256, dx=0.04, h0=0.4, lam=100.0, bed=True, nsteps=100) -> Workload:
+    """Still water over the bar (or flat): zeta = h0, u = 0."""
+    x = (np.arange(N) + 0.5) * dx
+    b = trapezoid_bar(x, 0.3 * N * dx) if bed else None
+    h = h0 - (b if b is not None else 0.0)
+    z = np.zeros(N)
+    return _pack("lake_at_rest", [_part(N, dx, lam, BC_TRANSMISSIVE, h, z, z, b=b)], nsteps)
+
+
+def concat(name, wls, nsteps=None) -> Workload:
+    """Concatenate workloads into one batch."""
+    parts = []
+    for w in wls:
+        for j in range(w.n_inst):
+            n, prm, b, U = w.instance(j)
+            d = dict(n=n, **{k: prm[k] for k in ("g", "lam", "dx", "cfl", "mcfl", "dt_fixed", "t_end", "bc")})
+            d.update(b=b, h=U[0], q=U[1], m=U[2], W=U[3])
+            parts.append(d)
+    return _pack(name, parts, nsteps if nsteps is not None else wls[0].nsteps)
