@@ -1,0 +1,130 @@
+/*
+ * hsgn.h -- C ABI of the MI355X (gfx950) library for the semi-implicit IMEX
+ * time step of the hyperbolic Serre-Green-Naghdi (hSGN) equations
+ * (Macca, Boscheri, Ricchiuto, arXiv 2510.07539).
+ *
+ * What one step computes (Sec. 3.2, eq. tableau and the efficient form of
+ * the remark after it): the two-stage partitioned IMEX Runge-Kutta step
+ *   U^(1)   = Stage(U_old = U^n,  U_E = U^n,     tau = gamma dt)
+ *   U^{n+1} = Stage(U_old = U~,   U_E = U_E^(2), tau = gamma dt)
+ * with gamma = 1 - 1/sqrt(2), U_E^(2) = (1 - c/gamma) U^n + (c/gamma) U^(1),
+ * U~ = (1 - (1-gamma)/gamma) U^n + ((1-gamma)/gamma) U^(1), c = 1/(2 gamma).
+ * Each Stage is the fully discrete first-order semi-implicit step of
+ * Sec. 4.2 (eq. GN_hyp_eq_semi_fully_discrete): explicit Rusanov fluxes of
+ * the convective terms on an unlimited linear reconstruction (Sec. 4.1),
+ * the exact elimination of the relaxation pair (Sec. 3.1, eq. b1), a
+ * tridiagonal (cyclic when periodic) system for the new depth from the
+ * linearised pressure (Sec. 3.1, eq. hnew; differenced in conservative
+ * pressure form), and back-substitution of momentum, h*eta and h*w.
+ * The time step is CFL dx / max(|u| + sqrt(g h)), capped by the material
+ * CFL max|u| dt/dx <= mcfl (Sec. 3.3 eq. MCFL and Sec. 5).
+ *
+ * State per cell (all FP64, structure of arrays): h (depth), q = h u,
+ * m = h eta, W = h w.  Independent instances ("batch") are concatenated:
+ * instance j owns cells [offsets[j], offsets[j+1]).  Bed b (bathymetry) is
+ * optional per instance.
+ *
+ * Memory: every pointer named d_* is a device pointer owned by the caller;
+ * the library copies from it or into it and never keeps it.  The library
+ * owns its own state buffers and workspace, allocated in hsgn_init and freed
+ * in hsgn_destroy.  Pointers named h_* are host pointers.
+ *
+ * Streams: every call is enqueued asynchronously on the HIP stream given to
+ * hsgn_init, except hsgn_status, which synchronises that stream.
+ *
+ * Errors: every int-returning call returns HSGN_OK (0) or a negative code;
+ * hsgn_last_error names the failing call.  A context is not thread-safe.
+ */
+#ifndef HSGN_H
+#define HSGN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HSGN_OK 0
+#define HSGN_EINVAL (-1)        /* bad argument (sizes, parameters, null)    */
+#define HSGN_EHIP (-2)          /* a HIP runtime call failed                 */
+#define HSGN_ENONPHYS (-3)      /* some instance produced h <= 0 or NaN      */
+#define HSGN_ENONCOERCIVE (-4)  /* some instance produced beta <= 0          */
+#define HSGN_ENOMEM (-5)        /* device allocation failed                  */
+
+/* Per-instance status bits returned by hsgn_status. A flagged instance is
+ * frozen: its later steps use dt = 0 and leave its state unchanged. */
+#define HSGN_FLAG_NONPHYS 1     /* h <= 0, or a non-finite value, in a stage */
+#define HSGN_FLAG_NONCOERCIVE 2 /* beta <= 0 (coercivity, Sec. 3.1 prop.)  */
+
+typedef enum { HSGN_BC_PERIODIC = 0, HSGN_BC_TRANSMISSIVE = 1 } hsgn_bc;
+
+/* Parameters of one instance, as the paper states the problem. */
+typedef struct {
+  double g;              /* gravity (9.81)                                  */
+  double lambda;         /* relaxation parameter lambda > 0 (eq. hSGN_eq)   */
+  double dx;             /* uniform cell width > 0                          */
+  double cfl;            /* CFL on max(|u| + sqrt(g h)) (e.g. 0.9)          */
+  double mcfl;           /* material CFL cap (0.5; <= 0 disables the cap)   */
+  double dt_fixed;       /* > 0: fixed time step; <= 0: adaptive            */
+  double t_end;          /* > 0: clamp the last step to t_end, then freeze  */
+  int32_t bc;            /* hsgn_bc                                         */
+  int32_t has_bathymetry;/* 1: use the bed b of this instance; 0: flat      */
+} hsgn_params;
+
+typedef struct hsgn_ctx hsgn_ctx;
+
+/* Create a context for n_inst instances.
+ *  offsets: host, n_inst+1 int64, offsets[0] = 0, each instance >= 4 cells.
+ *  params:  host, n_inst entries (copied).
+ *  d_b:     device, offsets[n_inst] doubles, or NULL if no instance uses a
+ *           bed (copied; instances with has_bathymetry = 0 ignore it).
+ *  hip_stream: a hipStream_t (NULL = default stream).
+ * Allocates the library's state buffers and workspace on the current device.
+ * The state is zero until hsgn_set_state.  Returns HSGN_EINVAL, HSGN_ENOMEM
+ * or HSGN_EHIP on failure (then *ctx is NULL). */
+int hsgn_init(hsgn_ctx** ctx, int32_t n_inst, const int64_t* offsets,
+              const hsgn_params* params, const double* d_b, void* hip_stream);
+
+/* Load the state (device arrays of offsets[n_inst] doubles).
+ *  d_m: NULL means m = h*h (eta = h, the initial data of Sec. 6.3).
+ *  d_W: NULL means W = 0.
+ *  d_t: device, n_inst times, or NULL for t = 0.
+ * Clears the status flags and computes the first step's speed bound. */
+int hsgn_set_state(hsgn_ctx* ctx, const double* d_h, const double* d_q,
+                   const double* d_m, const double* d_W, const double* d_t);
+
+/* Copy the current state out (any pointer may be NULL to skip it).
+ * d_t: device, n_inst doubles (time reached per instance). */
+int hsgn_get_state(hsgn_ctx* ctx, double* d_h, double* d_q, double* d_m,
+                   double* d_W, double* d_t);
+
+/* Copy the last step's dt of every instance (device, n_inst doubles). */
+int hsgn_get_dt(hsgn_ctx* ctx, double* d_dt);
+
+/* Advance every instance by nsteps IMEX steps with eager kernel launches. */
+int hsgn_step(hsgn_ctx* ctx, int32_t nsteps);
+
+/* Advance by nsteps IMEX steps, replaying a captured HIP graph of `block`
+ * steps (block >= 1; odd blocks are rounded up to even); remaining steps run
+ * eagerly.  Same results as hsgn_step. */
+int hsgn_run(hsgn_ctx* ctx, int32_t nsteps, int32_t block);
+
+/* Synchronise the stream and copy the per-instance status bits to host
+ * (h_flags: n_inst int32, may be NULL).  Returns HSGN_OK if no instance is
+ * flagged, else HSGN_ENONPHYS or HSGN_ENONCOERCIVE. */
+int hsgn_status(hsgn_ctx* ctx, int32_t* h_flags);
+
+/* Message describing the last failure of this context ("" if none).  The
+ * string is owned by the context. */
+const char* hsgn_last_error(const hsgn_ctx* ctx);
+
+/* Library version string. */
+const char* hsgn_version(void);
+
+/* Free the context and everything it allocated (NULL is a no-op). */
+void hsgn_destroy(hsgn_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSGN_H */

@@ -1,0 +1,41 @@
+"""Build the gfx950 HIP library libhsgn.so in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(HERE, "csrc", "hsgn.hip")
+DEPS = [SRC, os.path.join(HERE, "csrc", "hsgn_kernels.hpp"), os.path.join(ROOT, "include", "hsgn.h")]
+LIB = os.path.join(HERE, "libhsgn.so")
+
+HIPCC_FLAGS = [
+    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+    # no packed FP32 instructions anywhere (the path is FP64; this keeps the
+    # compiler from emitting v_pk_*_f32 in helper code)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-result", "-Wno-unused-value",
+]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libhsgn.so (always recompiles)."""
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", *HIPCC_FLAGS, "-I" + os.path.join(ROOT, "include"), SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def is_stale() -> bool:
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(d) > t for d in DEPS)
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

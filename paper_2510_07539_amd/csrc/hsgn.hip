@@ -1,0 +1,485 @@
+// hsgn.hip -- C ABI of the gfx950 hSGN IMEX library (see include/hsgn.h).
+//
+// Host side: context, device workspace, the tiling of the batch, the launch
+// sequence of one IMEX step, and HIP-graph capture of step blocks.
+//
+// Launch sequence of one step on the context's stream:
+//   k_dt                                   dt per instance from the speed bound
+//   stage 1: [k_stage<REDUCE> -> k_rsolve]  only if some instance has >1 tile
+//            k_stage<FULL>                  all tiles; writes U^(1)
+//   stage 2: same, reading U^n and U^(1); writes U^{n+1} and the next speed
+//            bound.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hsgn.h"
+#include "hsgn_kernels.hpp"
+
+namespace {
+
+constexpr int kNT = 256;      // threads per stage workgroup
+constexpr int kKMAX = 8;      // max cells per thread
+constexpr int kTileMax = kNT * kKMAX;
+constexpr int kNTR = 256;     // threads of the reduced-system solve
+
+using hsgn::InstDesc;
+using hsgn::StageArgs;
+using hsgn::TileDesc;
+
+struct GraphEntry {
+  int block;
+  int cur;
+  hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct hsgn_ctx {
+  int32_t n_inst = 0;
+  int64_t ncell = 0;
+  std::vector<int64_t> offsets;
+  std::vector<hsgn_params> params;
+  hipStream_t user_stream = nullptr;
+  hipStream_t stream = nullptr;  // where work is enqueued
+  bool own_stream = false;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  bool any_b = false;
+  bool any_multi = false;
+  int ntiles_all = 0, ntiles_multi = 0, n_multi_inst = 0;
+  int64_t red_total = 0;
+  // device memory
+  InstDesc* d_inst = nullptr;
+  TileDesc* d_tiles_all = nullptr;
+  TileDesc* d_tiles_multi = nullptr;
+  int32_t* d_multi = nullptr;
+  double* d_b = nullptr;
+  double* buf[3][4] = {};
+  int cur = 0, s1 = 1, nxt = 2;
+  double* d_dt = nullptr;
+  double* d_t = nullptr;
+  unsigned long long* d_smax = nullptr;
+  unsigned long long* d_umax = nullptr;
+  int32_t* d_status = nullptr;
+  double *d_rlo = nullptr, *d_rdi = nullptr, *d_rup = nullptr, *d_rrhs = nullptr,
+         *d_rx = nullptr, *d_scp = nullptr, *d_sy = nullptr, *d_sv = nullptr, *d_sw = nullptr;
+  std::vector<GraphEntry> graphs;
+  std::string err;
+};
+
+namespace {
+
+int fail(hsgn_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail((ctx), HSGN_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
+  } while (0)
+
+template <typename T>
+int dmalloc(hsgn_ctx* c, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return HSGN_OK;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, HSGN_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                hipGetErrorString(e));
+  }
+  return HSGN_OK;
+}
+
+void free_all(hsgn_ctx* c) {
+  for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+  void* ptrs[] = {c->d_inst, c->d_tiles_all, c->d_tiles_multi, c->d_multi, c->d_b,
+                  c->d_dt, c->d_t, c->d_smax, c->d_umax, c->d_status, c->d_rlo, c->d_rdi,
+                  c->d_rup, c->d_rrhs, c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  for (int i = 0; i < 3; ++i)
+    for (int f = 0; f < 4; ++f)
+      if (c->buf[i][f]) hipFree(c->buf[i][f]);
+  if (c->ev_in) hipEventDestroy(c->ev_in);
+  if (c->ev_out) hipEventDestroy(c->ev_out);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+}
+
+// Make the library stream wait for prior work of the caller's stream.
+int enter(hsgn_ctx* c) {
+  if (c->stream == c->user_stream) return HSGN_OK;
+  HIPCHK(c, hipEventRecord(c->ev_in, c->user_stream));
+  HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_in, 0));
+  return HSGN_OK;
+}
+// Make the caller's stream wait for the library's work.
+int leave(hsgn_ctx* c) {
+  if (c->stream == c->user_stream) return HSGN_OK;
+  HIPCHK(c, hipEventRecord(c->ev_out, c->stream));
+  HIPCHK(c, hipStreamWaitEvent(c->user_stream, c->ev_out, 0));
+  return HSGN_OK;
+}
+
+template <bool BED, int STAGE, bool REDUCE>
+void launch_stage(hsgn_ctx* c, const StageArgs& a, int ntiles) {
+  hipLaunchKernelGGL((hsgn::k_stage<kNT, kKMAX, BED, STAGE, REDUCE>), dim3(ntiles), dim3(kNT), 0,
+                     c->stream, a);
+}
+
+template <int STAGE>
+void launch_stage_any(hsgn_ctx* c, const StageArgs& a, int ntiles, bool reduce) {
+  if (c->any_b) {
+    if (reduce) launch_stage<true, STAGE, true>(c, a, ntiles);
+    else launch_stage<true, STAGE, false>(c, a, ntiles);
+  } else {
+    if (reduce) launch_stage<false, STAGE, true>(c, a, ntiles);
+    else launch_stage<false, STAGE, false>(c, a, ntiles);
+  }
+}
+
+StageArgs stage_args(hsgn_ctx* c, int stage) {
+  StageArgs a;
+  std::memset(&a, 0, sizeof a);
+  double** un = c->buf[c->cur];
+  double** u1 = c->buf[c->s1];
+  double** out = stage == 1 ? c->buf[c->s1] : c->buf[c->nxt];
+  a.un_h = un[0]; a.un_q = un[1]; a.un_m = un[2]; a.un_W = un[3];
+  a.u1_h = u1[0]; a.u1_q = u1[1]; a.u1_m = u1[2]; a.u1_W = u1[3];
+  a.o_h = out[0]; a.o_q = out[1]; a.o_m = out[2]; a.o_W = out[3];
+  a.b = c->d_b;
+  a.inst = c->d_inst;
+  a.dt = c->d_dt;
+  a.rlo = c->d_rlo; a.rdi = c->d_rdi; a.rup = c->d_rup; a.rrhs = c->d_rrhs;
+  a.rx = c->d_rx;
+  a.smax = c->d_smax;
+  a.umax = c->d_umax;
+  a.status = c->d_status;
+  return a;
+}
+
+// Enqueue one IMEX step (no synchronisation), then rotate the buffers.
+int enqueue_step(hsgn_ctx* c) {
+  const int nb = (c->n_inst + 255) / 256;
+  hipLaunchKernelGGL(hsgn::k_dt, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_inst, c->d_dt,
+                     c->d_t, c->d_smax, c->d_umax, c->d_status);
+  for (int stage = 1; stage <= 2; ++stage) {
+    StageArgs a = stage_args(c, stage);
+    if (c->any_multi) {
+      a.tiles = c->d_tiles_multi;
+      if (stage == 1) launch_stage_any<1>(c, a, c->ntiles_multi, true);
+      else launch_stage_any<2>(c, a, c->ntiles_multi, true);
+      hipLaunchKernelGGL(hsgn::k_rsolve<kNTR>, dim3(c->n_multi_inst), dim3(kNTR), 0, c->stream,
+                         c->d_inst, c->d_multi, c->d_dt, c->d_rlo, c->d_rdi, c->d_rup, c->d_rrhs,
+                         c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw);
+    }
+    a.tiles = c->d_tiles_all;
+    if (stage == 1) launch_stage_any<1>(c, a, c->ntiles_all, false);
+    else launch_stage_any<2>(c, a, c->ntiles_all, false);
+  }
+  HIPCHK(c, hipGetLastError());
+  const int old = c->cur;
+  c->cur = c->nxt;
+  c->nxt = old;
+  return HSGN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hsgn_version(void) { return "hsgn-gfx950 0.1"; }
+
+int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn_params* params,
+              const double* d_b, void* hip_stream) {
+  if (!out) return HSGN_EINVAL;
+  *out = nullptr;
+  if (n_inst <= 0 || !offsets || !params) return HSGN_EINVAL;
+  hsgn_ctx* c = new (std::nothrow) hsgn_ctx();
+  if (!c) return HSGN_ENOMEM;
+  int rc = HSGN_OK;
+  c->n_inst = n_inst;
+  c->offsets.assign(offsets, offsets + n_inst + 1);
+  c->params.assign(params, params + n_inst);
+  c->user_stream = (hipStream_t)hip_stream;
+  if (offsets[0] != 0) rc = fail(c, HSGN_EINVAL, "offsets[0] must be 0");
+  std::vector<InstDesc> inst(n_inst);
+  std::vector<TileDesc> tall, tmulti;
+  std::vector<int32_t> multi;
+  int64_t red = 0;
+  for (int j = 0; j < n_inst && rc == HSGN_OK; ++j) {
+    const int64_t n = offsets[j + 1] - offsets[j];
+    const hsgn_params& p = params[j];
+    if (n < 4 || n > (int64_t)1 << 30) {
+      rc = fail(c, HSGN_EINVAL, "instance %d has %lld cells (need 4 .. 2^30)", j, (long long)n);
+      break;
+    }
+    if (!(p.g > 0) || !(p.lambda > 0) || !(p.dx > 0) || (p.bc != 0 && p.bc != 1) ||
+        (!(p.dt_fixed > 0) && !(p.cfl > 0))) {
+      rc = fail(c, HSGN_EINVAL, "instance %d: invalid parameters", j);
+      break;
+    }
+    if (p.has_bathymetry && !d_b) {
+      rc = fail(c, HSGN_EINVAL, "instance %d uses a bed but d_b is NULL", j);
+      break;
+    }
+    InstDesc& d = inst[j];
+    std::memset(&d, 0, sizeof d);
+    d.off = offsets[j];
+    d.n = (int32_t)n;
+    d.bc = p.bc;
+    d.has_b = p.has_bathymetry ? 1 : 0;
+    d.g = p.g; d.lam = p.lambda; d.dx = p.dx; d.cfl = p.cfl; d.mcfl = p.mcfl;
+    d.dt_fixed = p.dt_fixed; d.t_end = p.t_end;
+    c->any_b |= d.has_b != 0;
+    const int nt = (int)((n + kTileMax - 1) / kTileMax);
+    d.ntiles = nt;
+    d.red_off = nt > 1 ? (int32_t)red : -1;
+    for (int k = 0; k < nt; ++k) {
+      TileDesc t;
+      t.inst = j;
+      t.tidx = k;
+      t.start = (int32_t)((n * k) / nt);
+      t.len = (int32_t)((n * (k + 1)) / nt) - t.start;
+      tall.push_back(t);
+      if (nt > 1) tmulti.push_back(t);
+    }
+    if (nt > 1) {
+      multi.push_back(j);
+      red += 2 * nt;
+    }
+    c->ncell += n;
+  }
+  if (rc == HSGN_OK && red > INT32_MAX) rc = fail(c, HSGN_EINVAL, "reduced system too large");
+  c->ntiles_all = (int)tall.size();
+  c->ntiles_multi = (int)tmulti.size();
+  c->n_multi_inst = (int)multi.size();
+  c->any_multi = c->n_multi_inst > 0;
+  c->red_total = red;
+  if (rc == HSGN_OK) {
+    if (c->user_stream) {
+      c->stream = c->user_stream;
+    } else {
+      hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+      if (e != hipSuccess) rc = fail(c, HSGN_EHIP, "hipStreamCreate: %s", hipGetErrorString(e));
+      c->own_stream = rc == HSGN_OK;
+    }
+  }
+  if (rc == HSGN_OK) {
+    if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+      rc = fail(c, HSGN_EHIP, "hipEventCreate failed");
+  }
+  const size_t nc = (size_t)c->ncell;
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_inst, inst.size());
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_tiles_all, tall.size());
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_tiles_multi, tmulti.size());
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_multi, multi.size());
+  for (int i = 0; i < 3 && rc == HSGN_OK; ++i)
+    for (int f = 0; f < 4 && rc == HSGN_OK; ++f) rc = dmalloc(c, &c->buf[i][f], nc);
+  if (rc == HSGN_OK && c->any_b) rc = dmalloc(c, &c->d_b, nc);
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_dt, (size_t)n_inst);
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_t, (size_t)n_inst);
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_smax, (size_t)n_inst);
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_umax, (size_t)n_inst);
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_status, (size_t)n_inst);
+  double** rp[] = {&c->d_rlo, &c->d_rdi, &c->d_rup, &c->d_rrhs, &c->d_rx,
+                   &c->d_scp, &c->d_sy, &c->d_sv, &c->d_sw};
+  for (double** p : rp)
+    if (rc == HSGN_OK) rc = dmalloc(c, p, (size_t)red);
+  auto up = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (!bytes) return HSGN_OK;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return fail(c, HSGN_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
+    return HSGN_OK;
+  };
+  if (rc == HSGN_OK) rc = enter(c);
+  if (rc == HSGN_OK) rc = up(c->d_inst, inst.data(), inst.size() * sizeof(InstDesc));
+  if (rc == HSGN_OK) rc = up(c->d_tiles_all, tall.data(), tall.size() * sizeof(TileDesc));
+  if (rc == HSGN_OK) rc = up(c->d_tiles_multi, tmulti.data(), tmulti.size() * sizeof(TileDesc));
+  if (rc == HSGN_OK) rc = up(c->d_multi, multi.data(), multi.size() * sizeof(int32_t));
+  if (rc == HSGN_OK && c->any_b) {
+    hipError_t e = hipMemcpyAsync(c->d_b, d_b, nc * sizeof(double), hipMemcpyDeviceToDevice,
+                                  c->stream);
+    if (e != hipSuccess) rc = fail(c, HSGN_EHIP, "copy of b: %s", hipGetErrorString(e));
+  }
+  if (rc == HSGN_OK) {
+    for (int i = 0; i < 3 && rc == HSGN_OK; ++i)
+      for (int f = 0; f < 4 && rc == HSGN_OK; ++f)
+        if (hipMemsetAsync(c->buf[i][f], 0, nc * sizeof(double), c->stream) != hipSuccess)
+          rc = fail(c, HSGN_EHIP, "hipMemsetAsync failed");
+  }
+  if (rc == HSGN_OK) {
+    if (hipMemsetAsync(c->d_t, 0, n_inst * sizeof(double), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_dt, 0, n_inst * sizeof(double), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_smax, 0, n_inst * sizeof(unsigned long long), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_umax, 0, n_inst * sizeof(unsigned long long), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_status, 0, n_inst * sizeof(int32_t), c->stream) != hipSuccess)
+      rc = fail(c, HSGN_EHIP, "hipMemsetAsync failed");
+  }
+  // host vectors are freed on return: wait for the uploads
+  if (rc == HSGN_OK && hipStreamSynchronize(c->stream) != hipSuccess)
+    rc = fail(c, HSGN_EHIP, "hipStreamSynchronize failed");
+  if (rc == HSGN_OK) rc = leave(c);
+  if (rc != HSGN_OK) {
+    fprintf(stderr, "hsgn_init: %s\n", c->err.c_str());
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return HSGN_OK;
+}
+
+int hsgn_set_state(hsgn_ctx* c, const double* d_h, const double* d_q, const double* d_m,
+                   const double* d_W, const double* d_t) {
+  if (!c) return HSGN_EINVAL;
+  if (!d_h || !d_q) return fail(c, HSGN_EINVAL, "hsgn_set_state: h and q are required");
+  int rc = enter(c);
+  if (rc) return rc;
+  const size_t bytes = (size_t)c->ncell * sizeof(double);
+  double** U = c->buf[c->cur];
+  HIPCHK(c, hipMemcpyAsync(U[0], d_h, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(U[1], d_q, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (d_m) HIPCHK(c, hipMemcpyAsync(U[2], d_m, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (d_W) HIPCHK(c, hipMemcpyAsync(U[3], d_W, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (!d_m || !d_W) {
+    const int64_t nb = (c->ncell + 255) / 256;
+    hipLaunchKernelGGL(hsgn::k_default_mW, dim3((unsigned)nb), dim3(256), 0, c->stream, c->ncell,
+                       U[0], U[2], U[3], d_m ? 0 : 1, d_W ? 0 : 1);
+  }
+  if (d_t) {
+    HIPCHK(c, hipMemcpyAsync(c->d_t, d_t, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+  } else {
+    HIPCHK(c, hipMemsetAsync(c->d_t, 0, c->n_inst * sizeof(double), c->stream));
+  }
+  const int nb = (c->n_inst + 255) / 256;
+  hipLaunchKernelGGL(hsgn::k_fill_i32, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_status,
+                     0);
+  hipLaunchKernelGGL(hsgn::k_fill_u64, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_smax,
+                     0ull);
+  hipLaunchKernelGGL(hsgn::k_fill_u64, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_umax,
+                     0ull);
+  hipLaunchKernelGGL(hsgn::k_speed<256>, dim3(c->ntiles_all), dim3(256), 0, c->stream, c->d_inst,
+                     c->d_tiles_all, U[0], U[1], c->d_smax, c->d_umax);
+  HIPCHK(c, hipGetLastError());
+  return leave(c);
+}
+
+int hsgn_get_state(hsgn_ctx* c, double* d_h, double* d_q, double* d_m, double* d_W,
+                   double* d_t) {
+  if (!c) return HSGN_EINVAL;
+  int rc = enter(c);
+  if (rc) return rc;
+  const size_t bytes = (size_t)c->ncell * sizeof(double);
+  double** U = c->buf[c->cur];
+  double* dst[4] = {d_h, d_q, d_m, d_W};
+  for (int f = 0; f < 4; ++f)
+    if (dst[f]) HIPCHK(c, hipMemcpyAsync(dst[f], U[f], bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (d_t)
+    HIPCHK(c, hipMemcpyAsync(d_t, c->d_t, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+  return leave(c);
+}
+
+int hsgn_get_dt(hsgn_ctx* c, double* d_dt) {
+  if (!c || !d_dt) return HSGN_EINVAL;
+  int rc = enter(c);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(d_dt, c->d_dt, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+  return leave(c);
+}
+
+int hsgn_step(hsgn_ctx* c, int32_t nsteps) {
+  if (!c) return HSGN_EINVAL;
+  if (nsteps < 0) return fail(c, HSGN_EINVAL, "hsgn_step: nsteps < 0");
+  int rc = enter(c);
+  for (int s = 0; s < nsteps && rc == HSGN_OK; ++s) rc = enqueue_step(c);
+  if (rc) return rc;
+  return leave(c);
+}
+
+int hsgn_run(hsgn_ctx* c, int32_t nsteps, int32_t block) {
+  if (!c) return HSGN_EINVAL;
+  if (nsteps < 0 || block < 1) return fail(c, HSGN_EINVAL, "hsgn_run: bad nsteps/block");
+  if (block & 1) block += 1;  // the buffer rotation repeats every 2 steps
+  int rc = enter(c);
+  if (rc) return rc;
+  int done = 0;
+  if (nsteps >= block) {
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : c->graphs)
+      if (g.block == block && g.cur == c->cur) exec = g.exec;
+    if (!exec) {
+      const int cur0 = c->cur, nxt0 = c->nxt;
+      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+      int erc = HSGN_OK;
+      for (int s = 0; s < block && erc == HSGN_OK; ++s) erc = enqueue_step(c);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(c->stream, &graph);
+      c->cur = cur0;  // capture does not execute: restore the rotation
+      c->nxt = nxt0;
+      if (erc) return erc;
+      if (e != hipSuccess) return fail(c, HSGN_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (e != hipSuccess)
+        return fail(c, HSGN_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      c->graphs.push_back({block, c->cur, exec});
+    }
+    for (; done + block <= nsteps; done += block)
+      HIPCHK(c, hipGraphLaunch(exec, c->stream));
+  }
+  for (; done < nsteps && rc == HSGN_OK; ++done) rc = enqueue_step(c);
+  if (rc) return rc;
+  return leave(c);
+}
+
+int hsgn_status(hsgn_ctx* c, int32_t* h_flags) {
+  if (!c) return HSGN_EINVAL;
+  std::vector<int32_t> f(c->n_inst);
+  HIPCHK(c, hipMemcpyAsync(f.data(), c->d_status, c->n_inst * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (h_flags) std::memcpy(h_flags, f.data(), f.size() * sizeof(int32_t));
+  int any = 0;
+  for (int j = 0; j < c->n_inst; ++j) any |= f[j];
+  if (any & hsgn::kFlagNonPhys) {
+    for (int j = 0; j < c->n_inst; ++j)
+      if (f[j] & hsgn::kFlagNonPhys) return fail(c, HSGN_ENONPHYS, "instance %d: h <= 0 or non-finite value", j);
+  }
+  if (any & hsgn::kFlagNonCoercive) {
+    for (int j = 0; j < c->n_inst; ++j)
+      if (f[j] & hsgn::kFlagNonCoercive) return fail(c, HSGN_ENONCOERCIVE, "instance %d: beta <= 0", j);
+  }
+  return HSGN_OK;
+}
+
+const char* hsgn_last_error(const hsgn_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void hsgn_destroy(hsgn_ctx* c) {
+  if (!c) return;
+  hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+}  // extern "C"

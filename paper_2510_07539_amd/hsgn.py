@@ -1,0 +1,156 @@
+"""Python binding of the gfx950 hSGN library (libhsgn.so, C ABI in include/hsgn.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels.
+PyTorch provides device memory and the stream.  If the library is not built,
+importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhsgn.so")
+
+HSGN_OK, HSGN_EINVAL, HSGN_EHIP, HSGN_ENONPHYS, HSGN_ENONCOERCIVE, HSGN_ENOMEM = 0, -1, -2, -3, -4, -5
+FLAG_NONPHYS, FLAG_NONCOERCIVE = 1, 2
+BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+
+
+class HsgnParams(C.Structure):
+    _fields_ = [("g", C.c_double), ("lam", C.c_double), ("dx", C.c_double), ("cfl", C.c_double),
+                ("mcfl", C.c_double), ("dt_fixed", C.c_double), ("t_end", C.c_double),
+                ("bc", C.c_int32), ("has_bathymetry", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libhsgn.so is not built (run __graft_entry__.build()); "
+                               "there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.c_void_p
+        L.hsgn_init.restype = C.c_int
+        L.hsgn_init.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(C.c_int64),
+                                C.POINTER(HsgnParams), dp, vp]
+        L.hsgn_set_state.restype = C.c_int
+        L.hsgn_set_state.argtypes = [vp, dp, dp, dp, dp, dp]
+        L.hsgn_get_state.restype = C.c_int
+        L.hsgn_get_state.argtypes = [vp, dp, dp, dp, dp, dp]
+        L.hsgn_get_dt.restype = C.c_int
+        L.hsgn_get_dt.argtypes = [vp, dp]
+        L.hsgn_step.restype = C.c_int
+        L.hsgn_step.argtypes = [vp, C.c_int32]
+        L.hsgn_run.restype = C.c_int
+        L.hsgn_run.argtypes = [vp, C.c_int32, C.c_int32]
+        L.hsgn_status.restype = C.c_int
+        L.hsgn_status.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.hsgn_last_error.restype = C.c_char_p
+        L.hsgn_last_error.argtypes = [vp]
+        L.hsgn_version.restype = C.c_char_p
+        L.hsgn_destroy.restype = None
+        L.hsgn_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+class HsgnError(RuntimeError):
+    pass
+
+
+class Solver:
+    """A batch of independent hSGN instances on one GPU.
+
+    offsets: int64 sequence (n_inst + 1); params: list of dicts with keys
+    g, lam, dx, cfl, mcfl, dt_fixed, t_end, bc, has_b; b: float64 device
+    tensor (sum of sizes) or None.
+    """
+
+    def __init__(self, offsets, params, b=None, device="cuda", stream=None):
+        L = lib()
+        self.device = torch.device(device)
+        offs = np.ascontiguousarray(offsets, dtype=np.int64)
+        self.n_inst = len(offs) - 1
+        self.ncell = int(offs[-1])
+        pa = (HsgnParams * self.n_inst)()
+        for j, p in enumerate(params):
+            pa[j] = HsgnParams(p["g"], p["lam"], p["dx"], p["cfl"], p["mcfl"], p["dt_fixed"],
+                               p["t_end"], int(p["bc"]), int(p["has_b"]))
+        if b is not None:
+            b = b.to(self.device, torch.float64).contiguous()
+        self._b = b
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._stream = s
+        h = C.c_void_p()
+        rc = L.hsgn_init(C.byref(h), self.n_inst, offs.ctypes.data_as(C.POINTER(C.c_int64)), pa,
+                         _ptr(b), C.c_void_p(s.cuda_stream))
+        if rc != HSGN_OK:
+            raise HsgnError("hsgn_init failed (%d)" % rc)
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, wl, device="cuda"):
+        params = [dict(g=wl.g[j], lam=wl.lam[j], dx=wl.dx[j], cfl=wl.cfl[j], mcfl=wl.mcfl[j],
+                       dt_fixed=wl.dt_fixed[j], t_end=wl.t_end[j], bc=wl.bc[j], has_b=wl.has_b[j])
+                  for j in range(wl.n_inst)]
+        b = None if wl.b is None else torch.from_numpy(wl.b).to(device)
+        s = cls(wl.offsets, params, b, device=device)
+        s.set_state(*[torch.from_numpy(a).to(device) for a in wl.state()])
+        return s
+
+    def _check(self, rc, what):
+        if rc != HSGN_OK:
+            msg = lib().hsgn_last_error(self._h).decode()
+            raise HsgnError("%s failed (%d): %s" % (what, rc, msg))
+
+    def set_state(self, h, q, m=None, W=None, t=None):
+        self._keep = (h, q, m, W, t)
+        self._check(lib().hsgn_set_state(self._h, _ptr(h), _ptr(q), _ptr(m), _ptr(W), _ptr(t)),
+                    "hsgn_set_state")
+
+    def get_state(self):
+        out = [torch.empty(self.ncell, dtype=torch.float64, device=self.device) for _ in range(4)]
+        t = torch.empty(self.n_inst, dtype=torch.float64, device=self.device)
+        self._check(lib().hsgn_get_state(self._h, *[_ptr(a) for a in out], _ptr(t)), "hsgn_get_state")
+        return tuple(out), t
+
+    def get_dt(self):
+        d = torch.empty(self.n_inst, dtype=torch.float64, device=self.device)
+        self._check(lib().hsgn_get_dt(self._h, _ptr(d)), "hsgn_get_dt")
+        return d
+
+    def step(self, nsteps=1):
+        self._check(lib().hsgn_step(self._h, int(nsteps)), "hsgn_step")
+
+    def run(self, nsteps, block=100):
+        self._check(lib().hsgn_run(self._h, int(nsteps), int(block)), "hsgn_run")
+
+    def status(self):
+        f = np.zeros(self.n_inst, dtype=np.int32)
+        rc = lib().hsgn_status(self._h, f.ctypes.data_as(C.POINTER(C.c_int32)))
+        return rc, f
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hsgn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -109,7 +109,7 @@ def soliton(x, h0, a, x0, t=0.0, g=G):
     eps = a / h0
     C = np.sqrt(g * h0 * (1.0 + eps))
     kap = np.sqrt(3.0 * eps / (4.0 * h0 * h0 * (1.0 + eps)))
-    xi = kap * (x - x0 - C * t)
+    xi = np.clip(kap * (x - x0 - C * t), -300.0, 300.0)
     sech2 = 1.0 / np.cosh(xi) ** 2
     h = h0 * (1.0 + eps * sech2)
     u = C * (1.0 - h0 / h)

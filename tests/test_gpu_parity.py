@@ -1,0 +1,200 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bar, per instance, after the given number of steps:
+ (1) state: max over fields and cells of |gpu - oracle| divided by max over
+     fields and cells of |oracle| <= 1e-11 (relative error of the state);
+ (2) every field f: max |gpu_f - oracle_f| <= max(1e-11 max |oracle_f|,
+     8 d_f), where d_f is how far the oracle's own f moves when its initial
+     state is perturbed by 2^-53 relative (its rounding sensitivity).  On the
+     stiff instances (lambda >= 1e3 over the bar) W = h w is the difference
+     of two O(lambda tau) terms, and a half-ulp input perturbation already
+     moves it by 2e-11 relative to max |W| after 100 steps.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_2510_07539_amd import workloads as WL  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def _solver():
+    from paper_2510_07539_amd.hsgn import Solver
+    return Solver
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def field_err(a, ref):
+    scale = np.max(np.abs(ref))
+    d = np.max(np.abs(a - ref)) if len(ref) else 0.0
+    return d / scale if scale > 0 else d
+
+
+def check_instance(j, U, wl, nsteps, tol=TOL, seed=0):
+    """Bars (1) and (2) for instance j; returns (state error, worst field ratio)."""
+    n, prm, b, U0 = wl.instance(j)
+    p = O.make_params(**prm)
+    orc, Uo, to = O.run(p, b, U0, 0.0, nsteps)
+    assert orc == 0, ("oracle", j, orc)
+    rng = np.random.default_rng(seed + j)
+    Up0 = tuple(u * (1.0 + 2.0 ** -53 * rng.choice([-1.0, 1.0], size=n)) for u in U0)
+    _, Up, _ = O.run(p, b, Up0, 0.0, nsteps)
+    o0, o1 = int(wl.offsets[j]), int(wl.offsets[j + 1])
+    scale = max(np.max(np.abs(x)) for x in Uo)
+    dev = [np.max(np.abs(U[f][o0:o1] - Uo[f])) for f in range(4)]
+    state_err = max(dev) / scale
+    assert state_err <= tol, ("instance", j, "state", state_err)
+    worst = 0.0
+    for f in range(4):
+        sens = np.max(np.abs(Up[f] - Uo[f]))
+        bound = max(tol * np.max(np.abs(Uo[f])), 8.0 * sens, 1e-300)
+        assert dev[f] <= bound, ("instance", j, "field", "hqmW"[f], dev[f], bound, sens)
+        worst = max(worst, dev[f] / bound)
+    return state_err, worst, to
+
+
+def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label=""):
+    note("parity %s: %s, %d instances, %d cells, %d steps" % (label, wl.name, wl.n_inst,
+                                                              wl.n_cells, nsteps))
+    Solver = _solver()
+    s = Solver.from_workload(wl)
+    if use_run:
+        s.run(nsteps, block=block)
+    else:
+        s.step(nsteps)
+    (h, q, m, W), t = s.get_state()
+    rc, flags = s.status()
+    assert rc == 0, ("status", rc, np.nonzero(flags))
+    U = [x.cpu().numpy() for x in (h, q, m, W)]
+    tg = t.cpu().numpy()
+    s.close()
+    insts = range(wl.n_inst) if insts is None else insts
+    worst = 0.0
+    worst_ratio = 0.0
+    for j in insts:
+        e, r, to = check_instance(j, U, wl, nsteps, tol)
+        assert abs(tg[j] - to) <= 1e-12 * max(1.0, abs(to)), (j, tg[j], to)
+        worst = max(worst, e)
+        worst_ratio = max(worst_ratio, r)
+    note("  worst state deviation %.3e, worst field deviation / bound %.3f" % (worst, worst_ratio))
+    return worst
+
+
+def test_solitary_single_tile_100_steps():
+    compare(WL.solitary(N=800, t_end=0.0), 100, label="C1 geometry")
+
+
+def test_solitary_to_t_end():
+    # the full solitary-wave configuration: t_end = 10 s (about 178 steps)
+    wl = WL.solitary()
+    compare(wl, 200, label="C1 to t_end")
+
+
+def test_multi_tile_periodic():
+    compare(WL.solitary(N=5000, L=1250.0, lam=1000.0, t_end=0.0), 100, label="periodic 3 tiles")
+
+
+def test_dam_break_transmissive_multi_tile():
+    compare(WL.dam_break(), 100, label="C2 100 steps")
+
+
+def test_batched_bar_small_batch():
+    wl = WL.batched_bar(n_inst=16, seed=5, n_lo=512, n_hi=6000)
+    compare(wl, 100, label="bar batch")
+
+
+def test_graph_run_matches_step_bitwise():
+    Solver = _solver()
+    wl = WL.concat("mix", [WL.solitary(N=3000, L=750.0, t_end=0.0),
+                           WL.batched_bar(n_inst=3, seed=2, n_lo=700, n_hi=5000)])
+    s1 = Solver.from_workload(wl)
+    s1.step(60)
+    s2 = Solver.from_workload(wl)
+    s2.run(60, block=20)
+    (a, ta), (b, tb) = s1.get_state(), s2.get_state()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    assert torch.equal(ta, tb)
+    # several replays of the cached graph, with eager work in between
+    s2.step(3)
+    s2.run(40, block=20)
+    s1.step(43)
+    (a, _), (b, _) = s1.get_state(), s2.get_state()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_edge_sizes_and_frozen_instances():
+    parts = []
+    for n in (4, 5, 7, 9, 31, 513, 2047, 2048, 2049, 4097):
+        for bc in (0, 1):
+            parts.append(WL.solitary(N=n, L=0.25 * n, lam=300.0, t_end=0.0, bc=bc,
+                                     x0=0.125 * n))
+    # an instance that reaches t_end after a few steps, then stays frozen
+    parts.append(WL.solitary(N=600, L=150.0, lam=100.0, t_end=0.2))
+    # fixed time step
+    fixed = WL.solitary(N=1000, L=250.0, lam=100.0, t_end=0.0)
+    fixed.dt_fixed[:] = 0.01
+    parts.append(fixed)
+    parts.append(WL.lake_at_rest(N=700, lam=1e4, bed=True))
+    wl = WL.concat("edges", parts)
+    compare(wl, 30, label="edge sizes")
+
+
+def test_lake_at_rest_gpu():
+    Solver = _solver()
+    for lam in (100.0, 1e4):
+        wl = WL.lake_at_rest(N=3000, lam=lam, bed=True)
+        s = Solver.from_workload(wl)
+        s.step(100)
+        (h, q, m, W), _ = s.get_state()
+        b = torch.from_numpy(wl.b).to(h.device)
+        assert float((h + b - 0.4).abs().max()) <= 1e-12
+        assert float(q.abs().max()) <= 1e-12
+        assert float(W.abs().max()) <= 1e-12
+
+
+def test_nonphysical_state_is_flagged_and_frozen():
+    Solver = _solver()
+    wl = WL.concat("bad", [WL.solitary(N=400, L=100.0, t_end=0.0),
+                           WL.solitary(N=400, L=100.0, t_end=0.0)])
+    wl.h[wl.offsets[1] + 10] = -0.5  # negative depth in the second instance
+    s = Solver.from_workload(wl)
+    s.step(3)
+    rc, flags = s.status()
+    assert rc != 0 and flags[1] != 0 and flags[0] == 0
+    (h, q, m, W), t = s.get_state()
+    # the healthy instance still matches the oracle
+    U = [x.cpu().numpy() for x in (h, q, m, W)]
+    check_instance(0, U, wl, 3)
+
+
+@pytest.mark.parametrize("N", [1 << 16])
+def test_long_periodic_scaled(N):
+    wl = WL.long_periodic(N=N)
+    compare(wl, 20, label="long periodic scaled")
+
+
+def test_batched_full_size_sampled():
+    """The full batched workload (4096 instances) in the launch configuration
+    the benchmark times (graph-captured blocks); instances sampled for the
+    oracle."""
+    wl = WL.batched_bar()
+    sizes = wl.sizes()
+    pick = [int(np.argmin(sizes)), int(np.argmax(sizes)), 0, 1, 2047, 4095]
+    lam = wl.lam
+    for v in (100.0, 1000.0, 10000.0):
+        pick.append(int(np.nonzero(lam == v)[0][0]))
+    compare(wl, 100, use_run=True, block=100, insts=sorted(set(pick)), label="C3 full, sampled")
