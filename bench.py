@@ -1,0 +1,227 @@
+"""Benchmark of the gfx950 hSGN IMEX step.
+
+Default workload: the batched ensemble -- 4096 independent 1D instances,
+N_j ~ U{512..16384} cells, solitary waves over a trapezoidal bar, lambda_j
+from {100, 1000, 10000}, FP64, HIP-graph-captured step blocks.  One "step" is
+one full two-stage IMEX step of every instance.  Metric: cell-stage updates
+per second (one cell advanced through one IMEX stage).
+
+Prints ONE JSON line.  Also reported: the same kernels on one instance per
+context with eager launches (the per-instance GPU path), the roofline of the
+dominant kernel from HIP events on the library's stream, and the CPU oracle
+on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+CSRC = [os.path.join(ROOT, "paper_2510_07539_amd", "csrc", f) for f in ("hsgn.hip", "hsgn_kernels.hpp")]
+
+# HBM traffic of the dominant kernel measured with rocprofv3 --pmc (FETCH_SIZE
+# and WRITE_SIZE in separate runs), scaled by the same counters on a plain
+# copy of known size.  Keyed by the hash of the kernel sources it was taken
+# on; reported as null once the sources change.
+TRAFFIC = {}
+
+
+def src_hash():
+    h = hashlib.sha256()
+    for f in CSRC:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_cell(kind, bed):
+    """Algorithmic HBM bytes per cell for one launch of a kernel kind:
+    what the kernel must read and write at least once (FP64)."""
+    b = 1 if bed else 0
+    return {"stage1": (4 + b + 4) * 8,      # reads U^n (+ b), writes U^(1)
+            "stage2": (8 + b + 4) * 8,      # reads U^n, U^(1) (+ b), writes U^{n+1}
+            "reduce1": (4 + b) * 8,         # reads U^n (+ b)
+            "reduce2": (8 + b) * 8,         # reads U^n, U^(1) (+ b)
+            }.get(kind, 0)
+
+
+def make_workload(name):
+    from paper_2510_07539_amd import workloads as WL
+    if name == "batched_bar":
+        return WL.batched_bar(), ("batched_bar: 4096 instances, N_j~U{512..16384} (seed 3), "
+                                  "dx=0.04 m, h0=0.4 m, soliton a_j~U[0.05,0.4]h0 over a "
+                                  "trapezoidal bar (0.3 m, 1:20 / 2 m crest / 1:10), "
+                                  "lambda_j in {100,1000,10000}, transmissive, CFL 0.9")
+    if name == "dam_break":
+        return WL.dam_break(), "dam_break: N=20000 on [-300,300] m, lambda=1000, transmissive"
+    if name == "long_periodic":
+        return WL.long_periodic(), "long_periodic: N=2^24, dx=0.01 m, lambda=1e4, periodic"
+    if name == "solitary":
+        w = WL.solitary(t_end=0.0)
+        return w, "solitary: N=800 on [0,200] m, h0=1, a=0.2, lambda=100, periodic"
+    raise SystemExit("unknown workload " + name)
+
+
+def per_instance_rate(wl, n_sample, steps):
+    """Same kernels, one context per instance, eager launches in a host loop."""
+    import numpy as np
+    import torch
+    from paper_2510_07539_amd.hsgn import Solver
+    idx = np.linspace(0, wl.n_inst - 1, n_sample).astype(int)
+    solvers = [Solver.from_workload(wl.subset([int(j)])) for j in idx]
+    for s in solvers:
+        s.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for s in solvers:
+            s.step(1)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cells = int(sum(wl.sizes()[idx]))
+    for s in solvers:
+        s.close()
+    return 2.0 * cells * steps / el, el, n_sample
+
+
+def cpu_baseline(wl, budget_s=15.0, n_sample=128):
+    """The oracle (OpenMP over instances, all host threads) on a bounded
+    sample: the first n_sample instances, in chunks of steps until the time
+    budget is spent."""
+    import oracle as O
+    sub = wl.subset(range(min(n_sample, wl.n_inst)))
+    plist = [O.make_params(**sub.instance(j)[1]) for j in range(sub.n_inst)]
+    U = sub.state()
+    t = [0.0] * sub.n_inst
+    steps, el = 0, 0.0
+    chunk = 5
+    while el < budget_s and steps < 200:
+        t0 = time.perf_counter()
+        rc, U, t, st = O.run_batch(sub.offsets, plist, sub.b, U, t, chunk, nthreads=0)
+        el += time.perf_counter() - t0
+        steps += chunk
+        if rc != 0:
+            break
+    cores = min(O.max_threads(), sub.n_inst)
+    rate = 2.0 * sub.n_cells * steps / el
+    return {"value": rate, "unit": "cell-stage updates/s", "cores": cores, "kind": "oracle",
+            "sample": "first %d instances (%d cells) of the same workload, %d IMEX steps, %.1f s"
+                      % (sub.n_inst, sub.n_cells, steps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--block", type=int, default=100)
+    ap.add_argument("--workload", default="batched_bar")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-per-instance", action="store_true")
+    ap.add_argument("--timed-steps", type=int, default=10)
+    ap.add_argument("--probe", action="store_true",
+                    help="counter probe: a plain copy of known size, then eager steps")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: there is no multi-GPU path in this library "
+              "(the instances are independent, so a batch would shard across GPUs by "
+              "instance with no communication).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2510_07539_amd.hsgn import Solver
+
+    wl, desc = make_workload(args.workload)
+    bed = wl.b is not None
+    s = Solver.from_workload(wl)
+
+    if args.probe:
+        a = torch.empty(64 << 20, dtype=torch.float64, device="cuda")  # 512 MiB
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        s.step(3)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": True, "copy_bytes": a.numel() * 8, "cells": wl.n_cells}))
+        return
+
+    # warmup (also captures the graph)
+    s.run(args.warmup, block=args.block)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run(args.steps, block=args.block)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rc, flags = s.status()
+    if rc != 0:
+        print("solver flagged %d instances" % int((flags != 0).sum()), file=sys.stderr)
+        sys.exit(1)
+    cell_stages = 2.0 * wl.n_cells * args.steps
+    value = cell_stages / el
+    ms_step = 1e3 * el / args.steps
+
+    # per-kernel durations from HIP events on the library's stream
+    kt = s.step_timed(args.timed_steps)
+    multi_cells = 0
+    sizes = wl.sizes()
+    multi_cells = int(sizes[sizes > 2048].sum())
+    tot = {k: v[0] for k, v in kt.items()}
+    dom = max(tot, key=lambda k: tot[k])
+    ms_avg, launches = kt[dom][0] / max(kt[dom][1], 1), kt[dom][1]
+    cells_launch = multi_cells if dom.startswith("reduce") else wl.n_cells
+    alg_bytes = bytes_per_cell(dom, bed) * cells_launch
+    achieved = alg_bytes / (ms_avg * 1e-3) / 1e9 if ms_avg > 0 else 0.0
+    h = src_hash()
+    tr = TRAFFIC.get(h)
+    traffic = None
+    if tr and tr.get("kernel") == dom and tr.get("workload") == args.workload:
+        traffic = tr["bytes_per_launch"]
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+            "kernel": "k_stage<%s>" % dom, "avg_launch_ms": round(ms_avg, 4),
+            "alg_bytes_per_launch": alg_bytes,
+            "alg_bytes_per_cell": bytes_per_cell(dom, bed)}
+    step_bytes = (bytes_per_cell("stage1", bed) + bytes_per_cell("stage2", bed)) / 2.0
+    out = {
+        "metric": "cell-stage updates/s (FP64, batched vs per-instance) at 1e-11 oracle match",
+        "value": value,
+        "unit": "cell-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "n_inst": wl.n_inst, "cells": wl.n_cells,
+                   "graph_block_steps": args.block},
+        "roofline": roof,
+        "step_hbm_frac": round(value * step_bytes / 1e9 / HBM_PEAK_GBPS, 4),
+        "kernel_ms_per_step": {k: round(v[0] / args.timed_steps, 4) for k, v in kt.items() if v[1]},
+    }
+    if not args.no_per_instance and wl.n_inst > 1:
+        r, pel, ns = per_instance_rate(wl, 32, 3)
+        out["per_instance"] = {"value": r, "unit": "cell-stage updates/s",
+                               "sample": "%d instances spread over the batch, one context each, "
+                                         "eager launches, 3 steps" % ns}
+        out["batched_over_per_instance"] = value / r
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    s.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -109,6 +109,23 @@ int hsgn_step(hsgn_ctx* ctx, int32_t nsteps);
  * eagerly.  Same results as hsgn_step. */
 int hsgn_run(hsgn_ctx* ctx, int32_t nsteps, int32_t block);
 
+/* Kernel kinds timed by hsgn_step_timed. */
+#define HSGN_K_DT 0           /* time step per instance                     */
+#define HSGN_K_REDUCE1 1      /* stage 1, tile reduction (multi-tile only)   */
+#define HSGN_K_RSOLVE1 2      /* stage 1, reduced system across tiles        */
+#define HSGN_K_STAGE1 3       /* stage 1, sweep + solve + back-substitution  */
+#define HSGN_K_REDUCE2 4
+#define HSGN_K_RSOLVE2 5
+#define HSGN_K_STAGE2 6
+#define HSGN_NKERNEL 7
+
+/* Measurement variant of hsgn_step: the same launches, each bracketed by HIP
+ * events on the library's stream; synchronises at the end.  h_ms[k]
+ * receives the summed milliseconds of kernel kind k over the nsteps steps
+ * and h_count[k] its number of launches (host arrays of HSGN_NKERNEL;
+ * either may be NULL).  Results are identical to hsgn_step. */
+int hsgn_step_timed(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_count);
+
 /* Synchronise the stream and copy the per-instance status bits to host
  * (h_flags: n_inst int32, may be NULL).  Returns HSGN_OK if no instance is
  * flagged, else HSGN_ENONPHYS or HSGN_ENONCOERCIVE. */

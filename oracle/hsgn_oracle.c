@@ -10,7 +10,7 @@
  * relaxation elimination, linearised elliptic problem for the new depth,
  * back-substitution), one loop per formula.
  *
- * Readings of the paper taken here (each is discussed in the design notes):
+ * Readings of the paper taken here:
  *  - the stage is the fully discrete first-order semi-implicit step of
  *    Sec. 4.2 (eq. GN_hyp_eq_semi_fully_discrete) with dt -> tau, explicit
  *    terms and frozen coefficients taken from the explicit stage value U_E,

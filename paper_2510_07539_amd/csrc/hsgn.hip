@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -175,23 +176,44 @@ StageArgs stage_args(hsgn_ctx* c, int stage) {
 }
 
 // Enqueue one IMEX step (no synchronisation), then rotate the buffers.
-int enqueue_step(hsgn_ctx* c) {
+// With `tm`, every launch is bracketed by a pair of events (kind k).
+int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* tm = nullptr) {
+  auto mark = [&](int kind, bool begin) {
+    if (!tm) return;
+    if (begin) {
+      hipEvent_t a, b;
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      tm->push_back({kind, {a, b}});
+      hipEventRecord(a, c->stream);
+    } else {
+      hipEventRecord(tm->back().second.second, c->stream);
+    }
+  };
   const int nb = (c->n_inst + 255) / 256;
+  mark(HSGN_K_DT, true);
   hipLaunchKernelGGL(hsgn::k_dt, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_inst, c->d_dt,
                      c->d_t, c->d_smax, c->d_umax, c->d_status);
+  mark(HSGN_K_DT, false);
   for (int stage = 1; stage <= 2; ++stage) {
     StageArgs a = stage_args(c, stage);
     if (c->any_multi) {
       a.tiles = c->d_tiles_multi;
+      mark(stage == 1 ? HSGN_K_REDUCE1 : HSGN_K_REDUCE2, true);
       if (stage == 1) launch_stage_any<1>(c, a, c->ntiles_multi, true);
       else launch_stage_any<2>(c, a, c->ntiles_multi, true);
+      mark(stage == 1 ? HSGN_K_REDUCE1 : HSGN_K_REDUCE2, false);
+      mark(stage == 1 ? HSGN_K_RSOLVE1 : HSGN_K_RSOLVE2, true);
       hipLaunchKernelGGL(hsgn::k_rsolve<kNTR>, dim3(c->n_multi_inst), dim3(kNTR), 0, c->stream,
                          c->d_inst, c->d_multi, c->d_dt, c->d_rlo, c->d_rdi, c->d_rup, c->d_rrhs,
                          c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw);
+      mark(stage == 1 ? HSGN_K_RSOLVE1 : HSGN_K_RSOLVE2, false);
     }
     a.tiles = c->d_tiles_all;
+    mark(stage == 1 ? HSGN_K_STAGE1 : HSGN_K_STAGE2, true);
     if (stage == 1) launch_stage_any<1>(c, a, c->ntiles_all, false);
     else launch_stage_any<2>(c, a, c->ntiles_all, false);
+    mark(stage == 1 ? HSGN_K_STAGE1 : HSGN_K_STAGE2, false);
   }
   HIPCHK(c, hipGetLastError());
   const int old = c->cur;
@@ -450,6 +472,31 @@ int hsgn_run(hsgn_ctx* c, int32_t nsteps, int32_t block) {
   }
   for (; done < nsteps && rc == HSGN_OK; ++done) rc = enqueue_step(c);
   if (rc) return rc;
+  return leave(c);
+}
+
+int hsgn_step_timed(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_count) {
+  if (!c) return HSGN_EINVAL;
+  if (nsteps < 0) return fail(c, HSGN_EINVAL, "hsgn_step_timed: nsteps < 0");
+  int rc = enter(c);
+  if (rc) return rc;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> tm;
+  for (int s = 0; s < nsteps && rc == HSGN_OK; ++s) rc = enqueue_step(c, &tm);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  double ms[HSGN_NKERNEL] = {0};
+  int32_t cnt[HSGN_NKERNEL] = {0};
+  for (auto& x : tm) {
+    float f = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&f, x.second.first, x.second.second);
+    ms[x.first] += f;
+    cnt[x.first] += 1;
+    hipEventDestroy(x.second.first);
+    hipEventDestroy(x.second.second);
+  }
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(c, HSGN_EHIP, "hsgn_step_timed: %s", hipGetErrorString(e));
+  if (h_ms) std::memcpy(h_ms, ms, sizeof ms);
+  if (h_count) std::memcpy(h_count, cnt, sizeof cnt);
   return leave(c);
 }
 

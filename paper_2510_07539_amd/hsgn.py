@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libhsgn.so")
 
 HSGN_OK, HSGN_EINVAL, HSGN_EHIP, HSGN_ENONPHYS, HSGN_ENONCOERCIVE, HSGN_ENOMEM = 0, -1, -2, -3, -4, -5
 FLAG_NONPHYS, FLAG_NONCOERCIVE = 1, 2
+KERNEL_KINDS = ("dt", "reduce1", "rsolve1", "stage1", "reduce2", "rsolve2", "stage2")
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 
 
@@ -50,6 +51,8 @@ def lib():
         L.hsgn_step.argtypes = [vp, C.c_int32]
         L.hsgn_run.restype = C.c_int
         L.hsgn_run.argtypes = [vp, C.c_int32, C.c_int32]
+        L.hsgn_step_timed.restype = C.c_int
+        L.hsgn_step_timed.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.hsgn_status.restype = C.c_int
         L.hsgn_status.argtypes = [vp, C.POINTER(C.c_int32)]
         L.hsgn_last_error.restype = C.c_char_p
@@ -138,6 +141,14 @@ class Solver:
 
     def run(self, nsteps, block=100):
         self._check(lib().hsgn_run(self._h, int(nsteps), int(block)), "hsgn_run")
+
+    def step_timed(self, nsteps=1):
+        """Eager steps with HIP events around every launch; returns
+        {kind: (total_ms, launches)}."""
+        ms = (C.c_double * len(KERNEL_KINDS))()
+        cnt = (C.c_int32 * len(KERNEL_KINDS))()
+        self._check(lib().hsgn_step_timed(self._h, int(nsteps), ms, cnt), "hsgn_step_timed")
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}
 
     def status(self):
         f = np.zeros(self.n_inst, dtype=np.int32)
