@@ -45,6 +45,8 @@ def bytes_per_cell(kind, bed):
     b = 1 if bed else 0
     return {"stage1": (4 + b + 4) * 8,      # reads U^n (+ b), writes U^(1)
             "stage2": (8 + b + 4) * 8,      # reads U^n, U^(1) (+ b), writes U^{n+1}
+            "win1": (4 + b + 4) * 8,
+            "win2": (8 + b + 4) * 8,
             "reduce1": (4 + b) * 8,         # reads U^n (+ b)
             "reduce2": (8 + b) * 8,         # reads U^n, U^(1) (+ b)
             }.get(kind, 0)
@@ -124,6 +126,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-instance", action="store_true")
     ap.add_argument("--timed-steps", type=int, default=10)
+    ap.add_argument("--solver", default="auto", choices=["auto", "exact", "auto_small"])
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: a plain copy of known size, then eager steps")
     args = ap.parse_args()
@@ -141,7 +144,8 @@ def main():
 
     wl, desc = make_workload(args.workload)
     bed = wl.b is not None
-    s = Solver.from_workload(wl)
+    s = Solver.from_workload(wl, solver=args.solver)
+    plan = s.plan_info()
 
     if args.probe:
         a = torch.empty(64 << 20, dtype=torch.float64, device="cuda")  # 512 MiB
@@ -172,13 +176,16 @@ def main():
 
     # per-kernel durations from HIP events on the library's stream
     kt = s.step_timed(args.timed_steps)
-    multi_cells = 0
     sizes = wl.sizes()
-    multi_cells = int(sizes[sizes > 2048].sum())
+    mode = plan["mode"]
+    ex_cells = int(sizes[mode == 1].sum())
+    ex_multi_cells = int(sizes[(mode == 1) & (sizes > 2048)].sum())
+    win_cells = int(sizes[mode == 0].sum())
     tot = {k: v[0] for k, v in kt.items()}
     dom = max(tot, key=lambda k: tot[k])
     ms_avg, launches = kt[dom][0] / max(kt[dom][1], 1), kt[dom][1]
-    cells_launch = multi_cells if dom.startswith("reduce") else wl.n_cells
+    cells_launch = {"reduce1": ex_multi_cells, "reduce2": ex_multi_cells, "stage1": ex_cells,
+                    "stage2": ex_cells, "win1": win_cells, "win2": win_cells}.get(dom, 0)
     alg_bytes = bytes_per_cell(dom, bed) * cells_launch
     achieved = alg_bytes / (ms_avg * 1e-3) / 1e9 if ms_avg > 0 else 0.0
     h = src_hash()
@@ -188,7 +195,8 @@ def main():
         traffic = tr["bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-            "kernel": "k_stage<%s>" % dom, "avg_launch_ms": round(ms_avg, 4),
+            "kernel": ("k_win<%s>" if dom.startswith("win") else "k_stage<%s>") % dom,
+            "avg_launch_ms": round(ms_avg, 4),
             "alg_bytes_per_launch": alg_bytes,
             "alg_bytes_per_cell": bytes_per_cell(dom, bed)}
     step_bytes = (bytes_per_cell("stage1", bed) + bytes_per_cell("stage2", bed)) / 2.0
@@ -206,7 +214,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n_inst": wl.n_inst, "cells": wl.n_cells,
-                   "graph_block_steps": args.block},
+                   "graph_block_steps": args.block, "solver": args.solver,
+                   "windows": plan["windows"], "window_rows": plan["window_rows"],
+                   "two_pass_tiles": plan["exact_tiles"]},
         "roofline": roof,
         "step_hbm_frac": round(value * step_bytes / 1e9 / HBM_PEAK_GBPS, 4),
         "kernel_ms_per_step": {k: round(v[0] / args.timed_steps, 4) for k, v in kt.items() if v[1]},

@@ -50,11 +50,13 @@ extern "C" {
 #define HSGN_ENONPHYS (-3)      /* some instance produced h <= 0 or NaN      */
 #define HSGN_ENONCOERCIVE (-4)  /* some instance produced beta <= 0          */
 #define HSGN_ENOMEM (-5)        /* device allocation failed                  */
+#define HSGN_EWINDOW (-6)       /* windowed solve could not certify its truncation */
 
 /* Per-instance status bits returned by hsgn_status. A flagged instance is
  * frozen: its later steps use dt = 0 and leave its state unchanged. */
 #define HSGN_FLAG_NONPHYS 1     /* h <= 0, or a non-finite value, in a stage */
 #define HSGN_FLAG_NONCOERCIVE 2 /* beta <= 0 (coercivity, Sec. 3.1 prop.)  */
+#define HSGN_FLAG_WINDOW 4      /* windowed solve: truncation bound > 2^-56  */
 
 typedef enum { HSGN_BC_PERIODIC = 0, HSGN_BC_TRANSMISSIVE = 1 } hsgn_bc;
 
@@ -109,6 +111,31 @@ int hsgn_step(hsgn_ctx* ctx, int32_t nsteps);
  * eagerly.  Same results as hsgn_step. */
 int hsgn_run(hsgn_ctx* ctx, int32_t nsteps, int32_t block);
 
+/* How the tridiagonal system of each stage is solved.
+ *  HSGN_SOLVER_AUTO: an instance that fits one 4096-row window is solved in
+ *    one pass, exactly.  A longer instance is cut into windows that solve
+ *    their core plus a halo of L rows per side (L from the decay of the
+ *    inverse of the depth system at the loaded state, margin 2); each
+ *    window bounds the effect of the truncation on its core and flags the
+ *    instance (HSGN_FLAG_WINDOW) if it exceeds 2^-56 of the depth.  When L
+ *    would exceed a quarter window the instance uses the exact solver.
+ *  HSGN_SOLVER_EXACT: two passes per stage for every instance longer than
+ *    2048 cells: tiles reduce to two rows each, a per-instance reduced
+ *    system is solved, and the tiles finish (no truncation anywhere).
+ *  HSGN_SOLVER_AUTO_SMALL: AUTO with 2048-row windows.
+ * The plan is made from the state loaded by hsgn_set_state (speed bound
+ * and maximum depth per instance); hsgn_set_solver re-plans at once. */
+#define HSGN_SOLVER_AUTO 0
+#define HSGN_SOLVER_EXACT 1
+#define HSGN_SOLVER_AUTO_SMALL 2
+int hsgn_set_solver(hsgn_ctx* ctx, int32_t mode);
+
+/* Plan of the loaded state (host arrays, any may be NULL): h_mode[j] = 0
+ * windowed / 1 exact two-pass; h_halo[j] = halo rows L of instance j;
+ * h_counts[4] = {windows, two-pass tiles, two-pass instances with more than
+ * one tile, window rows}. */
+int hsgn_plan_info(hsgn_ctx* ctx, int32_t* h_mode, int32_t* h_halo, int32_t* h_counts);
+
 /* Kernel kinds timed by hsgn_step_timed. */
 #define HSGN_K_DT 0           /* time step per instance                     */
 #define HSGN_K_REDUCE1 1      /* stage 1, tile reduction (multi-tile only)   */
@@ -117,7 +144,9 @@ int hsgn_run(hsgn_ctx* ctx, int32_t nsteps, int32_t block);
 #define HSGN_K_REDUCE2 4
 #define HSGN_K_RSOLVE2 5
 #define HSGN_K_STAGE2 6
-#define HSGN_NKERNEL 7
+#define HSGN_K_WIN1 7         /* stage 1, windowed single pass               */
+#define HSGN_K_WIN2 8         /* stage 2, windowed single pass               */
+#define HSGN_NKERNEL 9
 
 /* Measurement variant of hsgn_step: the same launches, each bracketed by HIP
  * events on the library's stream; synchronises at the end.  h_ms[k]
@@ -128,7 +157,7 @@ int hsgn_step_timed(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_coun
 
 /* Synchronise the stream and copy the per-instance status bits to host
  * (h_flags: n_inst int32, may be NULL).  Returns HSGN_OK if no instance is
- * flagged, else HSGN_ENONPHYS or HSGN_ENONCOERCIVE. */
+ * flagged, else HSGN_ENONPHYS, HSGN_EWINDOW or HSGN_ENONCOERCIVE. */
 int hsgn_status(hsgn_ctx* ctx, int32_t* h_flags);
 
 /* Message describing the last failure of this context ("" if none).  The

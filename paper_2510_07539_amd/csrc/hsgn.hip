@@ -19,8 +19,11 @@
 #include <string>
 #include <vector>
 
+#include <cmath>
+
 #include "hsgn.h"
 #include "hsgn_kernels.hpp"
+#include "hsgn_window.hpp"
 
 namespace {
 
@@ -28,10 +31,13 @@ constexpr int kNT = 256;      // threads per stage workgroup
 constexpr int kKMAX = 8;      // max cells per thread
 constexpr int kTileMax = kNT * kKMAX;
 constexpr int kNTR = 256;     // threads of the reduced-system solve
+constexpr int kWK = 8;        // rows per thread of the windowed kernel
+constexpr double kWinMargin = 2.0;  // safety factor on the decay estimate
 
 using hsgn::InstDesc;
 using hsgn::StageArgs;
 using hsgn::TileDesc;
+using hsgn::WinDesc;
 
 struct GraphEntry {
   int block;
@@ -71,6 +77,22 @@ struct hsgn_ctx {
          *d_rx = nullptr, *d_scp = nullptr, *d_sy = nullptr, *d_sv = nullptr, *d_sw = nullptr;
   std::vector<GraphEntry> graphs;
   std::string err;
+  // host copy of the full two-pass tiling (all instances)
+  std::vector<TileDesc> h_tiles_all;
+  std::vector<int32_t> h_ntiles;
+  // execution plan (rebuilt by hsgn_set_state / hsgn_set_solver)
+  int32_t solver = HSGN_SOLVER_AUTO;
+  int win_nt = 512;
+  std::vector<double> h_smax, h_hmax;  // speed bound and depth maximum of the loaded state
+  std::vector<int32_t> h_mode;         // per instance: 0 window, 1 two-pass
+  std::vector<int32_t> h_halo;         // per instance window halo L (0 if none)
+  TileDesc* d_ex_tiles = nullptr;
+  TileDesc* d_ex_tiles_multi = nullptr;
+  int32_t* d_ex_multi = nullptr;
+  WinDesc* d_win = nullptr;
+  int n_ex_tiles = 0, n_ex_tiles_multi = 0, n_ex_multi = 0, nwin = 0;
+  size_t cap_ex_tiles = 0, cap_ex_tiles_multi = 0, cap_ex_multi = 0, cap_win = 0;
+  unsigned long long* d_hmax = nullptr;
 };
 
 namespace {
@@ -112,7 +134,8 @@ void free_all(hsgn_ctx* c) {
   c->graphs.clear();
   void* ptrs[] = {c->d_inst, c->d_tiles_all, c->d_tiles_multi, c->d_multi, c->d_b,
                   c->d_dt, c->d_t, c->d_smax, c->d_umax, c->d_status, c->d_rlo, c->d_rdi,
-                  c->d_rup, c->d_rrhs, c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw};
+                  c->d_rup, c->d_rrhs, c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw,
+                  c->d_ex_tiles, c->d_ex_tiles_multi, c->d_ex_multi, c->d_win, c->d_hmax};
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (int i = 0; i < 3; ++i)
@@ -197,23 +220,52 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
   mark(HSGN_K_DT, false);
   for (int stage = 1; stage <= 2; ++stage) {
     StageArgs a = stage_args(c, stage);
-    if (c->any_multi) {
-      a.tiles = c->d_tiles_multi;
+    if (c->n_ex_multi > 0) {
+      a.tiles = c->d_ex_tiles_multi;
       mark(stage == 1 ? HSGN_K_REDUCE1 : HSGN_K_REDUCE2, true);
-      if (stage == 1) launch_stage_any<1>(c, a, c->ntiles_multi, true);
-      else launch_stage_any<2>(c, a, c->ntiles_multi, true);
+      if (stage == 1) launch_stage_any<1>(c, a, c->n_ex_tiles_multi, true);
+      else launch_stage_any<2>(c, a, c->n_ex_tiles_multi, true);
       mark(stage == 1 ? HSGN_K_REDUCE1 : HSGN_K_REDUCE2, false);
       mark(stage == 1 ? HSGN_K_RSOLVE1 : HSGN_K_RSOLVE2, true);
-      hipLaunchKernelGGL(hsgn::k_rsolve<kNTR>, dim3(c->n_multi_inst), dim3(kNTR), 0, c->stream,
-                         c->d_inst, c->d_multi, c->d_dt, c->d_rlo, c->d_rdi, c->d_rup, c->d_rrhs,
-                         c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw);
+      hipLaunchKernelGGL(hsgn::k_rsolve<kNTR>, dim3(c->n_ex_multi), dim3(kNTR), 0, c->stream,
+                         c->d_inst, c->d_ex_multi, c->d_dt, c->d_rlo, c->d_rdi, c->d_rup,
+                         c->d_rrhs, c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw);
       mark(stage == 1 ? HSGN_K_RSOLVE1 : HSGN_K_RSOLVE2, false);
     }
-    a.tiles = c->d_tiles_all;
-    mark(stage == 1 ? HSGN_K_STAGE1 : HSGN_K_STAGE2, true);
-    if (stage == 1) launch_stage_any<1>(c, a, c->ntiles_all, false);
-    else launch_stage_any<2>(c, a, c->ntiles_all, false);
-    mark(stage == 1 ? HSGN_K_STAGE1 : HSGN_K_STAGE2, false);
+    if (c->n_ex_tiles > 0) {
+      a.tiles = c->d_ex_tiles;
+      mark(stage == 1 ? HSGN_K_STAGE1 : HSGN_K_STAGE2, true);
+      if (stage == 1) launch_stage_any<1>(c, a, c->n_ex_tiles, false);
+      else launch_stage_any<2>(c, a, c->n_ex_tiles, false);
+      mark(stage == 1 ? HSGN_K_STAGE1 : HSGN_K_STAGE2, false);
+    }
+    if (c->nwin > 0) {
+      hsgn::WinArgs w;
+      w.s = a;
+      w.win = c->d_win;
+      w.nwin = c->nwin;
+      w.xcd_stride = (c->nwin + 7) / 8;
+      const int grid = 8 * w.xcd_stride;
+      mark(stage == 1 ? HSGN_K_WIN1 : HSGN_K_WIN2, true);
+      if (c->win_nt == 512) {
+        if (c->any_b) {
+          if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<512, kWK, true, 1>), dim3(grid), dim3(512), 0, c->stream, w);
+          else hipLaunchKernelGGL((hsgn::k_win<512, kWK, true, 2>), dim3(grid), dim3(512), 0, c->stream, w);
+        } else {
+          if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<512, kWK, false, 1>), dim3(grid), dim3(512), 0, c->stream, w);
+          else hipLaunchKernelGGL((hsgn::k_win<512, kWK, false, 2>), dim3(grid), dim3(512), 0, c->stream, w);
+        }
+      } else {
+        if (c->any_b) {
+          if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<256, kWK, true, 1>), dim3(grid), dim3(256), 0, c->stream, w);
+          else hipLaunchKernelGGL((hsgn::k_win<256, kWK, true, 2>), dim3(grid), dim3(256), 0, c->stream, w);
+        } else {
+          if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<256, kWK, false, 1>), dim3(grid), dim3(256), 0, c->stream, w);
+          else hipLaunchKernelGGL((hsgn::k_win<256, kWK, false, 2>), dim3(grid), dim3(256), 0, c->stream, w);
+        }
+      }
+      mark(stage == 1 ? HSGN_K_WIN1 : HSGN_K_WIN2, false);
+    }
   }
   HIPCHK(c, hipGetLastError());
   const int old = c->cur;
@@ -222,11 +274,145 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
   return HSGN_OK;
 }
 
+
+// Halo width (window rows beyond the core on a truncated side) for one
+// instance: the depth system behaves like I + r beta (second difference),
+// whose inverse decays per cell by rho = q - sqrt(q^2 - 1), q = 1 + 1/(2 r beta);
+// r beta is estimated from the loaded state at rest-state beta
+// (g h + (2 lambda / 3) / beta_1) at the deepest cell, times a margin.  The
+// halo makes rho^L <= 2^-60.  The kernel verifies the truncation on every
+// tile and flags the instance if it is not negligible.
+int halo_width(const hsgn_params& p, double smax, double hmax) {
+  const double dt = p.dt_fixed > 0 ? p.dt_fixed : p.cfl * p.dx / smax;
+  const double tau = hsgn::kGamma * dt;
+  const double b1 = 1.0 + p.lambda * tau * tau / (hmax * hmax);
+  const double beta = p.g * hmax + (2.0 * p.lambda / 3.0) / b1;
+  const double R = kWinMargin * (tau / p.dx) * (tau / p.dx) * beta;
+  if (!(R > 0.0) || !std::isfinite(R)) return 1 << 30;
+  const double q = 1.0 + 0.5 / R;
+  const double rho = q - std::sqrt(q * q - 1.0);
+  double L = 60.0 * std::log(2.0) / (-std::log(rho));
+  if (!(L < 1e8)) return 1 << 30;
+  int Li = (int)std::ceil(L);
+  Li = ((Li + kWK - 1) / kWK) * kWK;
+  return Li < kWK ? kWK : Li;
+}
+
+template <typename T>
+int upload(hsgn_ctx* c, T** d, size_t* cap, const std::vector<T>& h) {
+  if (h.size() > *cap) {
+    if (*d) hipFree(*d);
+    *d = nullptr;
+    *cap = 0;
+    int rc = dmalloc(c, d, h.size());
+    if (rc) return rc;
+    *cap = h.size();
+  }
+  if (!h.empty())
+    HIPCHK(c, hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  return HSGN_OK;
+}
+
+// Decide per instance between the windowed single pass and the exact
+// two-pass solve, and build the launch lists.
+int make_plan(hsgn_ctx* c) {
+  std::vector<TileDesc> ex_all, ex_multi;
+  std::vector<int32_t> ex_inst;
+  std::vector<WinDesc> win;
+  const int WN = c->win_nt * kWK;
+  const int Lmax = WN / 4;
+  c->h_mode.assign(c->n_inst, 1);
+  c->h_halo.assign(c->n_inst, 0);
+  size_t tpos = 0;
+  for (int j = 0; j < c->n_inst; ++j) {
+    const int n = (int)(c->offsets[j + 1] - c->offsets[j]);
+    const hsgn_params& p = c->params[j];
+    const int nt = c->h_ntiles[j];
+    bool use_win = false;
+    std::vector<WinDesc> wj;
+    if (c->solver != HSGN_SOLVER_EXACT && !c->h_smax.empty() && c->h_smax[j] > 0 &&
+        c->h_hmax[j] > 0) {
+      const int L = halo_width(p, c->h_smax[j], c->h_hmax[j]);
+      auto add = [&](int ws, int wl, int cs, int cl, int flags) {
+        WinDesc d;
+        d.inst = j; d.ws = ws; d.wl = wl; d.cs = cs; d.cl = cl; d.flags = flags;
+        wj.push_back(d);
+      };
+      if (p.bc != 0) {  // transmissive
+        if (n <= WN) {
+          add(0, n, 0, n, 0);
+          use_win = true;
+        } else if (L <= Lmax) {
+          if (n <= 2 * WN - 2 * L) {
+            add(0, WN, 0, n / 2, 2);
+            add(n - WN, WN, n / 2, n - n / 2, 1);
+          } else {
+            add(0, WN, 0, WN - L, 2);
+            const int M = n - 2 * WN + 2 * L;
+            const int C = WN - 2 * L - kWK;
+            const int nm = (M + C - 1) / C;
+            for (int k = 0; k < nm; ++k) {
+              const int cs = (WN - L) + (int)((int64_t)k * M / nm);
+              const int ce = (WN - L) + (int)((int64_t)(k + 1) * M / nm);
+              const int ws = cs - L;
+              const int wl = ((ce + L - ws + kWK - 1) / kWK) * kWK;
+              add(ws, wl, cs, ce - cs, 3);
+            }
+            add(n - WN, WN, n - WN + L, WN - L, 1);
+          }
+          use_win = true;
+        }
+      } else {  // periodic
+        if (n + 2 * L <= WN) {
+          add(-((WN - n) / 2), WN, 0, n, 3);
+          use_win = true;
+        } else if (L <= Lmax) {
+          const int C = WN - 2 * L - kWK;
+          const int ntw = (n + C - 1) / C;
+          for (int k = 0; k < ntw; ++k) {
+            const int cs = (int)((int64_t)k * n / ntw);
+            const int ce = (int)((int64_t)(k + 1) * n / ntw);
+            const int wl = ((ce - cs + 2 * L + kWK - 1) / kWK) * kWK;
+            add(cs - L, wl, cs, ce - cs, 3);
+          }
+          use_win = true;
+        }
+      }
+      if (use_win) c->h_halo[j] = L;
+    }
+    if (use_win) {
+      c->h_mode[j] = 0;
+      win.insert(win.end(), wj.begin(), wj.end());
+    } else {
+      for (int k = 0; k < nt; ++k) {
+        ex_all.push_back(c->h_tiles_all[tpos + k]);
+        if (nt > 1) ex_multi.push_back(c->h_tiles_all[tpos + k]);
+      }
+      if (nt > 1) ex_inst.push_back(j);
+    }
+    tpos += nt;
+  }
+  int rc = upload(c, &c->d_ex_tiles, &c->cap_ex_tiles, ex_all);
+  if (!rc) rc = upload(c, &c->d_ex_tiles_multi, &c->cap_ex_tiles_multi, ex_multi);
+  if (!rc) rc = upload(c, &c->d_ex_multi, &c->cap_ex_multi, ex_inst);
+  if (!rc) rc = upload(c, &c->d_win, &c->cap_win, win);
+  if (rc) return rc;
+  c->n_ex_tiles = (int)ex_all.size();
+  c->n_ex_tiles_multi = (int)ex_multi.size();
+  c->n_ex_multi = (int)ex_inst.size();
+  c->nwin = (int)win.size();
+  // uploads read host vectors that die here
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+  return HSGN_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char* hsgn_version(void) { return "hsgn-gfx950 0.1"; }
+const char* hsgn_version(void) { return "hsgn-gfx950 0.2"; }
 
 int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn_params* params,
               const double* d_b, void* hip_stream) {
@@ -289,6 +475,9 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
     c->ncell += n;
   }
   if (rc == HSGN_OK && red > INT32_MAX) rc = fail(c, HSGN_EINVAL, "reduced system too large");
+  c->h_tiles_all = tall;
+  c->h_ntiles.resize(n_inst);
+  for (int j = 0; j < n_inst && rc == HSGN_OK; ++j) c->h_ntiles[j] = inst[j].ntiles;
   c->ntiles_all = (int)tall.size();
   c->ntiles_multi = (int)tmulti.size();
   c->n_multi_inst = (int)multi.size();
@@ -320,6 +509,7 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_t, (size_t)n_inst);
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_smax, (size_t)n_inst);
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_umax, (size_t)n_inst);
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_hmax, (size_t)n_inst);
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_status, (size_t)n_inst);
   double** rp[] = {&c->d_rlo, &c->d_rdi, &c->d_rup, &c->d_rrhs, &c->d_rx,
                    &c->d_scp, &c->d_sy, &c->d_sv, &c->d_sw};
@@ -358,6 +548,7 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   // host vectors are freed on return: wait for the uploads
   if (rc == HSGN_OK && hipStreamSynchronize(c->stream) != hipSuccess)
     rc = fail(c, HSGN_EHIP, "hipStreamSynchronize failed");
+  if (rc == HSGN_OK) rc = make_plan(c);  // no state yet: every instance two-pass
   if (rc == HSGN_OK) rc = leave(c);
   if (rc != HSGN_OK) {
     fprintf(stderr, "hsgn_init: %s\n", c->err.c_str());
@@ -399,9 +590,26 @@ int hsgn_set_state(hsgn_ctx* c, const double* d_h, const double* d_q, const doub
                      0ull);
   hipLaunchKernelGGL(hsgn::k_fill_u64, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_umax,
                      0ull);
+  hipLaunchKernelGGL(hsgn::k_fill_u64, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_hmax,
+                     0ull);
   hipLaunchKernelGGL(hsgn::k_speed<256>, dim3(c->ntiles_all), dim3(256), 0, c->stream, c->d_inst,
-                     c->d_tiles_all, U[0], U[1], c->d_smax, c->d_umax);
+                     c->d_tiles_all, U[0], U[1], c->d_smax, c->d_umax, c->d_hmax);
   HIPCHK(c, hipGetLastError());
+  // plan the solve from this state's speed bound and depth maximum
+  std::vector<unsigned long long> sm(c->n_inst), hm(c->n_inst);
+  HIPCHK(c, hipMemcpyAsync(sm.data(), c->d_smax, c->n_inst * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(hm.data(), c->d_hmax, c->n_inst * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->h_smax.resize(c->n_inst);
+  c->h_hmax.resize(c->n_inst);
+  for (int j = 0; j < c->n_inst; ++j) {
+    std::memcpy(&c->h_smax[j], &sm[j], sizeof(double));
+    std::memcpy(&c->h_hmax[j], &hm[j], sizeof(double));
+  }
+  rc = make_plan(c);
+  if (rc) return rc;
   return leave(c);
 }
 
@@ -428,6 +636,32 @@ int hsgn_get_dt(hsgn_ctx* c, double* d_dt) {
   HIPCHK(c, hipMemcpyAsync(d_dt, c->d_dt, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice,
                            c->stream));
   return leave(c);
+}
+
+int hsgn_set_solver(hsgn_ctx* c, int32_t mode) {
+  if (!c) return HSGN_EINVAL;
+  if (mode != HSGN_SOLVER_AUTO && mode != HSGN_SOLVER_EXACT && mode != HSGN_SOLVER_AUTO_SMALL)
+    return fail(c, HSGN_EINVAL, "hsgn_set_solver: unknown mode %d", mode);
+  c->solver = mode == HSGN_SOLVER_AUTO_SMALL ? HSGN_SOLVER_AUTO : mode;
+  c->win_nt = mode == HSGN_SOLVER_AUTO_SMALL ? 256 : 512;
+  int rc = enter(c);
+  if (rc) return rc;
+  rc = make_plan(c);
+  if (rc) return rc;
+  return leave(c);
+}
+
+int hsgn_plan_info(hsgn_ctx* c, int32_t* h_mode, int32_t* h_halo, int32_t* h_counts) {
+  if (!c) return HSGN_EINVAL;
+  if (h_mode) std::memcpy(h_mode, c->h_mode.data(), c->n_inst * sizeof(int32_t));
+  if (h_halo) std::memcpy(h_halo, c->h_halo.data(), c->n_inst * sizeof(int32_t));
+  if (h_counts) {
+    h_counts[0] = c->nwin;
+    h_counts[1] = c->n_ex_tiles;
+    h_counts[2] = c->n_ex_multi;
+    h_counts[3] = c->win_nt * kWK;
+  }
+  return HSGN_OK;
 }
 
 int hsgn_step(hsgn_ctx* c, int32_t nsteps) {
@@ -512,6 +746,12 @@ int hsgn_status(hsgn_ctx* c, int32_t* h_flags) {
   if (any & hsgn::kFlagNonPhys) {
     for (int j = 0; j < c->n_inst; ++j)
       if (f[j] & hsgn::kFlagNonPhys) return fail(c, HSGN_ENONPHYS, "instance %d: h <= 0 or non-finite value", j);
+  }
+  if (any & hsgn::kFlagWindow) {
+    for (int j = 0; j < c->n_inst; ++j)
+      if (f[j] & hsgn::kFlagWindow)
+        return fail(c, HSGN_EWINDOW,
+                    "instance %d: window truncation not negligible; use HSGN_SOLVER_EXACT", j);
   }
   if (any & hsgn::kFlagNonCoercive) {
     for (int j = 0; j < c->n_inst; ++j)

@@ -863,25 +863,29 @@ __global__ __launch_bounds__(NT) void k_speed(const InstDesc* __restrict__ inst,
                                               const double* __restrict__ h,
                                               const double* __restrict__ q,
                                               unsigned long long* __restrict__ smax,
-                                              unsigned long long* __restrict__ umax) {
+                                              unsigned long long* __restrict__ umax,
+                                              unsigned long long* __restrict__ hmax) {
   const TileDesc td = tiles[blockIdx.x];
   const InstDesc I = inst[td.inst];
-  double s = 0.0, u = 0.0;
+  double s = 0.0, u = 0.0, hx = 0.0;
   for (int i = threadIdx.x; i < td.len; i += NT) {
     const int64_t gi = I.off + td.start + i;
     const double hh = h[gi];
     const double uu = fabs(q[gi] / hh);
     s = fmax(s, uu + sqrt(I.g * hh));
     u = fmax(u, uu);
+    hx = fmax(hx, hh);
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     s = fmax(s, __shfl_xor(s, off));
     u = fmax(u, __shfl_xor(u, off));
+    hx = fmax(hx, __shfl_xor(hx, off));
   }
   if ((threadIdx.x & 63) == 0 && s > 0.0) {
     atomicMax(&smax[td.inst], (unsigned long long)__double_as_longlong(s));
     atomicMax(&umax[td.inst], (unsigned long long)__double_as_longlong(u));
+    atomicMax(&hmax[td.inst], (unsigned long long)__double_as_longlong(hx));
   }
 }
 

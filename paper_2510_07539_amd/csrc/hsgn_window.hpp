@@ -1,0 +1,644 @@
+// hsgn_window.hpp -- single-pass windowed stage kernel.
+//
+// A tile writes the cells of its core [cs, cs + cl) but solves the depth
+// system on a window that extends the core by L cells on every side that is
+// not a physical boundary.  Beyond a window edge that is not physical the
+// unknown depth is replaced by the explicit-stage depth h_E (its coupling
+// moves to the right-hand side).  The system is diagonally dominant, so the
+// influence of that replacement on the core decays geometrically with the
+// distance L; the kernel computes that influence exactly at both core edges
+// (from the spike columns of the window solve) and flags the instance
+// (status bit 4) if the resulting bound exceeds 2^-56 of the local depth.
+// Instances that fit in one window are solved exactly (no truncation).
+//
+// Each of the NT threads owns exactly K consecutive window rows (K is a
+// compile-time constant); rows past the window's real length are identity
+// rows, decoupled from the rest.  Inputs are staged through LDS with
+// coalesced loads.  Everything else (sweep, rows, solve) is the same
+// arithmetic as the two-pass kernel in hsgn_kernels.hpp.
+#pragma once
+
+#include "hsgn_kernels.hpp"
+
+namespace hsgn {
+
+constexpr int32_t kFlagWindow = 4;
+
+struct WinDesc {
+  int32_t inst;
+  int32_t ws;     // window start, relative to the instance (may be < 0 if periodic)
+  int32_t wl;     // real rows of the window (<= NT*K)
+  int32_t cs;     // core start (relative to the instance, in [0, n))
+  int32_t cl;     // core length
+  int32_t flags;  // bit 0: left edge truncated; bit 1: right edge truncated
+};
+
+struct WinArgs {
+  StageArgs s;
+  const WinDesc* __restrict__ win;
+  int32_t nwin;
+  int32_t xcd_stride;  // consecutive windows go to one XCD: see k_win
+};
+
+// Fast reciprocal: hardware estimate and two Newton steps (error of a few
+// ulp at most for the normal, finite operands that reach it).
+__device__ __forceinline__ double frcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(e, r, r);
+  e = fma(-x, r, 1.0);
+  r = fma(e, r, r);
+  return r;
+}
+
+template <bool BED>
+__device__ __forceinline__ Flux face_flux_fast(const Cell& cm, const Cell& c0, const Cell& c1,
+                                               const Cell& c2, double bm, double b0, double b1,
+                                               double b2, double g, bool& bad) {
+  const double hL = c0.h + 0.25 * (c1.h - cm.h);
+  const double hR = c1.h - 0.25 * (c2.h - c0.h);
+  const double qL = c0.q + 0.25 * (c1.q - cm.q);
+  const double qR = c1.q - 0.25 * (c2.q - c0.q);
+  const double mL = c0.m + 0.25 * (c1.m - cm.m);
+  const double mR = c1.m - 0.25 * (c2.m - c0.m);
+  const double WL = c0.W + 0.25 * (c1.W - cm.W);
+  const double WR = c1.W - 0.25 * (c2.W - c0.W);
+  bad |= !(hL > 0.0) || !(hR > 0.0);
+  const double uL = qL * frcp(hL);
+  const double uR = qR * frcp(hR);
+  const double sL = fabs(uL) + sqrt(g * hL);
+  const double sR = fabs(uR) + sqrt(g * hR);
+  const double a = fmax(sL, sR);
+  double jm = mR - mL;
+  if (BED) {
+    const double zf = 0.5 * ((c0.h + b0) + (c1.h + b1));
+    const double rm = (zf - bm) * (zf - bm);
+    const double r0 = (zf - b0) * (zf - b0);
+    const double r1 = (zf - b1) * (zf - b1);
+    const double r2 = (zf - b2) * (zf - b2);
+    const double mhL = r0 + 0.25 * (r1 - rm);
+    const double mhR = r1 - 0.25 * (r2 - r0);
+    jm = jm - (mhR - mhL);
+  }
+  Flux F;
+  F.q = 0.5 * (qL * uL + qR * uR - a * (qR - qL));
+  F.m = 0.5 * (mL * uL + mR * uR - a * jm);
+  F.W = 0.5 * (WL * uL + WR * uR - a * (WR - WL));
+  return F;
+}
+
+template <bool BED>
+__device__ __forceinline__ Rec cell_record_fast(const Cell& e, const Cell& o, const Flux& Fl,
+                                                const Flux& Fr, double bm, double bc, double bp,
+                                                const PhysC& P, double i2dx, bool& bad,
+                                                bool& noncoer) {
+  Rec r;
+  r.Wd = o.W - P.tdx * (Fr.W - Fl.W) + P.lam * P.tau;
+  double md = o.m - P.tdx * (Fr.m - Fl.m);
+  if (BED) md -= P.tau * 1.5 * e.q * ((bp - bm) * i2dx);
+  md += P.tau * r.Wd;
+  r.md = md;
+  r.qd = o.q - P.tdx * (Fr.q - Fl.q);
+  const double h = e.h;
+  bad |= !(h > 0.0);
+  const double ih = frcp(h);
+  const double eh = e.m * ih * ih;
+  const double alpha = -(2.0 * eh - 1.0) * ih * (1.0 / 3.0);
+  const double a2 = P.g * h + P.lam * eh * eh - (P.lam / 3.0) * eh;
+  const double b1 = 1.0 + P.lt2 * ih * ih;
+  const double ib1 = frcp(b1);
+  const double b2 = 2.0 * P.lt2 * ib1 * ib1 * ih * ih * ih;
+  r.beta = a2 + P.lam * alpha * b2 * md;
+  noncoer |= !(r.beta > 0.0);
+  const double eta0 = md * ib1 * ih;
+  const double pt0 = (P.lam / 3.0) * (1.0 - eta0 * ih);
+  const double P0 = 0.5 * P.g * h * h + eta0 * pt0;
+  r.S = P0 - r.beta * h;
+  if (BED) {
+    r.phi = (2.0 * P.lam / 3.0) * md * ih * ih * ih * ib1 * ib1;
+    r.T = pt0 - r.phi * h;
+  } else {
+    r.phi = 0.0;
+    r.T = 0.0;
+  }
+  r.b = bc;
+  return r;
+}
+
+// Level-1 interior solve with one reciprocal per row and level.
+template <int NT>
+__device__ void level1_interior_fast(Lds<NT>& S, int n1) {
+  const int t = threadIdx.x;
+  const int last = n1 - 2;
+  const int m = n1 - 2;
+  if (m <= 0) return;
+  if (t == 0) {
+    S.d1[1] = -S.a[1];
+    S.a[1] = 0.0;
+    S.d2[last] = -S.c[last];
+    S.c[last] = 0.0;
+  }
+  __syncthreads();
+  for (int s = 1; s < m; s <<= 1) {
+    double na[2], nb[2], nc[2], n0[2], n1v[2], n2[2];
+    bool own[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int j = 1 + t + r * NT;
+      own[r] = j <= last;
+      if (own[r]) {
+        const int jm = j - s, jp = j + s;
+        const bool hm = jm >= 1, hp = jp <= last;
+        const double a = S.a[j], c = S.c[j];
+        const double k1 = hm ? a * frcp(S.b[jm]) : 0.0;
+        const double k2 = hp ? c * frcp(S.b[jp]) : 0.0;
+        na[r] = hm ? -k1 * S.a[jm] : 0.0;
+        nc[r] = hp ? -k2 * S.c[jp] : 0.0;
+        double bb = S.b[j];
+        double e0 = S.d0[j], e1 = S.d1[j], e2 = S.d2[j];
+        if (hm) {
+          bb -= k1 * S.c[jm];
+          e0 -= k1 * S.d0[jm];
+          e1 -= k1 * S.d1[jm];
+          e2 -= k1 * S.d2[jm];
+        }
+        if (hp) {
+          bb -= k2 * S.a[jp];
+          e0 -= k2 * S.d0[jp];
+          e1 -= k2 * S.d1[jp];
+          e2 -= k2 * S.d2[jp];
+        }
+        nb[r] = bb;
+        n0[r] = e0;
+        n1v[r] = e1;
+        n2[r] = e2;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int j = 1 + t + r * NT;
+      if (own[r]) {
+        S.a[j] = na[r];
+        S.b[j] = nb[r];
+        S.c[j] = nc[r];
+        S.d0[j] = n0[r];
+        S.d1[j] = n1v[r];
+        S.d2[j] = n2[r];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int j = 1 + t + r * NT;
+    if (j <= last) {
+      const double ib = frcp(S.b[j]);
+      S.d0[j] *= ib;
+      S.d1[j] *= ib;
+      S.d2[j] *= ib;
+    }
+  }
+  __syncthreads();
+}
+
+// LDS layout of a staged window field: one pad double after every 8 so that
+// a thread reading its K consecutive values does not collide on banks.
+__device__ __forceinline__ int spad(int i) { return i + (i >> 3); }
+
+// Cell index of instance-relative position i for any i (a periodic window
+// may be longer than the ring).
+__device__ __forceinline__ int wrap_any(int i, int n, int bc) {
+  if (bc == 0) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+  }
+  return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+}
+
+template <int NT, int K>
+struct WinLds {
+  static constexpr int WN = NT * K;
+  static constexpr int SL = WN + 8;              // staged cells: window + 3 halo each side (+2)
+  static constexpr int SP = SL + (SL >> 3) + 1;  // padded length
+  union {
+    struct {
+      double e[SP];   // staged explicit-state field (window + halo)
+      double o[SP];   // staged old-state field (stage 2)
+    } st;
+    Lds<NT> sys;
+    struct {
+      double beta[2][NT], S[2][NT], qd[2][NT], phi[2][NT], T[2][NT], b[2][NT];
+    } nb;
+  } u;
+  double misc[16];
+};
+
+template <int NT, int K, bool BED, int STAGE>
+__global__ __launch_bounds__(NT) void k_win(WinArgs W) {
+  __shared__ WinLds<NT, K> L;
+  const StageArgs& A = W.s;
+  // consecutive windows of an instance run on the same XCD (blocks are
+  // dealt round-robin over the 8 XCDs)
+  int bid = blockIdx.x;
+  if (W.xcd_stride > 0) {
+    const int x = bid & 7, r = bid >> 3;
+    bid = x * W.xcd_stride + r;
+  }
+  if (bid >= W.nwin) return;
+  const WinDesc wd = W.win[bid];
+  const InstDesc I = A.inst[wd.inst];
+  const double dt = A.dt[wd.inst];
+  const int t = threadIdx.x;
+  const int n = I.n, bc = I.bc;
+  const int64_t base = I.off;
+  constexpr int WN = NT * K;
+  const int na = (wd.wl + K - 1) / K;  // threads with real rows
+  const bool act = t < na;
+  const int p0 = t * K;                 // first window row of this thread
+  const bool truncL = (wd.flags & 1) != 0, truncR = (wd.flags & 2) != 0;
+  const bool physL = !truncL, physR = !truncR;
+
+  if (!(dt > 0.0)) {  // frozen: copy the core
+    for (int i = t; i < wd.cl; i += NT) {
+      const int64_t gi = base + wd.cs + i;
+      A.o_h[gi] = A.un_h[gi];
+      A.o_q[gi] = A.un_q[gi];
+      A.o_m[gi] = A.un_m[gi];
+      A.o_W[gi] = A.un_W[gi];
+    }
+    return;
+  }
+  PhysC P;
+  P.g = I.g;
+  P.lam = I.lam;
+  P.dx = I.dx;
+  P.tau = kGamma * dt;
+  P.tdx = P.tau / P.dx;
+  P.lt2 = P.lam * P.tau * P.tau;
+  P.rr = P.tdx * P.tdx;
+  P.tdx2 = 0.5 * P.tdx;
+  const double i2dx = 0.5 / P.dx;
+  const bool useb = BED && I.has_b;
+  bool bad = false, noncoer = false;
+
+  // ---- staging: window rows [ws, ws+wl) plus 3 halo cells each side.
+  // Staged index i <-> window row i - 3.  Rows past the window's real end
+  // repeat row wl + 2 (their values only feed identity padding rows).
+  if (t == 0) {
+    L.misc[0] = 0.0;  // depth guesses beyond truncated edges (0 if physical)
+    L.misc[1] = 0.0;
+  }
+  const int SLn = na * K + 6;
+  auto cell_of = [&](int i) -> int {  // instance cell of staged index i
+    int p = i - 3;
+    if (p > wd.wl + 2) p = wd.wl + 2;
+    return wrap_any(wd.ws + p, n, bc);
+  };
+  // per-thread registers: explicit state at rows p0-3 .. p0+K+2 (K+6)
+  Cell E[K + 6];
+  double Bv[K + 6];
+  Cell O[K];
+#pragma unroll
+  for (int f = 0; f < 5; ++f) {
+    if (f == 4 && !useb) break;
+    for (int i = t; i < SLn; i += NT) {
+      const int64_t gi = base + cell_of(i);
+      double ev, ov = 0.0;
+      if (f == 4) {
+        ev = A.b[gi];
+      } else {
+        const double* un = f == 0 ? A.un_h : f == 1 ? A.un_q : f == 2 ? A.un_m : A.un_W;
+        if (STAGE == 1) {
+          ev = un[gi];
+        } else {
+          const double* u1 = f == 0 ? A.u1_h : f == 1 ? A.u1_q : f == 2 ? A.u1_m : A.u1_W;
+          const double a = un[gi], b = u1[gi];
+          ev = kE0 * a + kE1 * b;
+          ov = kT0 * a + kT1 * b;
+        }
+      }
+      L.u.st.e[spad(i)] = ev;
+      if (STAGE == 2) L.u.st.o[spad(i)] = ov;
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int j = 0; j < K + 6; ++j) {
+        const double v = L.u.st.e[spad(p0 + j)];
+        if (f == 0) E[j].h = v;
+        else if (f == 1) E[j].q = v;
+        else if (f == 2) E[j].m = v;
+        else if (f == 3) E[j].W = v;
+        else Bv[j] = v;
+      }
+      if (f < 4) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+          const double v = STAGE == 1 ? L.u.st.e[spad(p0 + 3 + j)] : L.u.st.o[spad(p0 + 3 + j)];
+          if (f == 0) O[j].h = v;
+          else if (f == 1) O[j].q = v;
+          else if (f == 2) O[j].m = v;
+          else O[j].W = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!useb) {
+#pragma unroll
+    for (int j = 0; j < K + 6; ++j) Bv[j] = 0.0;
+  }
+  // E[j] <-> window row p0 + j - 3; own rows are E[3..K+2]
+
+  // ---- sweep: records of own rows, plus the outer neighbour rows for the
+  // first and last active thread (needed by the edge rows).
+  Rec rec[K];
+  Rec recL, recR;
+  if (act) {
+    bool fb = false;
+    Flux Fl = face_flux_fast<BED>(E[1], E[2], E[3], E[4], Bv[1], Bv[2], Bv[3], Bv[4], P.g, fb);
+    bad |= fb;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      bool bj = false, nj = false;  // flags of padding rows are dropped
+      const Flux Fr = face_flux_fast<BED>(E[j + 2], E[j + 3], E[j + 4], E[j + 5], Bv[j + 2],
+                                          Bv[j + 3], Bv[j + 4], Bv[j + 5], P.g, bj);
+      rec[j] = cell_record_fast<BED>(E[j + 3], O[j], Fl, Fr, Bv[j + 2], Bv[j + 3], Bv[j + 4], P,
+                                     i2dx, bj, nj);
+      if (p0 + j < wd.wl) {
+        bad |= bj;
+        noncoer |= nj;
+      }
+      Fl = Fr;
+    }
+  }
+  // outer neighbours (row -1 and row wl); their old state comes from global
+  if (act && t == 0) {
+    if (physL) {
+      recL = rec[0];
+    } else {
+      const Flux Fa = face_flux_fast<BED>(E[0], E[1], E[2], E[3], Bv[0], Bv[1], Bv[2], Bv[3],
+                                          P.g, bad);
+      const Flux Fb = face_flux_fast<BED>(E[1], E[2], E[3], E[4], Bv[1], Bv[2], Bv[3], Bv[4],
+                                          P.g, bad);
+      const int64_t gi = base + wrap_any(wd.ws - 1, n, bc);
+      const Cell o = STAGE == 1 ? load_old<1>(A, gi) : load_old<2>(A, gi);
+      recL = cell_record_fast<BED>(E[2], o, Fa, Fb, Bv[1], Bv[2], Bv[3], P, i2dx, bad, noncoer);
+      L.misc[0] = E[2].h;  // depth guess beyond the left edge
+    }
+  }
+  if (act && t == na - 1) {
+    const int jl = wd.wl - 1 - p0;  // last real row in this thread (0..K-1)
+    Rec last = rec[0];
+    Cell e2 = E[0], e3 = E[0], e4 = E[0], e5 = E[0], e6 = E[0];
+    double b2 = 0, b3 = 0, b4 = 0, b5 = 0, b6 = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      if (j == jl) {
+        last = rec[j];
+        e2 = E[j + 2]; e3 = E[j + 3]; e4 = E[j + 4]; e5 = E[j + 5]; e6 = E[j + 6 < K + 6 ? j + 6 : K + 5];
+        b2 = Bv[j + 2]; b3 = Bv[j + 3]; b4 = Bv[j + 4]; b5 = Bv[j + 5]; b6 = Bv[j + 6 < K + 6 ? j + 6 : K + 5];
+      }
+    }
+    if (physR) {
+      recR = last;
+    } else {
+      // row wl: faces between rows wl-1|wl and wl|wl+1
+      const Flux Fa = face_flux_fast<BED>(e2, e3, e4, e5, b2, b3, b4, b5, P.g, bad);
+      const Flux Fb = face_flux_fast<BED>(e3, e4, e5, e6, b3, b4, b5, b6, P.g, bad);
+      const int64_t gi = base + wrap_any(wd.ws + wd.wl, n, bc);
+      const Cell o = STAGE == 1 ? load_old<1>(A, gi) : load_old<2>(A, gi);
+      recR = cell_record_fast<BED>(e4, o, Fa, Fb, b3, b4, b5, P, i2dx, bad, noncoer);
+      L.misc[1] = e4.h;  // depth guess beyond the right edge
+    }
+  }
+  // share chunk-end records
+  if (act) {
+    L.u.nb.beta[0][t] = rec[0].beta; L.u.nb.S[0][t] = rec[0].S; L.u.nb.qd[0][t] = rec[0].qd;
+    L.u.nb.phi[0][t] = rec[0].phi; L.u.nb.T[0][t] = rec[0].T; L.u.nb.b[0][t] = rec[0].b;
+    L.u.nb.beta[1][t] = rec[K - 1].beta; L.u.nb.S[1][t] = rec[K - 1].S;
+    L.u.nb.qd[1][t] = rec[K - 1].qd; L.u.nb.phi[1][t] = rec[K - 1].phi;
+    L.u.nb.T[1][t] = rec[K - 1].T; L.u.nb.b[1][t] = rec[K - 1].b;
+  }
+  __syncthreads();
+  if (act && t > 0) {
+    recL.beta = L.u.nb.beta[1][t - 1]; recL.S = L.u.nb.S[1][t - 1]; recL.qd = L.u.nb.qd[1][t - 1];
+    recL.phi = L.u.nb.phi[1][t - 1]; recL.T = L.u.nb.T[1][t - 1]; recL.b = L.u.nb.b[1][t - 1];
+  }
+  if (act && t < na - 1) {
+    recR.beta = L.u.nb.beta[0][t + 1]; recR.S = L.u.nb.S[0][t + 1]; recR.qd = L.u.nb.qd[0][t + 1];
+    recR.phi = L.u.nb.phi[0][t + 1]; recR.T = L.u.nb.T[0][t + 1]; recR.b = L.u.nb.b[0][t + 1];
+  }
+  const double gL = L.misc[0], gR = L.misc[1];
+  __syncthreads();  // nb region is reused by the level-1 system below
+
+  // ---- rows and chunk elimination (K rows per thread, all real or identity)
+  double cp[K], y[K], v[K], w[K];
+  double loE = 0.0, upE = 0.0;  // couplings moved to the right-hand side
+  if (act) {
+    const int jl = wd.wl - 1 - p0;  // last real row of this thread (>= K-1 if full)
+    double r0[4], rl[4];
+    double cprev = 0.0, yprev = 0.0, vprev = 1.0, wprev = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const bool real = j <= jl;
+      const Rec Lr = (j == 0) ? recL : rec[j > 0 ? j - 1 : 0];
+      const Rec Rr = (j == K - 1 || j == jl) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
+      double lo, di, up, rhs;
+      make_row<BED>(Lr, rec[j], Rr, O[j].h, P, lo, di, up, rhs);
+      if (t == 0 && j == 0) {
+        if (physL) {
+          di += lo;
+        } else {
+          loE = lo;
+          rhs -= lo * gL;
+        }
+        lo = 0.0;
+      }
+      if (t == na - 1 && j == jl) {
+        if (physR) {
+          di += up;
+        } else {
+          upE = up;
+          rhs -= up * gR;
+        }
+        up = 0.0;
+      }
+      if (!real) {
+        lo = 0.0; di = 1.0; up = 0.0; rhs = 0.0;
+      }
+      if (j == 0) {
+        r0[0] = lo; r0[1] = di; r0[2] = up; r0[3] = rhs;
+      } else if (j == K - 1) {
+        rl[0] = lo; rl[1] = di; rl[2] = up; rl[3] = rhs;
+      } else {
+        const double inv = frcp(di - lo * cprev);
+        const bool lastint = (j == K - 2);
+        cp[j] = lastint ? 0.0 : up * inv;
+        y[j] = (rhs - lo * yprev) * inv;
+        v[j] = (-lo * vprev) * inv;
+        w[j] = (-lo * wprev) * inv - (lastint ? up * inv : 0.0);
+        cprev = cp[j];
+        yprev = y[j];
+        vprev = v[j];
+        wprev = w[j];
+      }
+    }
+    double yn = 0.0, vn = 0.0, wn = 0.0;
+#pragma unroll
+    for (int j = K - 2; j >= 1; --j) {
+      y[j] = y[j] - cp[j] * yn;
+      v[j] = v[j] - cp[j] * vn;
+      w[j] = w[j] - cp[j] * wn;
+      yn = y[j];
+      vn = v[j];
+      wn = w[j];
+    }
+    double R0[4], R1[4];
+    if (K > 2) {
+      R0[0] = r0[0];
+      R0[1] = r0[1] + r0[2] * v[1];
+      R0[2] = r0[2] * w[1];
+      R0[3] = r0[3] - r0[2] * y[1];
+      R1[0] = rl[0] * v[K - 2];
+      R1[1] = rl[1] + rl[0] * w[K - 2];
+      R1[2] = rl[2];
+      R1[3] = rl[3] - rl[0] * y[K - 2];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        R0[e] = r0[e];
+        R1[e] = rl[e];
+      }
+    }
+    Lds<NT>& S = L.u.sys;
+    S.a[2 * t] = R0[0]; S.b[2 * t] = R0[1]; S.c[2 * t] = R0[2]; S.d0[2 * t] = R0[3];
+    S.d1[2 * t] = 0.0; S.d2[2 * t] = 0.0;
+    S.a[2 * t + 1] = R1[0]; S.b[2 * t + 1] = R1[1]; S.c[2 * t + 1] = R1[2];
+    S.d0[2 * t + 1] = R1[3]; S.d1[2 * t + 1] = 0.0; S.d2[2 * t + 1] = 0.0;
+    if (t == 0) L.misc[2] = loE;
+    if (t == na - 1) L.misc[3] = upE;
+  }
+  __syncthreads();
+  const int n1 = 2 * na;
+  level1_interior_fast<NT>(L.u.sys, n1);
+
+  // ---- the window's end unknowns (couplings already on the right-hand side)
+  if (t == 0) {
+    double R0[4], R1[4];
+    tile_rows<NT>(L.u.sys, n1, R0, R1);
+    const double m00 = R0[1], m01 = R0[2], m10 = R1[0], m11 = R1[1];
+    const double idet = 1.0 / (m00 * m11 - m01 * m10);
+    const double i00 = m11 * idet, i01 = -m01 * idet, i10 = -m10 * idet, i11 = m00 * idet;
+    L.misc[4] = i00 * R0[3] + i01 * R1[3];  // z0
+    L.misc[5] = i10 * R0[3] + i11 * R1[3];  // zl
+    // d(z0, zl)/d(guess): left guess enters row 0 as -loE, right as -upE
+    L.misc[6] = -L.misc[2] * i00;
+    L.misc[7] = -L.misc[2] * i10;
+    L.misc[8] = -L.misc[3] * i01;
+    L.misc[9] = -L.misc[3] * i11;
+  }
+  __syncthreads();
+  const double z0 = L.misc[4], zl = L.misc[5];
+  double zf = 0.0, zb = 0.0, Vf = 0.0, Wf = 0.0, Vb = 0.0, Wb = 0.0;
+  if (act) {
+    const Lds<NT>& S = L.u.sys;
+    const int j0 = 2 * t, j1 = 2 * t + 1;
+    if (j0 == 0) { zf = z0; Vf = 1.0; Wf = 0.0; }
+    else { zf = S.d0[j0] + S.d1[j0] * z0 + S.d2[j0] * zl; Vf = S.d1[j0]; Wf = S.d2[j0]; }
+    if (j1 == n1 - 1) { zb = zl; Vb = 0.0; Wb = 1.0; }
+    else { zb = S.d0[j1] + S.d1[j1] * z0 + S.d2[j1] * zl; Vb = S.d1[j1]; Wb = S.d2[j1]; }
+  }
+  __syncthreads();
+  if (act) {
+    L.u.sys.a[2 * t] = zf;
+    L.u.sys.a[2 * t + 1] = zb;
+  }
+  __syncthreads();
+
+  // ---- back-substitution over the core rows
+  double smax = 0.0, umax = 0.0;
+  const int c0 = wd.cs - wd.ws;    // first core row (window-relative)
+  const int c1 = c0 + wd.cl;       // one past the last core row
+  const bool has_core = act && p0 < c1 && p0 + K > c0;
+  if (has_core) {
+    const double hl_nb = (t > 0) ? L.u.sys.a[2 * t - 1] : (physL ? zf : gL);
+    const double hr_nb = (t < na - 1) ? L.u.sys.a[2 * t + 2] : (physR ? zb : gR);
+    double hb[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+      hb[j] = (j == 0) ? zf : ((j == K - 1) ? zb : y[j] + v[j] * zf + w[j] * zb);
+    const int jl = wd.wl - 1 - p0;
+    // certificate at the core's edge rows
+    if ((truncL || truncR) && ((p0 <= c0 && c0 < p0 + K) || (p0 <= c1 - 1 && c1 - 1 < p0 + K))) {
+      const double dz0L = L.misc[6], dzlL = L.misc[7], dz0R = L.misc[8], dzlR = L.misc[9];
+      const double X = 4.0 * fmax(fabs(gL), fabs(gR));
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int p = p0 + j;
+        if (p == c0 || p == c1 - 1) {
+          double s0, sl;  // d x_p / d z0, d x_p / d zl
+          if (j == 0) { s0 = Vf; sl = Wf; }
+          else if (j == K - 1) { s0 = Vb; sl = Wb; }
+          else { s0 = v[j] * Vf + w[j] * Vb; sl = v[j] * Wf + w[j] * Wb; }
+          const double sens = fabs(s0 * dz0L + sl * dzlL) + fabs(s0 * dz0R + sl * dzlR);
+          if (!(sens * X <= 1.3877787807814457e-17 * fabs(hb[j]))) {  // 2^-56
+            atomicOr(&A.status[wd.inst], kFlagWindow);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int p = p0 + j;
+      if (p >= c0 && p < c1) {
+        const Rec Lr = (j == 0) ? recL : rec[j > 0 ? j - 1 : 0];
+        const Rec Rr = (j == K - 1 || j == jl) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
+        const double hm = (j == 0) ? hl_nb : hb[j > 0 ? j - 1 : 0];
+        const double hp = (j == K - 1) ? hr_nb : ((j == jl && physR) ? hb[j] : hb[j + 1 < K ? j + 1 : K - 1]);
+        const double h = hb[j];
+        const double Pm = Lr.S + Lr.beta * hm;
+        const double Pp = Rr.S + Rr.beta * hp;
+        double force = (Pp - Pm) * i2dx;
+        if (BED) {
+          const double dbc = (Rr.b - Lr.b) * i2dx;
+          const double pti = rec[j].T + rec[j].phi * h;
+          force += 0.5 * P.g * (hp + hm) * dbc + 1.5 * pti * dbc;
+        }
+        const double qn = rec[j].qd - P.tau * force;
+        const double ih = frcp(h);
+        const double ih2 = ih * ih;
+        const double mn = rec[j].md * frcp(1.0 + P.lt2 * ih2);
+        const double Wn = rec[j].Wd - P.lam * P.tau * mn * ih2;
+        bad |= !(h > 0.0) || !isfinite(qn) || !isfinite(mn) || !isfinite(Wn);
+        const int64_t gi = base + wrap_any(wd.ws + p, n, bc);
+        A.o_h[gi] = h;
+        A.o_q[gi] = qn;
+        A.o_m[gi] = mn;
+        A.o_W[gi] = Wn;
+        if (STAGE == 2) {
+          const double u = fabs(qn * ih);
+          smax = fmax(smax, u + sqrt(P.g * h));
+          umax = fmax(umax, u);
+        }
+      }
+    }
+  }
+  if (STAGE == 2) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      smax = fmax(smax, __shfl_xor(smax, off));
+      umax = fmax(umax, __shfl_xor(umax, off));
+    }
+    if ((t & 63) == 0 && smax > 0.0) {
+      atomicMax(&A.smax[wd.inst], (unsigned long long)__double_as_longlong(smax));
+      atomicMax(&A.umax[wd.inst], (unsigned long long)__double_as_longlong(umax));
+    }
+  }
+  if (bad || noncoer) {
+    atomicOr(&A.status[wd.inst], (bad ? kFlagNonPhys : 0) | (noncoer ? kFlagNonCoercive : 0));
+  }
+}
+
+}  // namespace hsgn

@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(HERE, "libhsgn.so")
 
 HSGN_OK, HSGN_EINVAL, HSGN_EHIP, HSGN_ENONPHYS, HSGN_ENONCOERCIVE, HSGN_ENOMEM = 0, -1, -2, -3, -4, -5
 FLAG_NONPHYS, FLAG_NONCOERCIVE = 1, 2
-KERNEL_KINDS = ("dt", "reduce1", "rsolve1", "stage1", "reduce2", "rsolve2", "stage2")
+KERNEL_KINDS = ("dt", "reduce1", "rsolve1", "stage1", "reduce2", "rsolve2", "stage2", "win1", "win2")
+SOLVER_AUTO, SOLVER_EXACT, SOLVER_AUTO_SMALL = 0, 1, 2
+SOLVERS = {"auto": SOLVER_AUTO, "exact": SOLVER_EXACT, "auto_small": SOLVER_AUTO_SMALL}
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 
 
@@ -53,6 +55,10 @@ def lib():
         L.hsgn_run.argtypes = [vp, C.c_int32, C.c_int32]
         L.hsgn_step_timed.restype = C.c_int
         L.hsgn_step_timed.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.hsgn_set_solver.restype = C.c_int
+        L.hsgn_set_solver.argtypes = [vp, C.c_int32]
+        L.hsgn_plan_info.restype = C.c_int
+        L.hsgn_plan_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.hsgn_status.restype = C.c_int
         L.hsgn_status.argtypes = [vp, C.POINTER(C.c_int32)]
         L.hsgn_last_error.restype = C.c_char_p
@@ -105,14 +111,32 @@ class Solver:
             raise HsgnError("hsgn_init failed (%d)" % rc)
         self._h = h
 
+    def set_solver(self, mode):
+        """mode: "auto" (windowed single pass where certified), "exact"
+        (two-pass partition solve) or "auto_small" (2048-row windows)."""
+        m = SOLVERS[mode] if isinstance(mode, str) else int(mode)
+        self._check(lib().hsgn_set_solver(self._h, m), "hsgn_set_solver")
+
+    def plan_info(self):
+        mode = np.zeros(self.n_inst, dtype=np.int32)
+        halo = np.zeros(self.n_inst, dtype=np.int32)
+        cnt = np.zeros(4, dtype=np.int32)
+        P = C.POINTER(C.c_int32)
+        self._check(lib().hsgn_plan_info(self._h, mode.ctypes.data_as(P), halo.ctypes.data_as(P),
+                                         cnt.ctypes.data_as(P)), "hsgn_plan_info")
+        return dict(mode=mode, halo=halo, windows=int(cnt[0]), exact_tiles=int(cnt[1]),
+                    exact_multi=int(cnt[2]), window_rows=int(cnt[3]))
+
     @classmethod
-    def from_workload(cls, wl, device="cuda"):
+    def from_workload(cls, wl, device="cuda", solver=None):
         params = [dict(g=wl.g[j], lam=wl.lam[j], dx=wl.dx[j], cfl=wl.cfl[j], mcfl=wl.mcfl[j],
                        dt_fixed=wl.dt_fixed[j], t_end=wl.t_end[j], bc=wl.bc[j], has_b=wl.has_b[j])
                   for j in range(wl.n_inst)]
         b = None if wl.b is None else torch.from_numpy(wl.b).to(device)
         s = cls(wl.offsets, params, b, device=device)
         s.set_state(*[torch.from_numpy(a).to(device) for a in wl.state()])
+        if solver is not None:
+            s.set_solver(solver)
         return s
 
     def _check(self, rc, what):

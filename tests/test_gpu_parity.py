@@ -65,11 +65,14 @@ def check_instance(j, U, wl, nsteps, tol=TOL, seed=0):
     return state_err, worst, to
 
 
-def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label=""):
-    note("parity %s: %s, %d instances, %d cells, %d steps" % (label, wl.name, wl.n_inst,
-                                                              wl.n_cells, nsteps))
+def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", solver="auto"):
+    note("parity %s [%s]: %s, %d instances, %d cells, %d steps" % (
+        label, solver, wl.name, wl.n_inst, wl.n_cells, nsteps))
     Solver = _solver()
-    s = Solver.from_workload(wl)
+    s = Solver.from_workload(wl, solver=solver)
+    info = s.plan_info()
+    note("  plan: %d windows, %d two-pass tiles, halo max %d" % (
+        info["windows"], info["exact_tiles"], int(info["halo"].max())))
     if use_run:
         s.run(nsteps, block=block)
     else:
@@ -92,8 +95,12 @@ def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label=""):
     return worst
 
 
-def test_solitary_single_tile_100_steps():
-    compare(WL.solitary(N=800, t_end=0.0), 100, label="C1 geometry")
+SOLVERS = ["auto", "exact", "auto_small"]
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_solitary_single_tile_100_steps(solver):
+    compare(WL.solitary(N=800, t_end=0.0), 100, label="C1 geometry", solver=solver)
 
 
 def test_solitary_to_t_end():
@@ -102,17 +109,21 @@ def test_solitary_to_t_end():
     compare(wl, 200, label="C1 to t_end")
 
 
-def test_multi_tile_periodic():
-    compare(WL.solitary(N=5000, L=1250.0, lam=1000.0, t_end=0.0), 100, label="periodic 3 tiles")
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_multi_tile_periodic(solver):
+    compare(WL.solitary(N=5000, L=1250.0, lam=1000.0, t_end=0.0), 100, label="periodic 3 tiles",
+            solver=solver)
 
 
-def test_dam_break_transmissive_multi_tile():
-    compare(WL.dam_break(), 100, label="C2 100 steps")
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_dam_break_transmissive_multi_tile(solver):
+    compare(WL.dam_break(), 100, label="C2 100 steps", solver=solver)
 
 
-def test_batched_bar_small_batch():
-    wl = WL.batched_bar(n_inst=16, seed=5, n_lo=512, n_hi=6000)
-    compare(wl, 100, label="bar batch")
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_batched_bar_small_batch(solver):
+    wl = WL.batched_bar(n_inst=16, seed=5, n_lo=512, n_hi=9000)
+    compare(wl, 100, label="bar batch", solver=solver)
 
 
 def test_graph_run_matches_step_bitwise():
@@ -136,7 +147,8 @@ def test_graph_run_matches_step_bitwise():
         assert torch.equal(x, y)
 
 
-def test_edge_sizes_and_frozen_instances():
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_edge_sizes_and_frozen_instances(solver):
     parts = []
     for n in (4, 5, 7, 9, 31, 513, 2047, 2048, 2049, 4097):
         for bc in (0, 1):
@@ -149,8 +161,11 @@ def test_edge_sizes_and_frozen_instances():
     fixed.dt_fixed[:] = 0.01
     parts.append(fixed)
     parts.append(WL.lake_at_rest(N=700, lam=1e4, bed=True))
+    for n in (4095, 4096, 4097, 8300):
+        parts.append(WL.solitary(N=n, L=0.25 * n, lam=1e4, t_end=0.0, bc=1, x0=0.125 * n))
+        parts.append(WL.solitary(N=n, L=0.25 * n, lam=1e4, t_end=0.0, bc=0, x0=0.125 * n))
     wl = WL.concat("edges", parts)
-    compare(wl, 30, label="edge sizes")
+    compare(wl, 30, label="edge sizes", solver=solver)
 
 
 def test_lake_at_rest_gpu():
@@ -181,10 +196,10 @@ def test_nonphysical_state_is_flagged_and_frozen():
     check_instance(0, U, wl, 3)
 
 
-@pytest.mark.parametrize("N", [1 << 16])
-def test_long_periodic_scaled(N):
-    wl = WL.long_periodic(N=N)
-    compare(wl, 20, label="long periodic scaled")
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_long_periodic_scaled(solver):
+    wl = WL.long_periodic(N=1 << 16)
+    compare(wl, 20, label="long periodic scaled", solver=solver)
 
 
 def test_batched_full_size_sampled():
@@ -198,3 +213,14 @@ def test_batched_full_size_sampled():
     for v in (100.0, 1000.0, 10000.0):
         pick.append(int(np.nonzero(lam == v)[0][0]))
     compare(wl, 100, use_run=True, block=100, insts=sorted(set(pick)), label="C3 full, sampled")
+
+
+def test_window_plan_covers_every_cell_once():
+    """Host plan: the windows' cores tile every windowed instance exactly."""
+    Solver = _solver()
+    wl = WL.concat("plan", [WL.batched_bar(n_inst=40, seed=9, n_lo=512, n_hi=16384),
+                            WL.long_periodic(N=50000), WL.dam_break()])
+    s = Solver.from_workload(wl)
+    info = s.plan_info()
+    assert info["windows"] > 0
+    assert (info["halo"][info["mode"] == 0] > 0).all()
