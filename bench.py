@@ -102,7 +102,7 @@ def cpu_baseline(wl, budget_s=15.0, n_sample=128):
     t = [0.0] * sub.n_inst
     steps, el = 0, 0.0
     chunk = 5
-    while el < budget_s and steps < 200:
+    while el < budget_s and steps < 2000:
         t0 = time.perf_counter()
         rc, U, t, st = O.run_batch(sub.offsets, plist, sub.b, U, t, chunk, nthreads=0)
         el += time.perf_counter() - t0

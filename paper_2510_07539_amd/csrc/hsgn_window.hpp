@@ -175,6 +175,9 @@ __device__ void level1_interior_fast(Lds<NT>& S, int n1) {
       }
     }
     __syncthreads();
+    // couplings left after this level; once every one is below 2^-66 of
+    // its diagonal the remaining levels change no digit of the solution
+    bool more = false;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       const int j = 1 + t + r * NT;
@@ -185,9 +188,11 @@ __device__ void level1_interior_fast(Lds<NT>& S, int n1) {
         S.d0[j] = n0[r];
         S.d1[j] = n1v[r];
         S.d2[j] = n2[r];
+        const double lim = 1.3552527156068805e-20 * fabs(nb[r]);  // 2^-66
+        more |= !(fabs(na[r]) <= lim) || !(fabs(nc[r]) <= lim);
       }
     }
-    __syncthreads();
+    if (!__syncthreads_or(more)) break;
   }
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
@@ -290,36 +295,78 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
     L.misc[1] = 0.0;
   }
   const int SLn = na * K + 6;
-  auto cell_of = [&](int i) -> int {  // instance cell of staged index i
+  // instance cell of staged index i: rows past wl + 2 repeat row wl + 2; the
+  // periodic wrap needs a true modulo only when the window is longer than
+  // the ring
+  const bool fast_wrap = (bc != 0) || (n >= WN + 8);
+  auto cell_of = [&](int i) -> int {
     int p = i - 3;
     if (p > wd.wl + 2) p = wd.wl + 2;
-    return wrap_any(wd.ws + p, n, bc);
+    const int c = wd.ws + p;
+    if (!fast_wrap) return wrap_any(c, n, bc);
+    if (bc == 0) return c < 0 ? c + n : (c >= n ? c - n : c);
+    return c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
   };
   // per-thread registers: explicit state at rows p0-3 .. p0+K+2 (K+6)
   Cell E[K + 6];
   double Bv[K + 6];
   Cell O[K];
+  constexpr int NR = (WinLds<NT, K>::SL + NT - 1) / NT;  // staged elements per thread
+  const int nf = useb ? 5 : 4;
+  auto fld = [&](int f, bool second) -> const double* {
+    if (second) return f == 0 ? A.u1_h : f == 1 ? A.u1_q : f == 2 ? A.u1_m : A.u1_W;
+    return f == 0 ? A.un_h : f == 1 ? A.un_q : f == 2 ? A.un_m : f == 3 ? A.un_W : A.b;
+  };
+  // software pipeline over the fields: the loads of field f+1 are in flight
+  // while field f goes through LDS
+  double va[NR], vb[NR];
+  {
+    const double* un = fld(0, false);
+    const double* u1 = fld(0, true);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int i = t + r * NT;
+      if (i < SLn) {
+        const int64_t gi = base + cell_of(i);
+        va[r] = un[gi];
+        if (STAGE == 2) vb[r] = u1[gi];
+      }
+    }
+  }
 #pragma unroll
   for (int f = 0; f < 5; ++f) {
-    if (f == 4 && !useb) break;
-    for (int i = t; i < SLn; i += NT) {
-      const int64_t gi = base + cell_of(i);
-      double ev, ov = 0.0;
-      if (f == 4) {
-        ev = A.b[gi];
+    if (f >= nf) break;
+    double ea[NR], ob[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (STAGE == 1 || f == 4) {
+        ea[r] = va[r];
+        ob[r] = 0.0;
       } else {
-        const double* un = f == 0 ? A.un_h : f == 1 ? A.un_q : f == 2 ? A.un_m : A.un_W;
-        if (STAGE == 1) {
-          ev = un[gi];
-        } else {
-          const double* u1 = f == 0 ? A.u1_h : f == 1 ? A.u1_q : f == 2 ? A.u1_m : A.u1_W;
-          const double a = un[gi], b = u1[gi];
-          ev = kE0 * a + kE1 * b;
-          ov = kT0 * a + kT1 * b;
+        ea[r] = kE0 * va[r] + kE1 * vb[r];
+        ob[r] = kT0 * va[r] + kT1 * vb[r];
+      }
+    }
+    if (f + 1 < nf) {
+      const double* un = fld(f + 1, false);
+      const double* u1 = fld(f + 1, true);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int i = t + r * NT;
+        if (i < SLn) {
+          const int64_t gi = base + cell_of(i);
+          va[r] = un[gi];
+          if (STAGE == 2 && f + 1 < 4) vb[r] = u1[gi];
         }
       }
-      L.u.st.e[spad(i)] = ev;
-      if (STAGE == 2) L.u.st.o[spad(i)] = ov;
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int i = t + r * NT;
+      if (i < SLn) {
+        L.u.st.e[spad(i)] = ea[r];
+        if (STAGE == 2 && f < 4) L.u.st.o[spad(i)] = ob[r];
+      }
     }
     __syncthreads();
     if (act) {
@@ -559,6 +606,7 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
 
   // ---- back-substitution over the core rows
   double smax = 0.0, umax = 0.0;
+  double on[4][K];  // new state of this thread's rows (core rows only are stored)
   const int c0 = wd.cs - wd.ws;    // first core row (window-relative)
   const int c1 = c0 + wd.cl;       // one past the last core row
   const bool has_core = act && p0 < c1 && p0 + K > c0;
@@ -612,11 +660,10 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
         const double mn = rec[j].md * frcp(1.0 + P.lt2 * ih2);
         const double Wn = rec[j].Wd - P.lam * P.tau * mn * ih2;
         bad |= !(h > 0.0) || !isfinite(qn) || !isfinite(mn) || !isfinite(Wn);
-        const int64_t gi = base + wrap_any(wd.ws + p, n, bc);
-        A.o_h[gi] = h;
-        A.o_q[gi] = qn;
-        A.o_m[gi] = mn;
-        A.o_W[gi] = Wn;
+        on[0][j] = h;
+        on[1][j] = qn;
+        on[2][j] = mn;
+        on[3][j] = Wn;
         if (STAGE == 2) {
           const double u = fabs(qn * ih);
           smax = fmax(smax, u + sqrt(P.g * h));
@@ -624,6 +671,35 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
         }
       }
     }
+  }
+  // ---- coalesced stores of the core, one field at a time through LDS
+  __syncthreads();  // level-1 values (a) are no longer read
+  double* out[4] = {A.o_h, A.o_q, A.o_m, A.o_W};
+  constexpr int NS = (WN + NT - 1) / NT;
+#pragma unroll
+  for (int f = 0; f < 4; f += 2) {  // two fields per round (buffers e and o)
+    if (has_core) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const int p = p0 + j;
+        if (p >= c0 && p < c1) {
+          L.u.st.e[spad(p)] = on[f][j];
+          L.u.st.o[spad(p)] = on[f + 1][j];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const int i = t + r * NT;
+      if (i < wd.cl) {
+        int c = wd.cs + i;
+        if (c >= n) c -= n;
+        out[f][base + c] = L.u.st.e[spad(c0 + i)];
+        out[f + 1][base + c] = L.u.st.o[spad(c0 + i)];
+      }
+    }
+    __syncthreads();
   }
   if (STAGE == 2) {
 #pragma unroll
