@@ -18,23 +18,36 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hsgn_oracle.c")
+_SRC_CS = os.path.join(_HERE, "hsgn_oracle_cs.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_CS = os.path.join(_HERE, "liboracle_cs.so")
 _lib = None
+_lib_cs = None
 
 OK, ENONPHYS, ENONCOERCIVE, EINVAL = 0, 1, 2, 3
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 
 
-def build(force: bool = True) -> str:
-    """Compile liboracle.so with gcc (portable flags, OpenMP over instances)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + ".tmp%d" % os.getpid()
+def _compile(src, lib):
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp",
            "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-label",
-           _SRC, "-o", tmp, "-lm"]
+           src, "-o", tmp, "-lm"]
     subprocess.check_call(cmd)
-    os.replace(tmp, _LIB)
+    os.replace(tmp, lib)
+
+
+def _stale(lib):
+    return (not os.path.exists(lib)) or os.path.getmtime(lib) < max(
+        os.path.getmtime(_SRC), os.path.getmtime(_SRC_CS))
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so and its complex-step twin liboracle_cs.so with gcc
+    (portable flags, no FMA contraction, OpenMP over instances)."""
+    for src, lib in ((_SRC, _LIB), (_SRC_CS, _LIB_CS)):
+        if force or _stale(lib):
+            _compile(src, lib)
     return _LIB
 
 
@@ -53,8 +66,8 @@ class StageDbg(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
+        if _stale(_LIB) or _stale(_LIB_CS):
+            build(force=False)
         L = C.CDLL(_LIB)
         dp = C.POINTER(C.c_double)
         L.or_stage.restype = C.c_int
@@ -74,6 +87,10 @@ def lib():
         L.or_max_threads.restype = C.c_int
         L.or_tableau.restype = None
         L.or_tableau.argtypes = [dp]
+        ip = C.POINTER(C.c_int)
+        L.or_run_loss.restype = C.c_int
+        L.or_run_loss.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, C.c_int,
+                                  C.c_int, ip, dp, dp]
         _lib = L
     return _lib
 
@@ -177,3 +194,47 @@ def tridiag(lo, di, up, rhs, cyclic=False):
     x = np.empty(len(di))
     rc = lib().or_tridiag(len(di), int(bool(cyclic)), _p(lo), _p(di), _p(up), _p(rhs), _p(x))
     return rc, x
+
+
+def lib_cs():
+    """Complex-step build: arrays are complex128 (interleaved re, im)."""
+    global _lib_cs
+    if _lib_cs is None:
+        lib()
+        L = C.CDLL(_LIB_CS)
+        cp = C.c_void_p
+        ip = C.POINTER(C.c_int)
+        dp = C.POINTER(C.c_double)
+        L.or_run_loss_cs.restype = C.c_int
+        L.or_run_loss_cs.argtypes = [C.c_int, C.POINTER(Params), cp, cp, cp, cp, cp, C.c_int,
+                                   C.c_int, ip, dp, cp]
+        L.or_run_cs.restype = C.c_int
+        L.or_run_cs.argtypes = [C.c_int, C.POINTER(Params), cp, cp, cp, cp, cp, dp, C.c_int]
+        _lib_cs = L
+    return _lib_cs
+
+
+def run_loss(p: Params, b, U, nsteps, gauges, targets):
+    """Gauge-misfit loss of nsteps steps (double build).  Returns (rc, J, Unew)."""
+    U = [np.array(a, dtype=np.float64, copy=True) for a in U]
+    g = np.ascontiguousarray(gauges, dtype=np.int32)
+    tg = np.ascontiguousarray(targets, dtype=np.float64).reshape(-1)
+    J = C.c_double(0.0)
+    bb = _f(b) if b is not None else None
+    rc = lib().or_run_loss(len(U[0]), C.byref(p), _p(bb), *[_p(a) for a in U], int(nsteps),
+                           len(g), g.ctypes.data_as(C.POINTER(C.c_int)), _p(tg), C.pointer(J))
+    return rc, J.value, tuple(U)
+
+
+def run_loss_cs(p: Params, b, U, nsteps, gauges, targets):
+    """Same on complex128 inputs (complex-step).  Returns (rc, J complex)."""
+    U = [np.array(a, dtype=np.complex128, copy=True) for a in U]
+    g = np.ascontiguousarray(gauges, dtype=np.int32)
+    tg = np.ascontiguousarray(targets, dtype=np.float64).reshape(-1)
+    J = np.zeros(1, dtype=np.complex128)
+    bb = None if b is None else np.ascontiguousarray(b, dtype=np.complex128)
+    vp = lambda a: None if a is None else C.c_void_p(a.ctypes.data)
+    rc = lib_cs().or_run_loss_cs(len(U[0]), C.byref(p), vp(bb), *[vp(a) for a in U], int(nsteps),
+                               len(g), g.ctypes.data_as(C.POINTER(C.c_int)),
+                               tg.ctypes.data_as(C.POINTER(C.c_double)), vp(J))
+    return rc, complex(J[0])

@@ -40,6 +40,27 @@
 #include <omp.h>
 #endif
 
+/* The same source builds twice: with real_t = double (the oracle), and with
+ * real_t = double complex (OR_COMPLEX) for complex-step derivatives
+ * (Im f(x + i e v) / e = f'(x) v to rounding for e ~ 1e-30): branches and
+ * comparisons act on real parts, |x| is x sign(Re x), max picks by real part,
+ * so the complex build differentiates exactly the double build's arithmetic.
+ * Exported names of the complex build carry the suffix _cs. */
+#ifdef OR_COMPLEX
+#include <complex.h>
+typedef double complex real_t;
+#define RE(x) creal(x)
+#define RSQRT(x) csqrt(x)
+#define FN(name) name##_cs
+#else
+typedef double real_t;
+#define RE(x) (x)
+#define RSQRT(x) sqrt(x)
+#define FN(name) name
+#endif
+#define RABS(x) (RE(x) < 0.0 ? -(x) : (x))
+#define RMAX(a, b) (RE(a) > RE(b) ? (a) : (b))
+
 /* Double Butcher tableau of Sec. 3.2 (eq. tableau): gamma = 1 - 1/sqrt(2),
  * c = 1/(2 gamma).  Efficient form of the remark after the tableau:
  *   U_E^(2) = (1 - c/gamma) U^n + (c/gamma) U_I^(1)
@@ -51,6 +72,7 @@ static const double OR_E1 = 5.82842712474619009760;  /* c/gamma */
 static const double OR_T0 = -1.41421356237309504880; /* 1 - (1-gamma)/gamma */
 static const double OR_T1 = 2.41421356237309504880;  /* (1-gamma)/gamma */
 
+#ifndef OR_COMPLEX
 double or_gamma(void) { return OR_GAMMA; }
 
 void or_tableau(double* out) {
@@ -68,6 +90,7 @@ int or_max_threads(void) {
   return 1;
 #endif
 }
+#endif
 
 /* Cell index with ghosts: periodic wrap or zero-order copy (transmissive). */
 static int gidx(int i, int n, int bc) {
@@ -80,15 +103,15 @@ static int gidx(int i, int n, int bc) {
 /* ---------------------------------------------------------------------- */
 /* Tridiagonal solvers: Thomas, and Sherman-Morrison for the cyclic case.   */
 /* ---------------------------------------------------------------------- */
-static int thomas(int n, const double* lo, const double* di, const double* up,
-                  const double* rhs, double* x) {
-  double* cp = (double*)malloc(sizeof(double) * (size_t)n);
-  double* dp = (double*)malloc(sizeof(double) * (size_t)n);
+static int thomas(int n, const real_t* lo, const real_t* di, const real_t* up,
+                  const real_t* rhs, real_t* x) {
+  real_t* cp = (real_t*)malloc(sizeof(real_t) * (size_t)n);
+  real_t* dp = (real_t*)malloc(sizeof(real_t) * (size_t)n);
   if (!cp || !dp) { free(cp); free(dp); return OR_EINVAL; }
   cp[0] = up[0] / di[0];
   dp[0] = rhs[0] / di[0];
   for (int i = 1; i < n; ++i) {
-    double den = di[i] - lo[i] * cp[i - 1];
+    real_t den = di[i] - lo[i] * cp[i - 1];
     cp[i] = up[i] / den;
     dp[i] = (rhs[i] - lo[i] * dp[i - 1]) / den;
   }
@@ -99,20 +122,20 @@ static int thomas(int n, const double* lo, const double* di, const double* up,
   return OR_OK;
 }
 
-int or_tridiag(int n, int cyclic, const double* lo, const double* di,
-               const double* up, const double* rhs, double* x) {
+int FN(or_tridiag)(int n, int cyclic, const real_t* lo, const real_t* di,
+               const real_t* up, const real_t* rhs, real_t* x) {
   if (n < 1) return OR_EINVAL;
   if (n == 1) {
-    double d = di[0] + (cyclic ? lo[0] + up[0] : 0.0);
+    real_t d = di[0] + (cyclic ? lo[0] + up[0] : 0.0);
     x[0] = rhs[0] / d;
     return OR_OK;
   }
   if (!cyclic || n == 2) {
     if (!cyclic) return thomas(n, lo, di, up, rhs, x);
     /* n == 2 cyclic: both couplings hit the other unknown. */
-    double a00 = di[0], a01 = up[0] + lo[0];
-    double a10 = lo[1] + up[1], a11 = di[1];
-    double det = a00 * a11 - a01 * a10;
+    real_t a00 = di[0], a01 = up[0] + lo[0];
+    real_t a10 = lo[1] + up[1], a11 = di[1];
+    real_t det = a00 * a11 - a01 * a10;
     x[0] = (rhs[0] * a11 - a01 * rhs[1]) / det;
     x[1] = (a00 * rhs[1] - a10 * rhs[0]) / det;
     return OR_OK;
@@ -120,13 +143,13 @@ int or_tridiag(int n, int cyclic, const double* lo, const double* di,
   /* Cyclic: A = B + u v^T with u = (gam, 0..0, up[n-1]),
    * v = (1, 0..0, lo[0]/gam); B has the corners removed and the two
    * diagonal ends corrected. */
-  double gam = -di[0];
-  double* dd = (double*)malloc(sizeof(double) * (size_t)n);
-  double* u = (double*)malloc(sizeof(double) * (size_t)n);
-  double* y = (double*)malloc(sizeof(double) * (size_t)n);
-  double* z = (double*)malloc(sizeof(double) * (size_t)n);
-  double* l2 = (double*)malloc(sizeof(double) * (size_t)n);
-  double* u2 = (double*)malloc(sizeof(double) * (size_t)n);
+  real_t gam = -di[0];
+  real_t* dd = (real_t*)malloc(sizeof(real_t) * (size_t)n);
+  real_t* u = (real_t*)malloc(sizeof(real_t) * (size_t)n);
+  real_t* y = (real_t*)malloc(sizeof(real_t) * (size_t)n);
+  real_t* z = (real_t*)malloc(sizeof(real_t) * (size_t)n);
+  real_t* l2 = (real_t*)malloc(sizeof(real_t) * (size_t)n);
+  real_t* u2 = (real_t*)malloc(sizeof(real_t) * (size_t)n);
   if (!dd || !u || !y || !z || !l2 || !u2) {
     free(dd); free(u); free(y); free(z); free(l2); free(u2);
     return OR_EINVAL;
@@ -146,9 +169,9 @@ int or_tridiag(int n, int cyclic, const double* lo, const double* di,
   int rc = thomas(n, l2, dd, u2, rhs, y);
   if (rc == OR_OK) rc = thomas(n, l2, dd, u2, u, z);
   if (rc == OR_OK) {
-    double vy = y[0] + lo[0] / gam * y[n - 1];
-    double vz = z[0] + lo[0] / gam * z[n - 1];
-    double f = vy / (1.0 + vz);
+    real_t vy = y[0] + lo[0] / gam * y[n - 1];
+    real_t vz = z[0] + lo[0] / gam * z[n - 1];
+    real_t f = vy / (1.0 + vz);
     for (int i = 0; i < n; ++i) x[i] = y[i] - f * z[i];
   }
   free(dd); free(u); free(y); free(z); free(l2); free(u2);
@@ -158,10 +181,10 @@ int or_tridiag(int n, int cyclic, const double* lo, const double* di,
 /* ---------------------------------------------------------------------- */
 /* One semi-implicit stage (Sec. 4.2, eq. GN_hyp_eq_semi_fully_discrete).   */
 /* ---------------------------------------------------------------------- */
-int or_stage(int n, const or_params* p, double tau, const double* bin,
-             const double* hE, const double* qE, const double* mE, const double* WE,
-             const double* ho, const double* qo, const double* mo, const double* Wo,
-             double* hn, double* qn, double* mn, double* Wn, or_stage_dbg* dbg) {
+int FN(or_stage)(int n, const or_params* p, double tau, const real_t* bin,
+             const real_t* hE, const real_t* qE, const real_t* mE, const real_t* WE,
+             const real_t* ho, const real_t* qo, const real_t* mo, const real_t* Wo,
+             real_t* hn, real_t* qn, real_t* mn, real_t* Wn, or_stage_dbg* dbg) {
   if (n < 1 || !p || p->dx <= 0.0) return OR_EINVAL;
   const int bc = p->bc;
   const double g = p->g, lam = p->lambda, dx = p->dx;
@@ -169,35 +192,35 @@ int or_stage(int n, const or_params* p, double tau, const double* bin,
   int rc = OR_OK;
 
   size_t nc = (size_t)n, nf = (size_t)n + 1;
-  double* bz = (double*)calloc(nc, sizeof(double));
-  double* Fq = (double*)malloc(nf * sizeof(double));
-  double* Fm = (double*)malloc(nf * sizeof(double));
-  double* FW = (double*)malloc(nf * sizeof(double));
-  double* qd = (double*)malloc(nc * sizeof(double));
-  double* md = (double*)malloc(nc * sizeof(double));
-  double* Wd = (double*)malloc(nc * sizeof(double));
-  double* beta = (double*)malloc(nc * sizeof(double));
-  double* S = (double*)malloc(nc * sizeof(double));
-  double* phi = (double*)malloc(nc * sizeof(double));
-  double* T = (double*)malloc(nc * sizeof(double));
-  double* P0 = (double*)malloc(nc * sizeof(double));
-  double* pt0 = (double*)malloc(nc * sizeof(double));
-  double* gL = (double*)malloc(nf * sizeof(double));
-  double* gR = (double*)malloc(nf * sizeof(double));
-  double* g0 = (double*)malloc(nf * sizeof(double));
-  double* qf = (double*)malloc(nf * sizeof(double));
-  double* lo = (double*)malloc(nc * sizeof(double));
-  double* di = (double*)malloc(nc * sizeof(double));
-  double* up = (double*)malloc(nc * sizeof(double));
-  double* rhs = (double*)malloc(nc * sizeof(double));
-  double* hb = (double*)malloc(nc * sizeof(double));
+  real_t* bz = (real_t*)calloc(nc, sizeof(real_t));
+  real_t* Fq = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* Fm = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* FW = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* qd = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* md = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* Wd = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* beta = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* S = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* phi = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* T = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* P0 = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* pt0 = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* gL = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* gR = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* g0 = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* qf = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* lo = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* di = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* up = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* rhs = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* hb = (real_t*)malloc(nc * sizeof(real_t));
   if (!bz || !Fq || !Fm || !FW || !qd || !md || !Wd || !beta || !S || !phi ||
       !T || !P0 || !pt0 || !gL || !gR || !g0 || !qf || !lo || !di || !up ||
       !rhs || !hb) {
     rc = OR_EINVAL;
     goto done;
   }
-  const double* b = useb ? bin : bz;
+  const real_t* b = useb ? bin : bz;
 
   /* (1) Explicit Rusanov fluxes of q u, m u, W u at every face, from the
    * unlimited component-wise linear reconstruction of U_E (Sec. 4.1:
@@ -207,28 +230,28 @@ int or_stage(int n, const or_params* p, double tau, const double* bin,
     int i1 = gidx(k, n, bc), i2 = gidx(k + 1, n, bc);
     /* left state: cell k-1 at its right face; right state: cell k at its
      * left face. */
-    double hL = hE[i0] + 0.25 * (hE[i1] - hE[im1]);
-    double hR = hE[i1] - 0.25 * (hE[i2] - hE[i0]);
-    double qL = qE[i0] + 0.25 * (qE[i1] - qE[im1]);
-    double qR = qE[i1] - 0.25 * (qE[i2] - qE[i0]);
-    double mL = mE[i0] + 0.25 * (mE[i1] - mE[im1]);
-    double mR = mE[i1] - 0.25 * (mE[i2] - mE[i0]);
-    double WL = WE[i0] + 0.25 * (WE[i1] - WE[im1]);
-    double WR = WE[i1] - 0.25 * (WE[i2] - WE[i0]);
-    if (!(hL > 0.0) || !(hR > 0.0)) rc = OR_ENONPHYS;
-    double uL = qL / hL, uR = qR / hR;
-    double sL = fabs(uL) + sqrt(g * hL), sR = fabs(uR) + sqrt(g * hR);
-    double a = sL > sR ? sL : sR;
+    real_t hL = hE[i0] + 0.25 * (hE[i1] - hE[im1]);
+    real_t hR = hE[i1] - 0.25 * (hE[i2] - hE[i0]);
+    real_t qL = qE[i0] + 0.25 * (qE[i1] - qE[im1]);
+    real_t qR = qE[i1] - 0.25 * (qE[i2] - qE[i0]);
+    real_t mL = mE[i0] + 0.25 * (mE[i1] - mE[im1]);
+    real_t mR = mE[i1] - 0.25 * (mE[i2] - mE[i0]);
+    real_t WL = WE[i0] + 0.25 * (WE[i1] - WE[im1]);
+    real_t WR = WE[i1] - 0.25 * (WE[i2] - WE[i0]);
+    if (!(RE(hL) > 0.0) || !(RE(hR) > 0.0)) rc = OR_ENONPHYS;
+    real_t uL = qL / hL, uR = qR / hR;
+    real_t sL = RABS(uL) + RSQRT(g * hL), sR = RABS(uR) + RSQRT(g * hR);
+    real_t a = RMAX(sL, sR);
     /* Face-local lake-at-rest moment: mhat_j = (zeta_f - b_j)^2 with
      * zeta_f the mean free surface of the two face cells, reconstructed
      * like m; identically zero jump on a flat bed. */
-    double zf = 0.5 * ((hE[i0] + b[i0]) + (hE[i1] + b[i1]));
-    double r_m1 = (zf - b[im1]) * (zf - b[im1]);
-    double r_0 = (zf - b[i0]) * (zf - b[i0]);
-    double r_1 = (zf - b[i1]) * (zf - b[i1]);
-    double r_2 = (zf - b[i2]) * (zf - b[i2]);
-    double mhL = r_0 + 0.25 * (r_1 - r_m1);
-    double mhR = r_1 - 0.25 * (r_2 - r_0);
+    real_t zf = 0.5 * ((hE[i0] + b[i0]) + (hE[i1] + b[i1]));
+    real_t r_m1 = (zf - b[im1]) * (zf - b[im1]);
+    real_t r_0 = (zf - b[i0]) * (zf - b[i0]);
+    real_t r_1 = (zf - b[i1]) * (zf - b[i1]);
+    real_t r_2 = (zf - b[i2]) * (zf - b[i2]);
+    real_t mhL = r_0 + 0.25 * (r_1 - r_m1);
+    real_t mhR = r_1 - 0.25 * (r_2 - r_0);
     Fq[k] = 0.5 * (qL * uL + qR * uR - a * (qR - qL));
     FW[k] = 0.5 * (WL * uL + WR * uR - a * (WR - WL));
     Fm[k] = 0.5 * (mL * uL + mR * uR - a * ((mR - mL) - (mhR - mhL)));
@@ -237,7 +260,7 @@ int or_stage(int n, const or_params* p, double tau, const double* bin,
   /* (2) Convective predictor with the exact relaxation elimination
    * (Sec. 3.1 eq. hSGN_eq-ustar and eq. b1; Sec. 4.2 first three lines). */
   for (int i = 0; i < n; ++i) {
-    double dbc = (b[gidx(i + 1, n, bc)] - b[gidx(i - 1, n, bc)]) / (2.0 * dx);
+    real_t dbc = (b[gidx(i + 1, n, bc)] - b[gidx(i - 1, n, bc)]) / (2.0 * dx);
     Wd[i] = Wo[i] - tau / dx * (FW[i + 1] - FW[i]) + lam * tau;
     md[i] = mo[i] - tau / dx * (Fm[i + 1] - Fm[i]) - tau * 1.5 * qE[i] * dbc +
             tau * Wd[i];
@@ -250,21 +273,21 @@ int or_stage(int n, const or_params* p, double tau, const double* bin,
    * phi is d p~/d h of p~ = (lambda/3)(1 - eta/h) along the same
    * relaxation closure (bed form, eq. hSGNb_eq). */
   for (int i = 0; i < n; ++i) {
-    double h = hE[i];
-    if (!(h > 0.0)) rc = OR_ENONPHYS;
-    double eta = mE[i] / h;
-    double alpha = -(2.0 * eta / h - 1.0) / (3.0 * h);
-    double c2 = g * h + lam / 3.0 * eta * eta / (h * h);
-    double a2 = c2 - lam * eta * alpha;
-    double beta1 = 1.0 + lam * tau * tau / (h * h);
-    double beta2 = 2.0 * lam * tau * tau / (beta1 * beta1 * h * h * h);
+    real_t h = hE[i];
+    if (!(RE(h) > 0.0)) rc = OR_ENONPHYS;
+    real_t eta = mE[i] / h;
+    real_t alpha = -(2.0 * eta / h - 1.0) / (3.0 * h);
+    real_t c2 = g * h + lam / 3.0 * eta * eta / (h * h);
+    real_t a2 = c2 - lam * eta * alpha;
+    real_t beta1 = 1.0 + lam * tau * tau / (h * h);
+    real_t beta2 = 2.0 * lam * tau * tau / (beta1 * beta1 * h * h * h);
     beta[i] = a2 + lam * alpha * beta2 * md[i];
-    if (!(beta[i] > 0.0)) rc = rc ? rc : OR_ENONCOERCIVE;
-    double eta0 = md[i] / (beta1 * h);
+    if (!(RE(beta[i]) > 0.0)) rc = rc ? rc : OR_ENONCOERCIVE;
+    real_t eta0 = md[i] / (beta1 * h);
     pt0[i] = lam / 3.0 * (1.0 - eta0 / h);
     P0[i] = 0.5 * g * h * h + eta0 * pt0[i];
     S[i] = P0[i] - beta[i] * h;
-    double den = h * h + lam * tau * tau;
+    real_t den = h * h + lam * tau * tau;
     phi[i] = 2.0 * lam / 3.0 * md[i] * h / (den * den);
     T[i] = pt0[i] - phi[i] * h;
   }
@@ -283,7 +306,7 @@ int or_stage(int n, const or_params* p, double tau, const double* bin,
       qf[k] = qd[k == 0 ? 0 : n - 1];
       continue;
     }
-    double db = b[R] - b[L];
+    real_t db = b[R] - b[L];
     gL[k] = (-beta[L] + db * (0.5 * g + 0.75 * phi[L])) / dx;
     gR[k] = (beta[R] + db * (0.5 * g + 0.75 * phi[R])) / dx;
     g0[k] = (S[R] - S[L] + 0.75 * db * (T[L] + T[R])) / dx;
@@ -293,14 +316,14 @@ int or_stage(int n, const or_params* p, double tau, const double* bin,
   /* (5) Mass balance hbar_i = h_old,i - tau/dx (Q_{i+1/2} - Q_{i-1/2}),
    * collected as rows of the tridiagonal (cyclic if periodic) system. */
   for (int i = 0; i < n; ++i) {
-    double c = tau * tau / dx;
+    real_t c = tau * tau / dx;
     up[i] = -c * gR[i + 1];
     lo[i] = c * gL[i];
     di[i] = 1.0 - c * (gL[i + 1] - gR[i]);
     rhs[i] = ho[i] - tau / dx * (qf[i + 1] - qf[i]) + c * (g0[i + 1] - g0[i]);
   }
   {
-    int trc = or_tridiag(n, bc == 0, lo, di, up, rhs, hb);
+    int trc = FN(or_tridiag)(n, bc == 0, lo, di, up, rhs, hb);
     if (trc) rc = trc;
   }
 
@@ -310,22 +333,23 @@ int or_stage(int n, const or_params* p, double tau, const double* bin,
    * W = W-dagger - lambda tau m / hbar^2. */
   for (int i = 0; i < n; ++i) {
     int im = gidx(i - 1, n, bc), ip = gidx(i + 1, n, bc);
-    double Pm = P0[im] + beta[im] * (hb[im] - hE[im]);
-    double Pp = P0[ip] + beta[ip] * (hb[ip] - hE[ip]);
-    double pti = pt0[i] + phi[i] * (hb[i] - hE[i]);
-    double dbc = (b[ip] - b[im]) / (2.0 * dx);
-    double hbi = hb[i];
-    if (!(hbi > 0.0)) rc = OR_ENONPHYS;
+    real_t Pm = P0[im] + beta[im] * (hb[im] - hE[im]);
+    real_t Pp = P0[ip] + beta[ip] * (hb[ip] - hE[ip]);
+    real_t pti = pt0[i] + phi[i] * (hb[i] - hE[i]);
+    real_t dbc = (b[ip] - b[im]) / (2.0 * dx);
+    real_t hbi = hb[i];
+    if (!(RE(hbi) > 0.0)) rc = OR_ENONPHYS;
     qn[i] = qd[i] - tau * ((Pp - Pm) / (2.0 * dx) +
                            0.5 * g * (hb[ip] + hb[im]) * dbc + 1.5 * pti * dbc);
     mn[i] = md[i] / (1.0 + lam * tau * tau / (hbi * hbi));
     Wn[i] = Wd[i] - lam * tau * mn[i] / (hbi * hbi);
     hn[i] = hbi;
-    if (!isfinite(qn[i]) || !isfinite(mn[i]) || !isfinite(Wn[i]) ||
-        !isfinite(hn[i]))
+    if (!isfinite(RE(qn[i])) || !isfinite(RE(mn[i])) || !isfinite(RE(Wn[i])) ||
+        !isfinite(RE(hn[i])))
       rc = OR_ENONPHYS;
   }
 
+#ifndef OR_COMPLEX
   if (dbg) {
 #define OR_CP(dst, src, cnt) \
   if (dbg->dst) memcpy(dbg->dst, src, (cnt) * sizeof(double))
@@ -337,6 +361,9 @@ int or_stage(int n, const or_params* p, double tau, const double* bin,
     OR_CP(Fq, Fq, nf); OR_CP(Fm, Fm, nf); OR_CP(FW, FW, nf);
 #undef OR_CP
   }
+#else
+  (void)dbg;
+#endif
 
 done:
   free(bz); free(Fq); free(Fm); free(FW); free(qd); free(md); free(Wd);
@@ -351,15 +378,15 @@ done:
 /* The speed is |u| + sqrt(g h): the lambda-independent rule of the remark  */
 /* after the coercivity proposition (Sec. 3.1).                             */
 /* ---------------------------------------------------------------------- */
-double or_dt(int n, const or_params* p, const double* h, const double* q, double t) {
+double FN(or_dt)(int n, const or_params* p, const real_t* h, const real_t* q, double t) {
   double dt;
   if (p->dt_fixed > 0.0) {
     dt = p->dt_fixed;
   } else {
     double smax = 0.0, umax = 0.0;
     for (int i = 0; i < n; ++i) {
-      double u = fabs(q[i] / h[i]);
-      double s = u + sqrt(p->g * h[i]);
+      double u = fabs(RE(q[i]) / RE(h[i]));
+      double s = u + sqrt(p->g * RE(h[i]));
       if (s > smax) smax = s;
       if (u > umax) umax = u;
     }
@@ -376,21 +403,21 @@ double or_dt(int n, const or_params* p, const double* h, const double* q, double
 /* ---------------------------------------------------------------------- */
 /* Two-stage IMEX step (Sec. 3.2, eq. tableau, steps 1-5 + efficient form). */
 /* ---------------------------------------------------------------------- */
-int or_step(int n, const or_params* p, const double* b,
-            double* h, double* q, double* m, double* W, double* t, double* dt_out) {
-  double dt = or_dt(n, p, h, q, *t);
+int FN(or_step)(int n, const or_params* p, const real_t* b,
+            real_t* h, real_t* q, real_t* m, real_t* W, double* t, double* dt_out) {
+  double dt = FN(or_dt)(n, p, h, q, *t);
   if (dt_out) *dt_out = dt;
   if (!(dt > 0.0)) return OR_OK; /* frozen instance */
   double tau = OR_GAMMA * dt;
   size_t nc = (size_t)n;
-  double* buf = (double*)malloc(12 * nc * sizeof(double));
+  real_t* buf = (real_t*)malloc(12 * nc * sizeof(real_t));
   if (!buf) return OR_EINVAL;
-  double *h1 = buf, *q1 = buf + nc, *m1 = buf + 2 * nc, *W1 = buf + 3 * nc;
-  double *hE = buf + 4 * nc, *qE = buf + 5 * nc, *mE = buf + 6 * nc, *WE = buf + 7 * nc;
-  double *ht = buf + 8 * nc, *qt = buf + 9 * nc, *mt = buf + 10 * nc, *Wt = buf + 11 * nc;
+  real_t *h1 = buf, *q1 = buf + nc, *m1 = buf + 2 * nc, *W1 = buf + 3 * nc;
+  real_t *hE = buf + 4 * nc, *qE = buf + 5 * nc, *mE = buf + 6 * nc, *WE = buf + 7 * nc;
+  real_t *ht = buf + 8 * nc, *qt = buf + 9 * nc, *mt = buf + 10 * nc, *Wt = buf + 11 * nc;
 
   /* stage 1: U_E^(1) = U^n, U_I^(1) = U^n + gamma dt H(U_E^(1), U_I^(1)) */
-  int rc = or_stage(n, p, tau, b, h, q, m, W, h, q, m, W, h1, q1, m1, W1, NULL);
+  int rc = FN(or_stage)(n, p, tau, b, h, q, m, W, h, q, m, W, h1, q1, m1, W1, NULL);
   int rc2 = OR_OK;
   if (rc == OR_OK) {
     /* efficient-form combinations */
@@ -406,22 +433,42 @@ int or_step(int n, const or_params* p, const double* b,
     }
     /* stage 2: U^{n+1} = U_I^(2) = U~ + gamma dt H(U_E^(2), U_I^(2))
      * (stiffly accurate: the last implicit stage is the new state) */
-    rc2 = or_stage(n, p, tau, b, hE, qE, mE, WE, ht, qt, mt, Wt, h, q, m, W, NULL);
+    rc2 = FN(or_stage)(n, p, tau, b, hE, qE, mE, WE, ht, qt, mt, Wt, h, q, m, W, NULL);
   }
   free(buf);
   *t += dt;
   return rc ? rc : rc2;
 }
 
-int or_run(int n, const or_params* p, const double* b,
-           double* h, double* q, double* m, double* W, double* t, int nsteps) {
+int FN(or_run)(int n, const or_params* p, const real_t* b,
+           real_t* h, real_t* q, real_t* m, real_t* W, double* t, int nsteps) {
   for (int s = 0; s < nsteps; ++s) {
-    int rc = or_step(n, p, b, h, q, m, W, t, NULL);
+    int rc = FN(or_step)(n, p, b, h, q, m, W, t, NULL);
     if (rc) return rc;
   }
   return OR_OK;
 }
 
+/* Gauge misfit: nsteps steps from the given state; after step s the loss
+ * gains (1/2) sum_g (h[gauge[g]] - target[s*ng + g])^2. */
+int FN(or_run_loss)(int n, const or_params* p, const real_t* b, real_t* h, real_t* q,
+                    real_t* m, real_t* W, int nsteps, int ng, const int* gauge,
+                    const double* target, real_t* loss) {
+  double t = 0.0;
+  real_t J = 0.0;
+  for (int s = 0; s < nsteps; ++s) {
+    int rc = FN(or_step)(n, p, b, h, q, m, W, &t, NULL);
+    if (rc) return rc;
+    for (int g = 0; g < ng; ++g) {
+      real_t d = h[gauge[g]] - target[(size_t)s * ng + g];
+      J += 0.5 * d * d;
+    }
+  }
+  *loss = J;
+  return OR_OK;
+}
+
+#ifndef OR_COMPLEX
 int or_run_batch(int n_inst, const long long* offsets, const or_params* p,
                  const double* b, double* h, double* q, double* m, double* W,
                  double* t, int nsteps, int nthreads, int* status) {
@@ -441,3 +488,4 @@ int or_run_batch(int n_inst, const long long* offsets, const or_params* p,
   (void)nthreads;
   return worst;
 }
+#endif

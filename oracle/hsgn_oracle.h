@@ -68,6 +68,18 @@ int or_step(int n, const or_params* p, const double* b,
 int or_run(int n, const or_params* p, const double* b,
            double* h, double* q, double* m, double* W, double* t, int nsteps);
 
+/* Gauge misfit of nsteps steps: after step s the loss gains
+ * (1/2) sum_g (h[gauge[g]] - target[s*ng + g])^2.  State updated in place. */
+int or_run_loss(int n, const or_params* p, const double* b, double* h, double* q,
+                double* m, double* W, int nsteps, int ng, const int* gauge,
+                const double* target, double* loss);
+
+/* Complex-step build (hsgn_oracle_cs.c, library liboracle_cs.so): the same
+ * functions on double complex state with the suffix _cs (or_stage_cs,
+ * or_step_cs, or_run_cs, or_run_loss_cs, or_tridiag_cs, or_dt_cs).  Im of the result
+ * for an input perturbed by i*eps*v, divided by eps, is the directional
+ * derivative of the double build to rounding. */
+
 /* Independent instances concatenated: instance j owns cells
  * [offsets[j], offsets[j+1]).  OpenMP over instances with nthreads threads
  * (<= 0: library default).  status[j] receives each instance's code. */

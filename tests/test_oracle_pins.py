@@ -390,3 +390,42 @@ def test_linear_dispersion_relation():
     gap = abs(w - wsgn) / w * 2 * math.pi
     ext = (4 * phase_err[2] - phase_err[1]) / 3
     assert abs(ext) < 0.01 * gap, (ext, gap)
+
+
+# ---------------------------------------------------------------------------
+# Complex-step build of the oracle (reference for the adjoint): it returns
+# the double build's loss in its real part and, for a perturbation i*eps*v,
+# the directional derivative in its imaginary part; checked against central
+# differences of the double build with Richardson extrapolation.
+# ---------------------------------------------------------------------------
+def test_complex_step_build_differentiates_the_oracle():
+    wl = WL.batched_bar(n_inst=1, seed=5, n_lo=300, n_hi=300)
+    n, prm, b, U0 = wl.instance(0)
+    prm = dict(prm, dt_fixed=0.004, lam=1000.0)
+    p = O.make_params(**prm)
+    g = np.array([n // 4, n // 2, 3 * n // 4])
+    tgt = np.full((15, 3), 0.41)
+    zeta = U0[0] + b
+    rng = np.random.default_rng(1)
+
+    def state(z, bb):
+        h = z - bb
+        return (h, np.zeros(n), h * h, np.zeros(n))
+
+    _, J0, _ = O.run_loss(p, b, state(zeta, b), 15, g, tgt)
+    for kind in ("zeta", "b"):
+        v = rng.standard_normal(n) * 1e-3
+        eps = 1e-30
+        if kind == "zeta":
+            rc, Jc = O.run_loss_cs(p, b.astype(complex), state(zeta + 1j * eps * v, b.astype(complex)), 15, g, tgt)
+            f = lambda e: O.run_loss(p, b, state(zeta + e * v, b), 15, g, tgt)[1]
+        else:
+            bc = b + 1j * eps * v
+            rc, Jc = O.run_loss_cs(p, bc, state(zeta.astype(complex), bc), 15, g, tgt)
+            f = lambda e: O.run_loss(p, b + e * v, state(zeta, b + e * v), 15, g, tgt)[1]
+        assert rc == 0
+        assert abs(Jc.real - J0) <= 1e-14 * abs(J0)
+        d_cs = Jc.imag / eps
+        fd = lambda e: (f(e) - f(-e)) / (2 * e)
+        d_rich = (4 * fd(1e-4) - fd(2e-4)) / 3
+        assert abs(d_cs - d_rich) <= 1e-7 * abs(d_cs), (kind, d_cs, d_rich)
