@@ -116,6 +116,57 @@ def cpu_baseline(wl, budget_s=15.0, n_sample=128):
                       % (sub.n_inst, sub.n_cells, steps, el)}
 
 
+def adjoint_cost(reps=2):
+    """Cost of the gradient of the gauge misfit against the forward pass on
+    the gradient workload: 1024 instances x 4096 cells over a bar plus a
+    sinusoid, lambda = 1000, 200 steps, checkpoints every 20 steps.  Targets
+    are the library's own gauge series from a perturbed initial surface
+    (made before timing).  Forward = the loss alone (200 steps and the gauge
+    misfit); adjoint = loss and both gradients (forward with checkpoints,
+    segment recompute, reverse sweep)."""
+    import torch
+    from paper_2510_07539_amd import workloads as WL
+    from paper_2510_07539_amd.hsgn import Solver
+    case = WL.adjoint_bar()
+    wl, nsteps, K = case.wl, case.nsteps, case.K
+    dev = "cuda"
+    s = Solver.from_workload(wl)
+    try:
+        bt = torch.from_numpy(wl.b).to(dev)
+        h = torch.from_numpy(case.zeta_target).to(dev) - bt
+        s.set_state(h, torch.zeros_like(h), h * h, torch.zeros_like(h))
+        gi = (torch.from_numpy(wl.offsets[:-1]).to(dev)[:, None]
+              + torch.from_numpy(case.gauges).to(dev).long())
+        tg = torch.empty((wl.n_inst, nsteps, case.gauges.shape[1]), dtype=torch.float64, device=dev)
+        for st in range(nsteps):
+            s.step(1)
+            (hs, _, _, _), _ = s.get_state()
+            tg[:, st, :] = hs[gi]
+        z = torch.from_numpy(case.zeta0).to(dev)
+        g = torch.from_numpy(case.gauges).to(dev)
+        s.adjoint(nsteps, K, g, tg, z, grad=True)  # allocates the workspace
+        torch.cuda.synchronize()
+        t_fwd, t_adj = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            s.adjoint(nsteps, K, g, tg, z, grad=False)
+            torch.cuda.synchronize()
+            t_fwd.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            s.adjoint(nsteps, K, g, tg, z, grad=True)
+            torch.cuda.synchronize()
+            t_adj.append(time.perf_counter() - t0)
+    finally:
+        s.close()
+    f, a = min(t_fwd), min(t_adj)
+    return {"workload": "adjoint_bar: 1024 instances x N=4096, dx=0.04 m, h0=0.4 m, bar (toe "
+                        "~U[0.4,0.5]L) + 0.02 sin(2 pi k x/L + phi), lambda=1000, 200 steps, "
+                        "K=20, 8 gauges, transmissive (seed 5, targets seed 55)",
+            "forward_ms": round(1e3 * f, 2), "adjoint_ms": round(1e3 * a, 2),
+            "cost_ratio": round(a / f, 3),
+            "forward_cell_stages_per_s": 2.0 * wl.n_cells * nsteps / f}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +178,7 @@ def main():
     ap.add_argument("--no-per-instance", action="store_true")
     ap.add_argument("--timed-steps", type=int, default=10)
     ap.add_argument("--solver", default="auto", choices=["auto", "exact", "auto_small"])
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: a plain copy of known size, then eager steps")
     args = ap.parse_args()
@@ -227,9 +279,11 @@ def main():
                                "sample": "%d instances spread over the batch, one context each, "
                                          "eager launches, 3 steps" % ns}
         out["batched_over_per_instance"] = value / r
+    s.close()
+    if not args.no_adjoint and args.workload == "batched_bar":
+        out["adjoint"] = adjoint_cost()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl)
-    s.close()
     print(json.dumps(out))
 
 

@@ -79,7 +79,8 @@ typedef struct hsgn_ctx hsgn_ctx;
  *  offsets: host, n_inst+1 int64, offsets[0] = 0, each instance >= 4 cells.
  *  params:  host, n_inst entries (copied).
  *  d_b:     device, offsets[n_inst] doubles, or NULL if no instance uses a
- *           bed (copied; instances with has_bathymetry = 0 ignore it).
+ *           bed (copied; instances with has_bathymetry = 0 ignore it: their
+ *           bed is 0, also for hsgn_adjoint's initial-state map).
  *  hip_stream: a hipStream_t (NULL = default stream).
  * Allocates the library's state buffers and workspace on the current device.
  * The state is zero until hsgn_set_state.  Returns HSGN_EINVAL, HSGN_ENOMEM
@@ -154,6 +155,35 @@ int hsgn_plan_info(hsgn_ctx* ctx, int32_t* h_mode, int32_t* h_halo, int32_t* h_c
  * and h_count[k] its number of launches (host arrays of HSGN_NKERNEL;
  * either may be NULL).  Results are identical to hsgn_step. */
 int hsgn_step_timed(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_count);
+
+/* Discrete adjoint (reverse mode of the IMEX step, hand-written) of the
+ * gauge misfit
+ *   J_j = (1/2) sum_{s=1..nsteps} sum_{g<n_gauge} (h_j^s(gauge_jg) - target_jsg)^2
+ * of every instance j, started from rest with free surface zeta0:
+ * h = zeta0 - b, q = 0, m = h^2, W = 0.  Gradients of J_j with respect to
+ * zeta0 and to the bed b of instance j (cells of instance j).
+ *  nsteps: steps; K: steps between checkpoints (segments are recomputed
+ *    from their checkpoint during the reverse sweep, storing U^n and U^(1)
+ *    of each step);
+ *  d_gauge: device int32 [n_inst][n_gauge], cells relative to the instance;
+ *  d_target: device [n_inst][nsteps][n_gauge];
+ *  d_zeta0: device, offsets[n_inst] doubles;
+ *  d_loss: device [n_inst]; d_grad_zeta0, d_grad_b: device, offsets[n_inst]
+ *    doubles or NULL; when both are NULL only the loss is computed (no
+ *    reverse sweep, no adjoint workspace).
+ * Every instance must use a fixed step (dt_fixed > 0, t_end <= 0), so that
+ * the step map is differentiable, and every gauge cell must lie in its
+ * instance (else HSGN_EINVAL).  Forward steps use the solver plan made from
+ * the initial state (the status flags are cleared first, as by
+ * hsgn_set_state); the reverse stages solve the transposed depth system
+ * exactly (no truncation).
+ * On return the state is the state after nsteps steps and t is reset to 0.
+ * The adjoint workspace (about 120 + 8 K doubles per cell, plus
+ * 4 (nsteps/K + 1) doubles per cell of checkpoints) is kept until
+ * hsgn_destroy.  Synchronises the stream once, after the initial state. */
+int hsgn_adjoint(hsgn_ctx* ctx, int32_t nsteps, int32_t K, int32_t n_gauge,
+                 const int32_t* d_gauge, const double* d_target, const double* d_zeta0,
+                 double* d_loss, double* d_grad_zeta0, double* d_grad_b);
 
 /* Synchronise the stream and copy the per-instance status bits to host
  * (h_flags: n_inst int32, may be NULL).  Returns HSGN_OK if no instance is

@@ -91,6 +91,9 @@ def lib():
         L.or_run_loss.restype = C.c_int
         L.or_run_loss.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, C.c_int,
                                   C.c_int, ip, dp, dp]
+        L.or_run_gauges.restype = C.c_int
+        L.or_run_gauges.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, C.c_int,
+                                    C.c_int, ip, dp]
         _lib = L
     return _lib
 
@@ -224,6 +227,17 @@ def run_loss(p: Params, b, U, nsteps, gauges, targets):
     rc = lib().or_run_loss(len(U[0]), C.byref(p), _p(bb), *[_p(a) for a in U], int(nsteps),
                            len(g), g.ctypes.data_as(C.POINTER(C.c_int)), _p(tg), C.pointer(J))
     return rc, J.value, tuple(U)
+
+
+def run_gauges(p: Params, b, U, nsteps, gauges):
+    """Gauge series (nsteps, n_gauge) of h after each step.  Returns (rc, series)."""
+    U = [np.array(a, dtype=np.float64, copy=True) for a in U]
+    g = np.ascontiguousarray(gauges, dtype=np.int32)
+    out = np.zeros((int(nsteps), len(g)))
+    bb = _f(b) if b is not None else None
+    rc = lib().or_run_gauges(len(U[0]), C.byref(p), _p(bb), *[_p(a) for a in U], int(nsteps),
+                             len(g), g.ctypes.data_as(C.POINTER(C.c_int)), _p(out))
+    return rc, out
 
 
 def run_loss_cs(p: Params, b, U, nsteps, gauges, targets):

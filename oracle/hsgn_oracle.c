@@ -469,6 +469,17 @@ int FN(or_run_loss)(int n, const or_params* p, const real_t* b, real_t* h, real_
 }
 
 #ifndef OR_COMPLEX
+int or_run_gauges(int n, const or_params* p, const double* b, double* h, double* q, double* m,
+                  double* W, int nsteps, int ng, const int* gauge, double* series) {
+  double t = 0.0;
+  for (int s = 0; s < nsteps; ++s) {
+    int rc = or_step(n, p, b, h, q, m, W, &t, NULL);
+    if (rc) return rc;
+    for (int g = 0; g < ng; ++g) series[(size_t)s * ng + g] = h[gauge[g]];
+  }
+  return OR_OK;
+}
+
 int or_run_batch(int n_inst, const long long* offsets, const or_params* p,
                  const double* b, double* h, double* q, double* m, double* W,
                  double* t, int nsteps, int nthreads, int* status) {

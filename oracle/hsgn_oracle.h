@@ -74,6 +74,11 @@ int or_run_loss(int n, const or_params* p, const double* b, double* h, double* q
                 double* m, double* W, int nsteps, int ng, const int* gauge,
                 const double* target, double* loss);
 
+/* Gauge series of nsteps steps: series[s*ng + g] = h[gauge[g]] after step
+ * s + 1 (double build only).  State updated in place. */
+int or_run_gauges(int n, const or_params* p, const double* b, double* h, double* q,
+                  double* m, double* W, int nsteps, int ng, const int* gauge, double* series);
+
 /* Complex-step build (hsgn_oracle_cs.c, library liboracle_cs.so): the same
  * functions on double complex state with the suffix _cs (or_stage_cs,
  * or_step_cs, or_run_cs, or_run_loss_cs, or_tridiag_cs, or_dt_cs).  Im of the result

@@ -24,6 +24,7 @@
 #include "hsgn.h"
 #include "hsgn_kernels.hpp"
 #include "hsgn_window.hpp"
+#include "hsgn_adjoint.hpp"
 
 namespace {
 
@@ -93,6 +94,17 @@ struct hsgn_ctx {
   int n_ex_tiles = 0, n_ex_tiles_multi = 0, n_ex_multi = 0, nwin = 0;
   size_t cap_ex_tiles = 0, cap_ex_tiles_multi = 0, cap_ex_multi = 0, cap_win = 0;
   unsigned long long* d_hmax = nullptr;
+  // adjoint workspace (allocated by the first hsgn_adjoint call)
+  struct Adj {
+    int K = 0, nseg = 0;
+    int64_t nres = 0;
+    double* cells = nullptr;   // NCELL_ARR x ncell
+    double* faces = nullptr;   // NFACE_ARR x (ncell + n_inst)
+    double* tape = nullptr;    // K x 8 x ncell  (U^n, U^(1) per step)
+    double* ckpt = nullptr;    // (nseg + 1) x 4 x ncell
+    double* res = nullptr;     // n_inst x nsteps x n_gauge residuals
+    double* st = nullptr;      // 12 x ncell adjoint states + 1 x ncell bed adjoint
+  } adj;
 };
 
 namespace {
@@ -141,6 +153,9 @@ void free_all(hsgn_ctx* c) {
   for (int i = 0; i < 3; ++i)
     for (int f = 0; f < 4; ++f)
       if (c->buf[i][f]) hipFree(c->buf[i][f]);
+  double* ap[] = {c->adj.cells, c->adj.faces, c->adj.tape, c->adj.ckpt, c->adj.res, c->adj.st};
+  for (double* p : ap)
+    if (p) hipFree(p);
   if (c->ev_in) hipEventDestroy(c->ev_in);
   if (c->ev_out) hipEventDestroy(c->ev_out);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -530,6 +545,16 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
     hipError_t e = hipMemcpyAsync(c->d_b, d_b, nc * sizeof(double), hipMemcpyDeviceToDevice,
                                   c->stream);
     if (e != hipSuccess) rc = fail(c, HSGN_EHIP, "copy of b: %s", hipGetErrorString(e));
+    // the library's bed is 0 on flat instances (runs of them cleared at once)
+    for (int j = 0; j < n_inst && rc == HSGN_OK;) {
+      if (params[j].has_bathymetry) { ++j; continue; }
+      int k = j;
+      while (k < n_inst && !params[k].has_bathymetry) ++k;
+      if (hipMemsetAsync(c->d_b + offsets[j], 0, (size_t)(offsets[k] - offsets[j]) * sizeof(double),
+                         c->stream) != hipSuccess)
+        rc = fail(c, HSGN_EHIP, "hipMemsetAsync failed");
+      j = k;
+    }
   }
   if (rc == HSGN_OK) {
     for (int i = 0; i < 3 && rc == HSGN_OK; ++i)
@@ -560,29 +585,10 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   return HSGN_OK;
 }
 
-int hsgn_set_state(hsgn_ctx* c, const double* d_h, const double* d_q, const double* d_m,
-                   const double* d_W, const double* d_t) {
-  if (!c) return HSGN_EINVAL;
-  if (!d_h || !d_q) return fail(c, HSGN_EINVAL, "hsgn_set_state: h and q are required");
-  int rc = enter(c);
-  if (rc) return rc;
-  const size_t bytes = (size_t)c->ncell * sizeof(double);
+// Clear the status flags, compute the speed bound and depth maximum of the
+// current state, and make the solver plan from them (synchronises the stream).
+static int reset_and_plan(hsgn_ctx* c) {
   double** U = c->buf[c->cur];
-  HIPCHK(c, hipMemcpyAsync(U[0], d_h, bytes, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(U[1], d_q, bytes, hipMemcpyDeviceToDevice, c->stream));
-  if (d_m) HIPCHK(c, hipMemcpyAsync(U[2], d_m, bytes, hipMemcpyDeviceToDevice, c->stream));
-  if (d_W) HIPCHK(c, hipMemcpyAsync(U[3], d_W, bytes, hipMemcpyDeviceToDevice, c->stream));
-  if (!d_m || !d_W) {
-    const int64_t nb = (c->ncell + 255) / 256;
-    hipLaunchKernelGGL(hsgn::k_default_mW, dim3((unsigned)nb), dim3(256), 0, c->stream, c->ncell,
-                       U[0], U[2], U[3], d_m ? 0 : 1, d_W ? 0 : 1);
-  }
-  if (d_t) {
-    HIPCHK(c, hipMemcpyAsync(c->d_t, d_t, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice,
-                             c->stream));
-  } else {
-    HIPCHK(c, hipMemsetAsync(c->d_t, 0, c->n_inst * sizeof(double), c->stream));
-  }
   const int nb = (c->n_inst + 255) / 256;
   hipLaunchKernelGGL(hsgn::k_fill_i32, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_status,
                      0);
@@ -608,7 +614,33 @@ int hsgn_set_state(hsgn_ctx* c, const double* d_h, const double* d_q, const doub
     std::memcpy(&c->h_smax[j], &sm[j], sizeof(double));
     std::memcpy(&c->h_hmax[j], &hm[j], sizeof(double));
   }
-  rc = make_plan(c);
+  return make_plan(c);
+}
+
+int hsgn_set_state(hsgn_ctx* c, const double* d_h, const double* d_q, const double* d_m,
+                   const double* d_W, const double* d_t) {
+  if (!c) return HSGN_EINVAL;
+  if (!d_h || !d_q) return fail(c, HSGN_EINVAL, "hsgn_set_state: h and q are required");
+  int rc = enter(c);
+  if (rc) return rc;
+  const size_t bytes = (size_t)c->ncell * sizeof(double);
+  double** U = c->buf[c->cur];
+  HIPCHK(c, hipMemcpyAsync(U[0], d_h, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(U[1], d_q, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (d_m) HIPCHK(c, hipMemcpyAsync(U[2], d_m, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (d_W) HIPCHK(c, hipMemcpyAsync(U[3], d_W, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (!d_m || !d_W) {
+    const int64_t nb = (c->ncell + 255) / 256;
+    hipLaunchKernelGGL(hsgn::k_default_mW, dim3((unsigned)nb), dim3(256), 0, c->stream, c->ncell,
+                       U[0], U[2], U[3], d_m ? 0 : 1, d_W ? 0 : 1);
+  }
+  if (d_t) {
+    HIPCHK(c, hipMemcpyAsync(c->d_t, d_t, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice,
+                             c->stream));
+  } else {
+    HIPCHK(c, hipMemsetAsync(c->d_t, 0, c->n_inst * sizeof(double), c->stream));
+  }
+  rc = reset_and_plan(c);
   if (rc) return rc;
   return leave(c);
 }
@@ -770,3 +802,257 @@ void hsgn_destroy(hsgn_ctx* c) {
 }
 
 }  // extern "C"
+
+namespace {
+
+// Adjoint helper kernels (one thread per cell or per instance).
+__global__ void k_state_from_surface(int64_t ncell, const double* __restrict__ zeta,
+                                     const double* __restrict__ b, double* __restrict__ h,
+                                     double* __restrict__ q, double* __restrict__ m,
+                                     double* __restrict__ W) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncell) return;
+  const double hh = zeta[i] - (b ? b[i] : 0.0);
+  h[i] = hh;
+  q[i] = 0.0;
+  m[i] = hh * hh;
+  W[i] = 0.0;
+}
+
+__global__ void k_fill_f64(int64_t n, double* __restrict__ p, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// loss after step s: (1/2) sum_g (h(gauge) - target)^2, residuals kept
+__global__ void k_gauge_fwd(int n_inst, const InstDesc* __restrict__ inst, int ng,
+                            const int32_t* __restrict__ gauge, const double* __restrict__ target,
+                            int nsteps, int s, const double* __restrict__ h,
+                            double* __restrict__ loss, double* __restrict__ res) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_inst) return;
+  const int64_t off = inst[j].off;
+  double acc = loss[j];
+  for (int g = 0; g < ng; ++g) {
+    const int64_t k = ((int64_t)j * nsteps + s) * ng + g;
+    const double r = h[off + gauge[(int64_t)j * ng + g]] - target[k];
+    res[k] = r;
+    acc += 0.5 * r * r;
+  }
+  loss[j] = acc;
+}
+
+__global__ void k_gauge_adj(int n_inst, const InstDesc* __restrict__ inst, int ng,
+                            const int32_t* __restrict__ gauge, int nsteps, int s,
+                            const double* __restrict__ res, double* __restrict__ ah) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_inst) return;
+  const int64_t off = inst[j].off;
+  for (int g = 0; g < ng; ++g)
+    ah[off + gauge[(int64_t)j * ng + g]] += res[((int64_t)j * nsteps + s) * ng + g];
+}
+
+// gradient of the initial-state map h = zeta - b, q = 0, m = h^2, W = 0
+// (one workgroup per instance; flat instances have no bed gradient)
+__global__ void k_adj_surface(const InstDesc* __restrict__ inst, const double* __restrict__ zeta,
+                              const double* __restrict__ b, const double* __restrict__ ah,
+                              const double* __restrict__ am, const double* __restrict__ gb_dyn,
+                              double* __restrict__ gz, double* __restrict__ gb) {
+  const InstDesc I = inst[blockIdx.x];
+  const bool bed = b && I.has_b;
+  for (int k = threadIdx.x; k < I.n; k += blockDim.x) {
+    const int64_t i = I.off + k;
+    const double hh = zeta[i] - (b ? b[i] : 0.0);
+    const double dz = ah[i] + 2.0 * hh * am[i];
+    if (gz) gz[i] = dz;
+    if (gb) gb[i] = bed ? gb_dyn[i] - dz : 0.0;
+  }
+}
+
+int adj_alloc(hsgn_ctx* c, int K, int nseg, int64_t nres, bool grad) {
+  auto& a = c->adj;
+  const size_t nc = (size_t)c->ncell, nfc = nc + (size_t)c->n_inst;
+  if (nres > a.nres) {
+    if (a.res) hipFree(a.res);
+    a.res = nullptr;
+    a.nres = 0;
+    int rc = dmalloc(c, &a.res, (size_t)nres);
+    if (rc) return rc;
+    a.nres = nres;
+  }
+  if (!grad) return HSGN_OK;
+  if (!a.cells) {
+    int rc = dmalloc(c, &a.cells, hsgn::adj::NCELL_ARR * nc);
+    if (!rc) rc = dmalloc(c, &a.faces, hsgn::adj::NFACE_ARR * nfc);
+    if (!rc) rc = dmalloc(c, &a.st, 13 * nc);
+    if (rc) return rc;
+  }
+  if (K > a.K) {
+    if (a.tape) hipFree(a.tape);
+    a.tape = nullptr;
+    a.K = 0;
+    int rc = dmalloc(c, &a.tape, (size_t)K * 8 * nc);
+    if (rc) return rc;
+    a.K = K;
+  }
+  if (nseg > a.nseg) {
+    if (a.ckpt) hipFree(a.ckpt);
+    a.ckpt = nullptr;
+    a.nseg = 0;
+    int rc = dmalloc(c, &a.ckpt, (size_t)(nseg + 1) * 4 * nc);
+    if (rc) return rc;
+    a.nseg = nseg;
+  }
+  return HSGN_OK;
+}
+
+int copy_state(hsgn_ctx* c, double* const* dst, double* const* src) {
+  const size_t bytes = (size_t)c->ncell * sizeof(double);
+  for (int f = 0; f < 4; ++f)
+    HIPCHK(c, hipMemcpyAsync(dst[f], src[f], bytes, hipMemcpyDeviceToDevice, c->stream));
+  return HSGN_OK;
+}
+
+}  // namespace
+
+extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
+                            const int32_t* d_gauge, const double* d_target,
+                            const double* d_zeta0, double* d_loss, double* d_grad_zeta0,
+                            double* d_grad_b) {
+  if (!c) return HSGN_EINVAL;
+  if (nsteps < 1 || K < 1 || ng < 1 || !d_gauge || !d_target || !d_zeta0 || !d_loss)
+    return fail(c, HSGN_EINVAL, "hsgn_adjoint: bad arguments");
+  for (int j = 0; j < c->n_inst; ++j) {
+    if (!(c->params[j].dt_fixed > 0) || c->params[j].t_end > 0)
+      return fail(c, HSGN_EINVAL,
+                  "hsgn_adjoint: instance %d needs dt_fixed > 0 and no t_end (the step map "
+                  "must not depend on the state through dt)", j);
+  }
+  {  // gauge cells must lie inside their instance
+    std::vector<int32_t> hg((size_t)c->n_inst * ng);
+    HIPCHK(c, hipMemcpy(hg.data(), d_gauge, hg.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int j = 0; j < c->n_inst; ++j) {
+      const int64_t n = c->offsets[j + 1] - c->offsets[j];
+      for (int g = 0; g < ng; ++g) {
+        const int32_t v = hg[(size_t)j * ng + g];
+        if (v < 0 || v >= n)
+          return fail(c, HSGN_EINVAL, "hsgn_adjoint: gauge %d of instance %d is cell %d (n = %lld)",
+                      g, j, (int)v, (long long)n);
+      }
+    }
+  }
+  if (K > nsteps) K = nsteps;
+  const int nseg = (nsteps + K - 1) / K;
+  const int64_t nres = (int64_t)c->n_inst * nsteps * ng;
+  const bool grad = d_grad_zeta0 || d_grad_b;
+  int rc = adj_alloc(c, K, nseg, nres, grad);
+  if (rc) return rc;
+  rc = enter(c);
+  if (rc) return rc;
+  auto& a = c->adj;
+  const size_t nc = (size_t)c->ncell;
+  const unsigned nbc = (unsigned)((c->ncell + 255) / 256);
+  const unsigned nbi = (unsigned)((c->n_inst + 255) / 256);
+  double** U = nullptr;
+  auto ckpt = [&](int k, int f) { return a.ckpt + ((size_t)k * 4 + f) * nc; };
+  auto tape = [&](int k, int f) { return a.tape + ((size_t)k * 8 + f) * nc; };
+  double* AS[4];
+  double* A1[4];
+  double* ANP[4];
+  for (int f = 0; f < 4; ++f) {
+    AS[f] = a.st + (size_t)f * nc;
+    A1[f] = a.st + (size_t)(4 + f) * nc;
+    ANP[f] = a.st + (size_t)(8 + f) * nc;
+  }
+  double* GB = a.st + (size_t)12 * nc;
+
+  // ---- forward: initial state from the surface, checkpoints, loss
+  U = c->buf[c->cur];
+  hipLaunchKernelGGL(k_state_from_surface, dim3(nbc), dim3(256), 0, c->stream, c->ncell, d_zeta0,
+                     c->d_b, U[0], U[1], U[2], U[3]);
+  HIPCHK(c, hipMemsetAsync(c->d_t, 0, c->n_inst * sizeof(double), c->stream));
+  rc = reset_and_plan(c);  // flags, speed bound and solver plan of the initial state
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_fill_f64, dim3(nbi), dim3(256), 0, c->stream, (int64_t)c->n_inst, d_loss, 0.0);
+  for (int s = 0; s < nsteps; ++s) {
+    if (grad && s % K == 0) {
+      double* dst[4] = {ckpt(s / K, 0), ckpt(s / K, 1), ckpt(s / K, 2), ckpt(s / K, 3)};
+      rc = copy_state(c, dst, c->buf[c->cur]);
+      if (rc) return rc;
+    }
+    rc = enqueue_step(c);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_gauge_fwd, dim3(nbi), dim3(256), 0, c->stream, c->n_inst, c->d_inst, ng,
+                       d_gauge, d_target, nsteps, s, c->buf[c->cur][0], d_loss, a.res);
+  }
+  if (!grad) {  // loss only
+    hipLaunchKernelGGL(k_fill_f64, dim3(nbi), dim3(256), 0, c->stream, (int64_t)c->n_inst,
+                       c->d_t, 0.0);
+    HIPCHK(c, hipGetLastError());
+    return leave(c);
+  }
+  {  // the final state and time, restored at the end
+    double* dst[4] = {ckpt(nseg, 0), ckpt(nseg, 1), ckpt(nseg, 2), ckpt(nseg, 3)};
+    rc = copy_state(c, dst, c->buf[c->cur]);
+    if (rc) return rc;
+  }
+  // ---- reverse
+  for (int f = 0; f < 4; ++f)
+    hipLaunchKernelGGL(k_fill_f64, dim3(nbc), dim3(256), 0, c->stream, (int64_t)c->ncell, AS[f], 0.0);
+  hipLaunchKernelGGL(k_fill_f64, dim3(nbc), dim3(256), 0, c->stream, (int64_t)c->ncell, GB, 0.0);
+  hsgn::AdjStageArgs P;
+  std::memset(&P, 0, sizeof P);
+  P.inst = c->d_inst;
+  P.dt = c->d_dt;
+  P.b = c->d_b;
+  P.gb = GB;
+  for (int k = 0; k < hsgn::adj::NCELL_ARR; ++k) P.arr.c[k] = a.cells + (size_t)k * nc;
+  for (int k = 0; k < hsgn::adj::NFACE_ARR; ++k)
+    P.arr.f[k] = a.faces + (size_t)k * (nc + (size_t)c->n_inst);
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int s0 = seg * K;
+    const int ks = std::min(K, nsteps - s0);
+    {
+      double* src[4] = {ckpt(seg, 0), ckpt(seg, 1), ckpt(seg, 2), ckpt(seg, 3)};
+      rc = copy_state(c, c->buf[c->cur], src);
+      if (rc) return rc;
+    }
+    for (int k = 0; k < ks; ++k) {  // recompute the segment, taping U^n and U^(1)
+      double* tn[4] = {tape(k, 0), tape(k, 1), tape(k, 2), tape(k, 3)};
+      rc = copy_state(c, tn, c->buf[c->cur]);
+      if (rc) return rc;
+      rc = enqueue_step(c);
+      if (rc) return rc;
+      double* t1[4] = {tape(k, 4), tape(k, 5), tape(k, 6), tape(k, 7)};
+      rc = copy_state(c, t1, c->buf[c->s1]);
+      if (rc) return rc;
+    }
+    for (int k = ks - 1; k >= 0; --k) {
+      hipLaunchKernelGGL(k_gauge_adj, dim3(nbi), dim3(256), 0, c->stream, c->n_inst, c->d_inst,
+                         ng, d_gauge, nsteps, s0 + k, a.res, AS[0]);
+      for (int f = 0; f < 4; ++f) {
+        P.un[f] = tape(k, f);
+        P.u1[f] = tape(k, 4 + f);
+        P.abar[f] = AS[f];
+        P.out1[f] = A1[f];
+        P.outn[f] = ANP[f];
+      }
+      hipLaunchKernelGGL((hsgn::k_adj_stage<256, 2>), dim3(c->n_inst), dim3(256), 0, c->stream, P);
+      for (int f = 0; f < 4; ++f) P.abar[f] = A1[f];
+      hipLaunchKernelGGL((hsgn::k_adj_stage<256, 1>), dim3(c->n_inst), dim3(256), 0, c->stream, P);
+      for (int f = 0; f < 4; ++f) std::swap(AS[f], ANP[f]);
+    }
+  }
+  // ---- gradients of the initial-state map; restore the final state
+  hipLaunchKernelGGL(k_adj_surface, dim3(c->n_inst), dim3(256), 0, c->stream, c->d_inst, d_zeta0,
+                     c->d_b, AS[0], AS[2], GB, d_grad_zeta0, d_grad_b);
+  {
+    double* src[4] = {ckpt(nseg, 0), ckpt(nseg, 1), ckpt(nseg, 2), ckpt(nseg, 3)};
+    rc = copy_state(c, c->buf[c->cur], src);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_fill_f64, dim3(nbi), dim3(256), 0, c->stream, (int64_t)c->n_inst, c->d_t,
+                     0.0);
+  HIPCHK(c, hipGetLastError());
+  return leave(c);
+}

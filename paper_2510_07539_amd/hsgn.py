@@ -59,6 +59,8 @@ def lib():
         L.hsgn_set_solver.argtypes = [vp, C.c_int32]
         L.hsgn_plan_info.restype = C.c_int
         L.hsgn_plan_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.hsgn_adjoint.restype = C.c_int
+        L.hsgn_adjoint.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp]
         L.hsgn_status.restype = C.c_int
         L.hsgn_status.argtypes = [vp, C.POINTER(C.c_int32)]
         L.hsgn_last_error.restype = C.c_char_p
@@ -174,6 +176,27 @@ class Solver:
         self._check(lib().hsgn_step_timed(self._h, int(nsteps), ms, cnt), "hsgn_step_timed")
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}
 
+    def adjoint(self, nsteps, K, gauges, targets, zeta0, grad=True):
+        """Gauge-misfit loss per instance and its gradients with respect to the
+        initial free surface zeta0 and the bed (hand-written discrete adjoint,
+        checkpoints every K steps).  gauges: int32 (n_inst, n_gauge) cells
+        relative to their instance; targets: (n_inst, nsteps, n_gauge);
+        zeta0: (ncell,).  Returns (loss, grad_zeta0, grad_b); with
+        grad=False only the loss is computed and the gradients are None."""
+        dev = self.device
+        g = gauges.to(dev, torch.int32).contiguous()
+        tg = targets.to(dev, torch.float64).contiguous()
+        z = zeta0.to(dev, torch.float64).contiguous()
+        assert g.shape[0] == self.n_inst and tg.shape == (self.n_inst, nsteps, g.shape[1])
+        loss = torch.empty(self.n_inst, dtype=torch.float64, device=dev)
+        gz = torch.empty(self.ncell, dtype=torch.float64, device=dev) if grad else None
+        gb = torch.empty(self.ncell, dtype=torch.float64, device=dev) if grad else None
+        self._keep_adj = (g, tg, z)
+        self._check(lib().hsgn_adjoint(self._h, int(nsteps), int(K), int(g.shape[1]),
+                                       C.c_void_p(g.data_ptr()), _ptr(tg), _ptr(z), _ptr(loss),
+                                       _ptr(gz), _ptr(gb)), "hsgn_adjoint")
+        return loss, gz, gb
+
     def status(self):
         f = np.zeros(self.n_inst, dtype=np.int32)
         rc = lib().hsgn_status(self._h, f.ctypes.data_as(C.POINTER(C.c_int32)))
@@ -189,3 +212,31 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+class HsgnAdjointFn(torch.autograd.Function):
+    """loss = HsgnAdjointFn.apply(zeta0, b, spec): per-instance gauge misfit
+    of a batch started from rest with free surface zeta0 over bed b (both
+    float64 tensors on the GPU).  spec: dict with offsets, params (list of
+    dicts, dt_fixed > 0), nsteps, K, gauges, targets.  The backward pass uses
+    the gradients the hand-written adjoint computed with the loss."""
+
+    @staticmethod
+    def forward(ctx, zeta0, b, spec):
+        s = Solver(spec["offsets"], spec["params"], b.detach(), device=zeta0.device)
+        try:
+            loss, gz, gb = s.adjoint(spec["nsteps"], spec["K"], spec["gauges"], spec["targets"],
+                                     zeta0.detach())
+        finally:
+            s.close()
+        offs = torch.as_tensor(np.asarray(spec["offsets"]), device=zeta0.device)
+        inst_of_cell = torch.repeat_interleave(torch.arange(len(offs) - 1, device=zeta0.device),
+                                               offs[1:] - offs[:-1])
+        ctx.save_for_backward(gz, gb, inst_of_cell)
+        return loss
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        gz, gb, inst_of_cell = ctx.saved_tensors
+        w = grad_loss[inst_of_cell]
+        return w * gz, w * gb, None

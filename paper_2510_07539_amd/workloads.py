@@ -226,3 +226,54 @@ def concat(name, wls, nsteps=None) -> Workload:
             d.update(b=b, h=U[0], q=U[1], m=U[2], W=U[3])
             parts.append(d)
     return _pack(name, parts, nsteps if nsteps is not None else wls[0].nsteps)
+
+
+@dataclass
+class AdjointCase:
+    """Inputs of the gradient workload: a batch released from rest over a
+    bar-plus-sinusoid bed, gauges, and the perturbed surface that defines the
+    targets (the targets themselves come from running the forward solver)."""
+    wl: Workload           # instances (params with dt_fixed) and bed; state = base surface at rest
+    zeta0: np.ndarray      # base free surface
+    zeta_target: np.ndarray  # perturbed free surface the targets are generated from
+    gauges: np.ndarray     # int32 (n_inst, n_gauge), instance-relative cells
+    nsteps: int
+    K: int
+
+
+def adjoint_bar(n_inst=1024, N=4096, dx=0.04, h0=0.4, lam=1000.0, seed=5, seed_target=55,
+                nsteps=200, K=20, n_gauge=8, cfl=0.9, g=G) -> AdjointCase:
+    """Gradient workload: bed b = trapezoidal bar (toe ~ U[0.4, 0.5] L) +
+    0.02 sin(2 pi k_s x / L + phi_s), k_s ~ U{2..8}, phi_s ~ U[0, 2 pi)
+    (default_rng(seed), drawn in that order per instance); base surface
+    zeta0 = h0 + 0.05 exp(-(x - 0.2 L)^2 / 4) released from rest; targets from
+    zeta0 + sum_{k=1..8} c_k sin(2 pi k x / L + psi_k), c_k ~ U[0, 2e-3],
+    psi_k ~ U[0, 2 pi) (default_rng(seed_target)); gauges at cells
+    floor((g + 1/2) N / n_gauge); fixed dt = cfl dx / max sqrt(g h) of the base
+    state; transmissive."""
+    rng = np.random.default_rng(seed)
+    rng_t = np.random.default_rng(seed_target)
+    L = N * dx
+    x = (np.arange(N) + 0.5) * dx
+    parts, zs, zts = [], [], []
+    for j in range(n_inst):
+        toe = rng.uniform(0.4, 0.5) * L
+        ks = int(rng.integers(2, 9))
+        ph = rng.uniform(0.0, 2.0 * np.pi)
+        b = trapezoid_bar(x, toe) + 0.02 * np.sin(2.0 * np.pi * ks * x / L + ph)
+        z = h0 + 0.05 * np.exp(-((x - 0.2 * L) ** 2) / 4.0)
+        ck = rng_t.uniform(0.0, 2e-3, size=8)
+        psi = rng_t.uniform(0.0, 2.0 * np.pi, size=8)
+        zt = z.copy()
+        for k in range(8):
+            zt += ck[k] * np.sin(2.0 * np.pi * (k + 1) * x / L + psi[k])
+        h = z - b
+        dt = cfl * dx / np.sqrt(g * h.max())
+        zero = np.zeros(N)
+        parts.append(_part(N, dx, lam, BC_TRANSMISSIVE, h, zero, zero, b=b, dt_fixed=dt, g=g))
+        zs.append(z)
+        zts.append(zt)
+    wl = _pack("adjoint_bar", parts, nsteps, dict(seed=seed))
+    gauges = np.array([[int((gi + 0.5) * N / n_gauge) for gi in range(n_gauge)]] * n_inst,
+                      dtype=np.int32)
+    return AdjointCase(wl, np.concatenate(zs), np.concatenate(zts), gauges, nsteps, K)

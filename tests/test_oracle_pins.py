@@ -429,3 +429,21 @@ def test_complex_step_build_differentiates_the_oracle():
         fd = lambda e: (f(e) - f(-e)) / (2 * e)
         d_rich = (4 * fd(1e-4) - fd(2e-4)) / 3
         assert abs(d_cs - d_rich) <= 1e-7 * abs(d_cs), (kind, d_cs, d_rich)
+
+
+def test_gauge_series_consistent_with_run_and_loss():
+    """The recorded gauge series is the state the plain run reaches, and its
+    misfit against any targets is the loss the loss routine accumulates."""
+    wl = WL.batched_bar(n_inst=1, seed=6, n_lo=200, n_hi=200)
+    n, prm, b, U0 = wl.instance(0)
+    prm = dict(prm, dt_fixed=0.005)
+    p = O.make_params(**prm)
+    g = np.array([3, n // 2, n - 1])
+    rc, ser = O.run_gauges(p, b, U0, 9, g)
+    assert rc == 0 and ser.shape == (9, 3)
+    for k in (1, 4, 9):
+        _, Uk, _ = O.run(p, b, U0, 0.0, k)
+        assert np.array_equal(ser[k - 1], Uk[0][g])
+    tgt = np.random.default_rng(2).uniform(0.3, 0.5, size=(9, 3))
+    _, J, _ = O.run_loss(p, b, U0, 9, g, tgt)
+    assert J == pytest.approx(0.5 * np.sum((ser - tgt) ** 2), rel=1e-14)
