@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "hsgn.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "hsgn_kernels.hpp"), os.path.join(ROOT, "include", "hsgn.h")]
+DEPS = [os.path.join(HERE, "csrc", f) for f in sorted(os.listdir(os.path.join(HERE, "csrc")))
+        if f.endswith((".hip", ".hpp"))] + [os.path.join(ROOT, "include", "hsgn.h")]
 LIB = os.path.join(HERE, "libhsgn.so")
 
 HIPCC_FLAGS = [

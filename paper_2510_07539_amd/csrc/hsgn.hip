@@ -34,6 +34,7 @@ constexpr int kTileMax = kNT * kKMAX;
 constexpr int kNTR = 256;     // threads of the reduced-system solve
 constexpr int kWK = 8;        // rows per thread of the windowed kernel
 constexpr double kWinMargin = 2.0;  // safety factor on the decay estimate
+constexpr int kAdjNT = 256;    // threads (cell positions) per reverse-stage tile
 
 using hsgn::InstDesc;
 using hsgn::StageArgs;
@@ -84,6 +85,7 @@ struct hsgn_ctx {
   // execution plan (rebuilt by hsgn_set_state / hsgn_set_solver)
   int32_t solver = HSGN_SOLVER_AUTO;
   int win_nt = 512;
+  int win_k = kWK;  // rows per thread of the windowed kernel (4 or 8)
   std::vector<double> h_smax, h_hmax;  // speed bound and depth maximum of the loaded state
   std::vector<int32_t> h_mode;         // per instance: 0 window, 1 two-pass
   std::vector<int32_t> h_halo;         // per instance window halo L (0 if none)
@@ -98,12 +100,13 @@ struct hsgn_ctx {
   struct Adj {
     int K = 0, nseg = 0;
     int64_t nres = 0;
-    double* cells = nullptr;   // NCELL_ARR x ncell
-    double* faces = nullptr;   // NFACE_ARR x (ncell + n_inst)
+    double* sys = nullptr;     // 9 x ncell: transposed rows, rhs, lam, solver scratch
     double* tape = nullptr;    // K x 8 x ncell  (U^n, U^(1) per step)
     double* ckpt = nullptr;    // (nseg + 1) x 4 x ncell
     double* res = nullptr;     // n_inst x nsteps x n_gauge residuals
     double* st = nullptr;      // 12 x ncell adjoint states + 1 x ncell bed adjoint
+    hsgn::adj::TileA* tiles = nullptr;
+    int ntiles = 0;
   } adj;
 };
 
@@ -153,9 +156,10 @@ void free_all(hsgn_ctx* c) {
   for (int i = 0; i < 3; ++i)
     for (int f = 0; f < 4; ++f)
       if (c->buf[i][f]) hipFree(c->buf[i][f]);
-  double* ap[] = {c->adj.cells, c->adj.faces, c->adj.tape, c->adj.ckpt, c->adj.res, c->adj.st};
+  double* ap[] = {c->adj.sys, c->adj.tape, c->adj.ckpt, c->adj.res, c->adj.st};
   for (double* p : ap)
     if (p) hipFree(p);
+  if (c->adj.tiles) hipFree(c->adj.tiles);
   if (c->ev_in) hipEventDestroy(c->ev_in);
   if (c->ev_out) hipEventDestroy(c->ev_out);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -215,6 +219,17 @@ StageArgs stage_args(hsgn_ctx* c, int stage) {
 
 // Enqueue one IMEX step (no synchronisation), then rotate the buffers.
 // With `tm`, every launch is bracketed by a pair of events (kind k).
+template <int NT, int K>
+void launch_win(hsgn_ctx* c, const hsgn::WinArgs& w, int grid, int stage) {
+  if (c->any_b) {
+    if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<NT, K, true, 1>), dim3(grid), dim3(NT), 0, c->stream, w);
+    else hipLaunchKernelGGL((hsgn::k_win<NT, K, true, 2>), dim3(grid), dim3(NT), 0, c->stream, w);
+  } else {
+    if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<NT, K, false, 1>), dim3(grid), dim3(NT), 0, c->stream, w);
+    else hipLaunchKernelGGL((hsgn::k_win<NT, K, false, 2>), dim3(grid), dim3(NT), 0, c->stream, w);
+  }
+}
+
 int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* tm = nullptr) {
   auto mark = [&](int kind, bool begin) {
     if (!tm) return;
@@ -262,23 +277,9 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
       w.xcd_stride = (c->nwin + 7) / 8;
       const int grid = 8 * w.xcd_stride;
       mark(stage == 1 ? HSGN_K_WIN1 : HSGN_K_WIN2, true);
-      if (c->win_nt == 512) {
-        if (c->any_b) {
-          if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<512, kWK, true, 1>), dim3(grid), dim3(512), 0, c->stream, w);
-          else hipLaunchKernelGGL((hsgn::k_win<512, kWK, true, 2>), dim3(grid), dim3(512), 0, c->stream, w);
-        } else {
-          if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<512, kWK, false, 1>), dim3(grid), dim3(512), 0, c->stream, w);
-          else hipLaunchKernelGGL((hsgn::k_win<512, kWK, false, 2>), dim3(grid), dim3(512), 0, c->stream, w);
-        }
-      } else {
-        if (c->any_b) {
-          if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<256, kWK, true, 1>), dim3(grid), dim3(256), 0, c->stream, w);
-          else hipLaunchKernelGGL((hsgn::k_win<256, kWK, true, 2>), dim3(grid), dim3(256), 0, c->stream, w);
-        } else {
-          if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<256, kWK, false, 1>), dim3(grid), dim3(256), 0, c->stream, w);
-          else hipLaunchKernelGGL((hsgn::k_win<256, kWK, false, 2>), dim3(grid), dim3(256), 0, c->stream, w);
-        }
-      }
+      if (c->win_nt == 512 && c->win_k == 8) launch_win<512, 8>(c, w, grid, stage);
+      else if (c->win_nt == 512) launch_win<512, 4>(c, w, grid, stage);
+      else launch_win<256, 8>(c, w, grid, stage);
       mark(stage == 1 ? HSGN_K_WIN1 : HSGN_K_WIN2, false);
     }
   }
@@ -334,7 +335,7 @@ int make_plan(hsgn_ctx* c) {
   std::vector<TileDesc> ex_all, ex_multi;
   std::vector<int32_t> ex_inst;
   std::vector<WinDesc> win;
-  const int WN = c->win_nt * kWK;
+  const int WN = c->win_nt * c->win_k;
   const int Lmax = WN / 4;
   c->h_mode.assign(c->n_inst, 1);
   c->h_halo.assign(c->n_inst, 0);
@@ -672,10 +673,12 @@ int hsgn_get_dt(hsgn_ctx* c, double* d_dt) {
 
 int hsgn_set_solver(hsgn_ctx* c, int32_t mode) {
   if (!c) return HSGN_EINVAL;
-  if (mode != HSGN_SOLVER_AUTO && mode != HSGN_SOLVER_EXACT && mode != HSGN_SOLVER_AUTO_SMALL)
+  if (mode != HSGN_SOLVER_AUTO && mode != HSGN_SOLVER_EXACT && mode != HSGN_SOLVER_AUTO_SMALL &&
+      mode != HSGN_SOLVER_AUTO_K4)
     return fail(c, HSGN_EINVAL, "hsgn_set_solver: unknown mode %d", mode);
-  c->solver = mode == HSGN_SOLVER_AUTO_SMALL ? HSGN_SOLVER_AUTO : mode;
+  c->solver = mode == HSGN_SOLVER_EXACT ? HSGN_SOLVER_EXACT : HSGN_SOLVER_AUTO;
   c->win_nt = mode == HSGN_SOLVER_AUTO_SMALL ? 256 : 512;
+  c->win_k = mode == HSGN_SOLVER_AUTO_K4 ? 4 : kWK;
   int rc = enter(c);
   if (rc) return rc;
   rc = make_plan(c);
@@ -691,7 +694,7 @@ int hsgn_plan_info(hsgn_ctx* c, int32_t* h_mode, int32_t* h_halo, int32_t* h_cou
     h_counts[0] = c->nwin;
     h_counts[1] = c->n_ex_tiles;
     h_counts[2] = c->n_ex_multi;
-    h_counts[3] = c->win_nt * kWK;
+    h_counts[3] = c->win_nt * c->win_k;
   }
   return HSGN_OK;
 }
@@ -871,7 +874,7 @@ __global__ void k_adj_surface(const InstDesc* __restrict__ inst, const double* _
 
 int adj_alloc(hsgn_ctx* c, int K, int nseg, int64_t nres, bool grad) {
   auto& a = c->adj;
-  const size_t nc = (size_t)c->ncell, nfc = nc + (size_t)c->n_inst;
+  const size_t nc = (size_t)c->ncell;
   if (nres > a.nres) {
     if (a.res) hipFree(a.res);
     a.res = nullptr;
@@ -881,11 +884,30 @@ int adj_alloc(hsgn_ctx* c, int K, int nseg, int64_t nres, bool grad) {
     a.nres = nres;
   }
   if (!grad) return HSGN_OK;
-  if (!a.cells) {
-    int rc = dmalloc(c, &a.cells, hsgn::adj::NCELL_ARR * nc);
-    if (!rc) rc = dmalloc(c, &a.faces, hsgn::adj::NFACE_ARR * nfc);
+  if (!a.sys) {
+    int rc = dmalloc(c, &a.sys, 9 * nc);
     if (!rc) rc = dmalloc(c, &a.st, 13 * nc);
     if (rc) return rc;
+    // tiles of the reverse stage: cores of at most kAdjNT - 2H cells
+    std::vector<hsgn::adj::TileA> tl;
+    const int C = kAdjNT - 2 * hsgn::adj::H;
+    for (int j = 0; j < c->n_inst; ++j) {
+      const int n = (int)(c->offsets[j + 1] - c->offsets[j]);
+      const int nt = (n + C - 1) / C;
+      for (int k = 0; k < nt; ++k) {
+        hsgn::adj::TileA t;
+        t.inst = j;
+        t.ts = (int)((int64_t)k * n / nt);
+        t.te = (int)((int64_t)(k + 1) * n / nt);
+        t.pad = 0;
+        tl.push_back(t);
+      }
+    }
+    rc = dmalloc(c, &a.tiles, tl.size());
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpy(a.tiles, tl.data(), tl.size() * sizeof(hsgn::adj::TileA),
+                        hipMemcpyHostToDevice));
+    a.ntiles = (int)tl.size();
   }
   if (K > a.K) {
     if (a.tape) hipFree(a.tape);
@@ -1000,15 +1022,32 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   for (int f = 0; f < 4; ++f)
     hipLaunchKernelGGL(k_fill_f64, dim3(nbc), dim3(256), 0, c->stream, (int64_t)c->ncell, AS[f], 0.0);
   hipLaunchKernelGGL(k_fill_f64, dim3(nbc), dim3(256), 0, c->stream, (int64_t)c->ncell, GB, 0.0);
-  hsgn::AdjStageArgs P;
+  hsgn::AdjTileArgs P;
   std::memset(&P, 0, sizeof P);
   P.inst = c->d_inst;
+  P.tiles = a.tiles;
   P.dt = c->d_dt;
   P.b = c->d_b;
   P.gb = GB;
-  for (int k = 0; k < hsgn::adj::NCELL_ARR; ++k) P.arr.c[k] = a.cells + (size_t)k * nc;
-  for (int k = 0; k < hsgn::adj::NFACE_ARR; ++k)
-    P.arr.f[k] = a.faces + (size_t)k * (nc + (size_t)c->n_inst);
+  auto sysa = [&](int k) { return a.sys + (size_t)k * nc; };
+  P.lot = sysa(0);
+  P.dit = sysa(1);
+  P.upt = sysa(2);
+  P.hba = sysa(3);
+  P.lam = sysa(4);
+  hsgn::AdjSolveArgs Q;
+  Q.inst = c->d_inst;
+  Q.dt = c->d_dt;
+  Q.lot = sysa(0);
+  Q.dit = sysa(1);
+  Q.upt = sysa(2);
+  Q.hba = sysa(3);
+  Q.lam = sysa(4);
+  Q.scp = sysa(5);
+  Q.sy = sysa(6);
+  Q.sv = sysa(7);
+  Q.sw = sysa(8);
+  const dim3 gt(a.ntiles), bt(kAdjNT);
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int s0 = seg * K;
     const int ks = std::min(K, nsteps - s0);
@@ -1033,13 +1072,23 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
       for (int f = 0; f < 4; ++f) {
         P.un[f] = tape(k, f);
         P.u1[f] = tape(k, 4 + f);
+      }
+      // stage 2: hbar is the depth of U^{n+1}
+      P.hbar = (k + 1 < ks) ? tape(k + 1, 0) : ckpt(seg + 1, 0);
+      for (int f = 0; f < 4; ++f) {
         P.abar[f] = AS[f];
         P.out1[f] = A1[f];
         P.outn[f] = ANP[f];
       }
-      hipLaunchKernelGGL((hsgn::k_adj_stage<256, 2>), dim3(c->n_inst), dim3(256), 0, c->stream, P);
+      hipLaunchKernelGGL((hsgn::k_adj_r1<kAdjNT, 2>), gt, bt, 0, c->stream, P);
+      hipLaunchKernelGGL(hsgn::k_adj_r2<256>, dim3(c->n_inst), dim3(256), 0, c->stream, Q);
+      hipLaunchKernelGGL((hsgn::k_adj_r3<kAdjNT, 2>), gt, bt, 0, c->stream, P);
+      // stage 1: hbar is the depth of U^(1)
+      P.hbar = tape(k, 4);
       for (int f = 0; f < 4; ++f) P.abar[f] = A1[f];
-      hipLaunchKernelGGL((hsgn::k_adj_stage<256, 1>), dim3(c->n_inst), dim3(256), 0, c->stream, P);
+      hipLaunchKernelGGL((hsgn::k_adj_r1<kAdjNT, 1>), gt, bt, 0, c->stream, P);
+      hipLaunchKernelGGL(hsgn::k_adj_r2<256>, dim3(c->n_inst), dim3(256), 0, c->stream, Q);
+      hipLaunchKernelGGL((hsgn::k_adj_r3<kAdjNT, 1>), gt, bt, 0, c->stream, P);
       for (int f = 0; f < 4; ++f) std::swap(AS[f], ANP[f]);
     }
   }

@@ -42,8 +42,11 @@ def field_err(a, ref):
     return d / scale if scale > 0 else d
 
 
-def check_instance(j, U, wl, nsteps, tol=TOL, seed=0):
-    """Bars (1) and (2) for instance j; returns (state error, worst field ratio)."""
+def check_instance(j, U, wl, nsteps, tol=TOL, seed=0, state_sens=False):
+    """Bars (1) and (2) for instance j; returns (state error, worst field ratio).
+    state_sens: bar (1) becomes max(tol, 8 s) with s the oracle's own relative
+    state sensitivity to a half-ulp perturbation (for runs that approach a
+    loss of coercivity, where that sensitivity itself exceeds tol)."""
     n, prm, b, U0 = wl.instance(j)
     p = O.make_params(**prm)
     orc, Uo, to = O.run(p, b, U0, 0.0, nsteps)
@@ -55,7 +58,11 @@ def check_instance(j, U, wl, nsteps, tol=TOL, seed=0):
     scale = max(np.max(np.abs(x)) for x in Uo)
     dev = [np.max(np.abs(U[f][o0:o1] - Uo[f])) for f in range(4)]
     state_err = max(dev) / scale
-    assert state_err <= tol, ("instance", j, "state", state_err)
+    state_tol = tol
+    if state_sens:
+        s_own = max(np.max(np.abs(Up[f] - Uo[f])) for f in range(4)) / scale
+        state_tol = max(tol, 8.0 * s_own)
+    assert state_err <= state_tol, ("instance", j, "state", state_err, state_tol)
     worst = 0.0
     for f in range(4):
         sens = np.max(np.abs(Up[f] - Uo[f]))
@@ -95,7 +102,7 @@ def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", 
     return worst
 
 
-SOLVERS = ["auto", "exact", "auto_small"]
+SOLVERS = ["auto", "exact", "auto_small", "auto_k4"]
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
@@ -224,3 +231,41 @@ def test_window_plan_covers_every_cell_once():
     info = s.plan_info()
     assert info["windows"] > 0
     assert (info["halo"][info["mode"] == 0] > 0).all()
+
+
+@pytest.mark.parametrize("solver", ["auto", "exact", "auto_k4"])
+def test_coercivity_loss_flagged_at_the_oracle_step(solver):
+    """Instance 84 of the batched bar (N = 586, lambda = 1e3): its solitary
+    wave steepens over the bar crest and the oracle's stage 2 of step 368
+    meets beta <= 0 (min beta 49 one step earlier, -31 there: a clear
+    crossing).  The library must match the oracle up to step 367, flag the
+    instance non-coercive at step 368, and then keep it frozen.  One step
+    before the crossing the oracle's own half-ulp sensitivity is 5.6e-11
+    relative in the state (4.6e-13 at step 300), so the state bar follows it
+    (bar (1) with state_sens)."""
+    from paper_2510_07539_amd.hsgn import HSGN_ENONCOERCIVE
+    Solver = _solver()
+    wl = WL.batched_bar().subset([84], name="bar-84")
+    n, prm, b, U0 = wl.instance(0)
+    p = O.make_params(**prm)
+    orc, _, _ = O.run(p, b, U0, 0.0, 368)
+    assert orc == 2  # oracle: non-coercive at step 368 ...
+    orc, _, _ = O.run(p, b, U0, 0.0, 367)
+    assert orc == 0  # ... and not before
+    note("coercivity loss [%s]: N=%d, 367 steps" % (solver, n))
+    s = Solver.from_workload(wl, solver=solver)
+    s.step(367)
+    rc, flags = s.status()
+    assert rc == 0 and flags[0] == 0
+    (h, q, m, W), t = s.get_state()
+    check_instance(0, [x.cpu().numpy() for x in (h, q, m, W)], wl, 367, state_sens=True)
+    s.step(1)
+    rc, flags = s.status()
+    assert rc == HSGN_ENONCOERCIVE and flags[0] & 2, (rc, flags)
+    (h1, q1, m1, W1), t1 = s.get_state()
+    s.step(3)
+    (h2, q2, m2, W2), t2 = s.get_state()
+    assert float(t2[0]) == float(t1[0])
+    for a, c in ((h1, h2), (q1, q2), (m1, m2), (W1, W2)):
+        assert torch.equal(a, c)
+    s.close()
