@@ -180,9 +180,9 @@ int hsgn_step_timed(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_coun
  * hsgn_set_state); the reverse stages solve the transposed depth system
  * exactly (no truncation).
  * On return the state is the state after nsteps steps and t is reset to 0.
- * The adjoint workspace (about 120 + 8 K doubles per cell, plus
- * 4 (nsteps/K + 1) doubles per cell of checkpoints) is kept until
- * hsgn_destroy.  Synchronises the stream once, after the initial state. */
+ * The adjoint workspace (22 + 8 K doubles per cell, plus 4 (nsteps/K + 1)
+ * doubles per cell of checkpoints) is kept until hsgn_destroy.
+ * Synchronises the stream once, after the initial state. */
 int hsgn_adjoint(hsgn_ctx* ctx, int32_t nsteps, int32_t K, int32_t n_gauge,
                  const int32_t* d_gauge, const double* d_target, const double* d_zeta0,
                  double* d_loss, double* d_grad_zeta0, double* d_grad_b);

@@ -70,6 +70,11 @@ struct hsgn_ctx {
   double* d_b = nullptr;
   double* buf[3][4] = {};
   int cur = 0, s1 = 1, nxt = 2;
+  // when set, the next step reads U^n from io_un, writes U^(1) to io_u1 and
+  // U^{n+1} to io_out instead of the rotating buffers
+  double* const* io_un = nullptr;
+  double* const* io_u1 = nullptr;
+  double* const* io_out = nullptr;
   double* d_dt = nullptr;
   double* d_t = nullptr;
   unsigned long long* d_smax = nullptr;
@@ -200,9 +205,9 @@ void launch_stage_any(hsgn_ctx* c, const StageArgs& a, int ntiles, bool reduce) 
 StageArgs stage_args(hsgn_ctx* c, int stage) {
   StageArgs a;
   std::memset(&a, 0, sizeof a);
-  double** un = c->buf[c->cur];
-  double** u1 = c->buf[c->s1];
-  double** out = stage == 1 ? c->buf[c->s1] : c->buf[c->nxt];
+  double* const* un = c->io_un ? c->io_un : c->buf[c->cur];
+  double* const* u1 = c->io_u1 ? c->io_u1 : c->buf[c->s1];
+  double* const* out = stage == 1 ? u1 : (c->io_out ? c->io_out : c->buf[c->nxt]);
   a.un_h = un[0]; a.un_q = un[1]; a.un_m = un[2]; a.un_W = un[3];
   a.u1_h = u1[0]; a.u1_q = u1[1]; a.u1_m = u1[2]; a.u1_W = u1[3];
   a.o_h = out[0]; a.o_q = out[1]; a.o_m = out[2]; a.o_W = out[3];
@@ -290,6 +295,19 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
   return HSGN_OK;
 }
 
+
+// One step between explicit buffers (no rotation of the state buffers).
+int enqueue_step_io(hsgn_ctx* c, double* const* un, double* const* u1, double* const* out) {
+  c->io_un = un;
+  c->io_u1 = u1;
+  c->io_out = out;
+  const int cur = c->cur, nxt = c->nxt;
+  const int rc = enqueue_step(c);
+  c->io_un = c->io_u1 = c->io_out = nullptr;
+  c->cur = cur;
+  c->nxt = nxt;
+  return rc;
+}
 
 // Halo width (window rows beyond the core on a truncated side) for one
 // instance: the depth system behaves like I + r beta (second difference),
@@ -996,16 +1014,33 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   rc = reset_and_plan(c);  // flags, speed bound and solver plan of the initial state
   if (rc) return rc;
   hipLaunchKernelGGL(k_fill_f64, dim3(nbi), dim3(256), 0, c->stream, (int64_t)c->n_inst, d_loss, 0.0);
+  // the last segment writes its tape (and the final state) directly, so the
+  // reverse sweep starts without recomputing it
+  const int s_last = (nseg - 1) * K;
   for (int s = 0; s < nsteps; ++s) {
     if (grad && s % K == 0) {
       double* dst[4] = {ckpt(s / K, 0), ckpt(s / K, 1), ckpt(s / K, 2), ckpt(s / K, 3)};
       rc = copy_state(c, dst, c->buf[c->cur]);
       if (rc) return rc;
     }
-    rc = enqueue_step(c);
+    const double* hnew;
+    if (grad && s >= s_last) {
+      const int k = s - s_last, ksl = nsteps - s_last;
+      double *un[4], *u1[4], *out[4];
+      for (int f = 0; f < 4; ++f) {
+        un[f] = k == 0 ? ckpt(nseg - 1, f) : tape(k, f);
+        u1[f] = tape(k, 4 + f);
+        out[f] = (k + 1 < ksl) ? tape(k + 1, f) : ckpt(nseg, f);
+      }
+      rc = enqueue_step_io(c, un, u1, out);
+      hnew = out[0];
+    } else {
+      rc = enqueue_step(c);
+      hnew = c->buf[c->cur][0];
+    }
     if (rc) return rc;
     hipLaunchKernelGGL(k_gauge_fwd, dim3(nbi), dim3(256), 0, c->stream, c->n_inst, c->d_inst, ng,
-                       d_gauge, d_target, nsteps, s, c->buf[c->cur][0], d_loss, a.res);
+                       d_gauge, d_target, nsteps, s, hnew, d_loss, a.res);
   }
   if (!grad) {  // loss only
     hipLaunchKernelGGL(k_fill_f64, dim3(nbi), dim3(256), 0, c->stream, (int64_t)c->n_inst,
@@ -1013,11 +1048,7 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
     HIPCHK(c, hipGetLastError());
     return leave(c);
   }
-  {  // the final state and time, restored at the end
-    double* dst[4] = {ckpt(nseg, 0), ckpt(nseg, 1), ckpt(nseg, 2), ckpt(nseg, 3)};
-    rc = copy_state(c, dst, c->buf[c->cur]);
-    if (rc) return rc;
-  }
+  // (the final state is in checkpoint nseg; it is restored at the end)
   // ---- reverse
   for (int f = 0; f < 4; ++f)
     hipLaunchKernelGGL(k_fill_f64, dim3(nbc), dim3(256), 0, c->stream, (int64_t)c->ncell, AS[f], 0.0);
@@ -1051,26 +1082,27 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int s0 = seg * K;
     const int ks = std::min(K, nsteps - s0);
-    {
-      double* src[4] = {ckpt(seg, 0), ckpt(seg, 1), ckpt(seg, 2), ckpt(seg, 3)};
-      rc = copy_state(c, c->buf[c->cur], src);
-      if (rc) return rc;
-    }
-    for (int k = 0; k < ks; ++k) {  // recompute the segment, taping U^n and U^(1)
-      double* tn[4] = {tape(k, 0), tape(k, 1), tape(k, 2), tape(k, 3)};
-      rc = copy_state(c, tn, c->buf[c->cur]);
-      if (rc) return rc;
-      rc = enqueue_step(c);
-      if (rc) return rc;
-      double* t1[4] = {tape(k, 4), tape(k, 5), tape(k, 6), tape(k, 7)};
-      rc = copy_state(c, t1, c->buf[c->s1]);
+    // recompute the segment from its checkpoint, keeping U^n and U^(1) of
+    // every step on the tape (the steps write there directly)
+    double* cks[4] = {ckpt(seg, 0), ckpt(seg, 1), ckpt(seg, 2), ckpt(seg, 3)};
+    auto un_of = [&](int k, int f) { return k == 0 ? cks[f] : tape(k, f); };
+    for (int k = 0; k < ks && seg != nseg - 1; ++k) {
+      double* un[4] = {un_of(k, 0), un_of(k, 1), un_of(k, 2), un_of(k, 3)};
+      double* u1[4] = {tape(k, 4), tape(k, 5), tape(k, 6), tape(k, 7)};
+      double* const* out = (k + 1 < ks) ? nullptr : c->buf[c->nxt];
+      double* nx[4];
+      if (k + 1 < ks) {
+        for (int f = 0; f < 4; ++f) nx[f] = tape(k + 1, f);
+        out = nx;
+      }
+      rc = enqueue_step_io(c, un, u1, out);
       if (rc) return rc;
     }
     for (int k = ks - 1; k >= 0; --k) {
       hipLaunchKernelGGL(k_gauge_adj, dim3(nbi), dim3(256), 0, c->stream, c->n_inst, c->d_inst,
                          ng, d_gauge, nsteps, s0 + k, a.res, AS[0]);
       for (int f = 0; f < 4; ++f) {
-        P.un[f] = tape(k, f);
+        P.un[f] = un_of(k, f);
         P.u1[f] = tape(k, 4 + f);
       }
       // stage 2: hbar is the depth of U^{n+1}
@@ -1081,13 +1113,13 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
         P.outn[f] = ANP[f];
       }
       hipLaunchKernelGGL((hsgn::k_adj_r1<kAdjNT, 2>), gt, bt, 0, c->stream, P);
-      hipLaunchKernelGGL(hsgn::k_adj_r2<256>, dim3(c->n_inst), dim3(256), 0, c->stream, Q);
+      hipLaunchKernelGGL((hsgn::k_adj_r2<512, 8>), dim3(c->n_inst), dim3(512), 0, c->stream, Q);
       hipLaunchKernelGGL((hsgn::k_adj_r3<kAdjNT, 2>), gt, bt, 0, c->stream, P);
       // stage 1: hbar is the depth of U^(1)
       P.hbar = tape(k, 4);
       for (int f = 0; f < 4; ++f) P.abar[f] = A1[f];
       hipLaunchKernelGGL((hsgn::k_adj_r1<kAdjNT, 1>), gt, bt, 0, c->stream, P);
-      hipLaunchKernelGGL(hsgn::k_adj_r2<256>, dim3(c->n_inst), dim3(256), 0, c->stream, Q);
+      hipLaunchKernelGGL((hsgn::k_adj_r2<512, 8>), dim3(c->n_inst), dim3(512), 0, c->stream, Q);
       hipLaunchKernelGGL((hsgn::k_adj_r3<kAdjNT, 1>), gt, bt, 0, c->stream, P);
       for (int f = 0; f < 4; ++f) std::swap(AS[f], ANP[f]);
     }

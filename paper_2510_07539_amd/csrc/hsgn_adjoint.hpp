@@ -34,6 +34,7 @@
 #include <stdint.h>
 
 #include "hsgn_kernels.hpp"
+#include "hsgn_window.hpp"
 
 namespace hsgn {
 namespace adj {
@@ -92,20 +93,29 @@ __device__ __forceinline__ Coef coefs(const TC& I, double h, double m, double md
   return c;
 }
 
-// LDS of a tile: arrays read at neighbouring positions.  The union holds
+// LDS of a tile: arrays read at neighbouring positions.  The unions hold
 // arrays whose lifetimes do not overlap (barriers separate them).
 template <int NT>
-struct TileLds {
+struct TileLds1 {  // R1
   double he[NT], qe[NT], me[NT], we[NT], bb[NT], hb[NT];  // U_E, bed, hbar
   double phi[NT], tt[NT];                                 // records read by rows
   double fa[NT], dba[NT];                                 // reverse back-substitution
-  double db2a[NT];                                        // bed-slope source adjoint
   union {
-    struct { double fq[NT], fm[NT], fw[NT]; } face;                  // fluxes
-    struct { double beta[NT], lo[NT], up[NT]; } row;                 // R1: rows
-    struct { double rl[5][NT], rr[5][NT], dbm[NT], dbp[NT]; } rrow;  // R3: row parts
-    struct { double fl[3][NT], fr[3][NT]; } rface;                   // R3: face adjoints
-    double pf[20][NT];                                               // R3: face partials
+    struct { double fq[NT], fm[NT], fw[NT]; } face;  // fluxes
+    struct { double beta[NT], lo[NT], up[NT]; } row; // rows
+  } u;
+};
+template <int NT>
+struct TileLds3 {  // R3
+  double he[NT], qe[NT], me[NT], we[NT], bb[NT], hb[NT];
+  double phi[NT], tt[NT];
+  double fa[NT], dba[NT];
+  double lam[NT];   // solution of the transposed system
+  double db2a[NT];  // bed-slope source adjoint
+  union {
+    struct { double fq[NT], fm[NT], fw[NT]; } face;     // fluxes
+    struct { double fl[3][NT], fr[3][NT]; } rface;      // face adjoints
+    double pf[5][NT];                                   // face partials, one stencil cell at a time
   } u;
 };
 
@@ -117,8 +127,8 @@ __device__ __forceinline__ int real_cell(const TC& T, int v) {
 }
 
 // Load the tile: U_E, the old state, the bed, hbar and the output adjoint.
-template <int NT, int STAGE>
-__device__ __forceinline__ void load_tile(const TC& T, TileLds<NT>& L, int64_t off, int v,
+template <int STAGE, class LT>
+__device__ __forceinline__ void load_tile(const TC& T, LT& L, int64_t off, int v,
                                           const double* const* un, const double* const* u1,
                                           const double* b, const double* hbs,
                                           const double* const* abar, double E[4], double O[4],
@@ -148,8 +158,8 @@ __device__ __forceinline__ void load_tile(const TC& T, TileLds<NT>& L, int64_t o
 }
 
 // Rusanov flux of face f (between virtual cells f-1 and f).
-template <int NT>
-__device__ __forceinline__ void face_flux(const TC& I, const TileLds<NT>& L, int f, double& Fq,
+template <class LT>
+__device__ __forceinline__ void face_flux(const TC& I, const LT& L, int f, double& Fq,
                                           double& Fm, double& Fw) {
   const int cm = slot(I, f - 2), c0 = slot(I, f - 1), c1 = slot(I, f), c2 = slot(I, f + 1);
   const double hm = L.he[cm], h0 = L.he[c0], h1 = L.he[c1], h2 = L.he[c2];
@@ -183,8 +193,8 @@ struct Own {
 };
 
 // Records of cell i (own thread) from the fluxes of faces i and i+1.
-template <int NT>
-__device__ __forceinline__ void records(const TC& I, const TileLds<NT>& L, int i, const double E[4],
+template <class LT>
+__device__ __forceinline__ void records(const TC& I, const LT& L, int i, const double E[4],
                                         const double O[4], Own& w) {
   const int t = i - I.lo0;
   const double Db = (L.bb[slot(I, i + 1)] - L.bb[slot(I, i - 1)]) * I.i2dx;
@@ -200,8 +210,8 @@ __device__ __forceinline__ void records(const TC& I, const TileLds<NT>& L, int i
 
 // Reverse back-substitution at cell i: own adjoints, and the parts that
 // neighbours gather (fa, dba).
-template <int NT>
-__device__ __forceinline__ void rev_back(const TC& I, TileLds<NT>& L, int i, const double aU[4],
+template <class LT>
+__device__ __forceinline__ void rev_back(const TC& I, LT& L, int i, const double aU[4],
                                          Own& w) {
   const int t = i - I.lo0;
   const double h = L.hb[t], ih = 1.0 / h, ih2 = ih * ih, md = w.md;
@@ -235,8 +245,8 @@ __device__ __forceinline__ void rev_back(const TC& I, TileLds<NT>& L, int i, con
 
 // Gather of the back-substitution parts at cell j: adjoints of S, beta and
 // hbar, and the bed part.  Source rows are j-1, j, j+1 (those that exist).
-template <int NT>
-__device__ __forceinline__ void gather_back(const TC& I, const TileLds<NT>& L, int j,
+template <class LT>
+__device__ __forceinline__ void gather_back(const TC& I, const LT& L, int j,
                                             const Own& w, double& SA0, double& BETAA0,
                                             double& HBA, double& BAB) {
   double PA = 0.0, hA = w.HBA0, bA = 0.0;
@@ -256,6 +266,52 @@ __device__ __forceinline__ void gather_back(const TC& I, const TileLds<NT>& L, i
   BETAA0 = PA * L.hb[j - I.lo0];
   HBA = hA + PA * w.beta;
   BAB = bA;
+}
+
+// Parts of the reverse of row i (A^a = -lam hbar^T, rhs^a = lam) that
+// belong to the records (beta, S, q+, phi, T) of cells i-1 (l), i+1 (r) and
+// i (c), and to the bed differences (dbm, dbp).
+struct RowParts {
+  double l[5], r[5], c[5], dbm, dbp;
+};
+template <class LT>
+__device__ __forceinline__ RowParts row_parts(const TC& I, const LT& L, int i) {
+  const int t = i - I.lo0;
+  const int sL = slot(I, i - 1), sR = slot(I, i + 1);
+  const double lamv = L.lam[t];
+  double loA = -lamv * L.hb[sL], diA = -lamv * L.hb[t], upA = -lamv * L.hb[sR];
+  const double rhsA = lamv;
+  if (I.bc != 0 && i == 0) loA = diA;        // folded: di = di_raw + lo_raw
+  if (I.bc != 0 && i == I.n - 1) upA = diA;  // folded: di = di_raw + up_raw
+  const double rr = I.rr;
+  const double bLA = -rr * loA, bRA = -rr * upA, bCA = 2.0 * rr * diA;
+  double eLA = 0.0, eCA = 0.0, eRA = 0.0, dbmA = 0.0, dbpA = 0.0;
+  double tLA = 0.0, tCA = 0.0, tRA = 0.0;
+  if (I.has_b) {
+    const double hg = 0.5 * I.g;
+    const double bL = L.bb[sL], bC = L.bb[t], bR = L.bb[sR];
+    const double dbm = bC - bL, dbp = bR - bC;
+    const double eL = hg + 0.75 * L.phi[sL], eC = hg + 0.75 * L.phi[t], eR = hg + 0.75 * L.phi[sR];
+    eLA = rr * dbm * loA;
+    dbmA = rr * eL * loA;
+    eRA = -rr * dbp * upA;
+    dbpA = -rr * eR * upA;
+    eCA = -rr * (dbp - dbm) * diA;
+    dbpA += -rr * eC * diA;
+    dbmA += rr * eC * diA;
+    tCA = 0.75 * rr * (dbp - dbm) * rhsA;
+    tRA = 0.75 * rr * dbp * rhsA;
+    tLA = -0.75 * rr * dbm * rhsA;
+    dbpA += 0.75 * rr * (L.tt[t] + L.tt[sR]) * rhsA;
+    dbmA += -0.75 * rr * (L.tt[sL] + L.tt[t]) * rhsA;
+  }
+  RowParts p;
+  p.l[0] = bLA; p.l[1] = rr * rhsA; p.l[2] = I.tdx2 * rhsA; p.l[3] = 0.75 * eLA; p.l[4] = tLA;
+  p.r[0] = bRA; p.r[1] = rr * rhsA; p.r[2] = -I.tdx2 * rhsA; p.r[3] = 0.75 * eRA; p.r[4] = tRA;
+  p.c[0] = bCA; p.c[1] = -2.0 * rr * rhsA; p.c[2] = 0.0; p.c[3] = 0.75 * eCA; p.c[4] = tCA;
+  p.dbm = dbmA;
+  p.dbp = dbpA;
+  return p;
 }
 
 __device__ __forceinline__ TC make_tc(const InstDesc& D, int lo0, double dt) {
@@ -299,7 +355,7 @@ struct AdjTileArgs {
 template <int NT, int STAGE>
 __global__ __launch_bounds__(NT) void k_adj_r1(AdjTileArgs P) {
   using namespace adj;
-  __shared__ TileLds<NT> L;
+  __shared__ TileLds1<NT> L;
   const TileA tl = P.tiles[blockIdx.x];
   const InstDesc D = P.inst[tl.inst];
   const double dt = P.dt[tl.inst];
@@ -308,20 +364,20 @@ __global__ __launch_bounds__(NT) void k_adj_r1(AdjTileArgs P) {
   const TC I = make_tc(D, tl.ts - H, dt);
   const int v = I.lo0 + t;
   double E[4] = {0, 0, 0, 0}, O[4] = {0, 0, 0, 0}, aU[4] = {0, 0, 0, 0};
-  load_tile<NT, STAGE>(I, L, D.off, v, P.un, P.u1, P.b, P.hbar, P.abar, E, O, aU);
+  load_tile<STAGE>(I, L, D.off, v, P.un, P.u1, P.b, P.hbar, P.abar, E, O, aU);
   __syncthreads();
   if (t >= 2 && t <= NT - 2 && face_ok(I, v))
-    face_flux<NT>(I, L, v, L.u.face.fq[t], L.u.face.fm[t], L.u.face.fw[t]);
+    face_flux(I, L, v, L.u.face.fq[t], L.u.face.fm[t], L.u.face.fw[t]);
   __syncthreads();
   Own w;
   const bool rec_ok = t >= 2 && t <= NT - 3 && cell_ok(I, v);
-  if (rec_ok) records<NT>(I, L, v, E, O, w);
+  if (rec_ok) records(I, L, v, E, O, w);
   __syncthreads();  // fluxes are dead: the union now holds rows
   if (rec_ok) {
     L.u.row.beta[t] = w.beta;
     L.phi[t] = w.phi;
     L.tt[t] = w.T;
-    rev_back<NT>(I, L, v, aU, w);
+    rev_back(I, L, v, aU, w);
   }
   __syncthreads();
   // rows (the forward's expressions, right-hand side not needed)
@@ -344,7 +400,7 @@ __global__ __launch_bounds__(NT) void k_adj_r1(AdjTileArgs P) {
     if (I.bc != 0 && v == 0) { di += lo; lo = 0.0; }
     if (I.bc != 0 && v == I.n - 1) { di += up; up = 0.0; }
     double SA0, BETAA0, BAB;
-    gather_back<NT>(I, L, v, w, SA0, BETAA0, hbarA, BAB);
+    gather_back(I, L, v, w, SA0, BETAA0, hbarA, BAB);
     L.u.row.lo[t] = lo;  // no storage shared with beta
     L.u.row.up[t] = up;
   }
@@ -369,7 +425,7 @@ __global__ __launch_bounds__(NT) void k_adj_r1(AdjTileArgs P) {
 template <int NT, int STAGE>
 __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
   using namespace adj;
-  __shared__ TileLds<NT> L;
+  __shared__ TileLds3<NT> L;
   const TileA tl = P.tiles[blockIdx.x];
   const InstDesc D = P.inst[tl.inst];
   const double dt = P.dt[tl.inst];
@@ -393,97 +449,52 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
     return;
   }
   double E[4] = {0, 0, 0, 0}, O[4] = {0, 0, 0, 0}, aU[4] = {0, 0, 0, 0};
-  load_tile<NT, STAGE>(I, L, D.off, v, P.un, P.u1, P.b, P.hbar, P.abar, E, O, aU);
-  const double lamv = cell_ok(I, v) ? P.lam[D.off + real_cell(I, v)] : 0.0;
+  load_tile<STAGE>(I, L, D.off, v, P.un, P.u1, P.b, P.hbar, P.abar, E, O, aU);
+  L.lam[t] = cell_ok(I, v) ? P.lam[D.off + real_cell(I, v)] : 0.0;
   __syncthreads();
   if (t >= 2 && t <= NT - 2 && face_ok(I, v))
-    face_flux<NT>(I, L, v, L.u.face.fq[t], L.u.face.fm[t], L.u.face.fw[t]);
+    face_flux(I, L, v, L.u.face.fq[t], L.u.face.fm[t], L.u.face.fw[t]);
   __syncthreads();
   Own w;
   const bool rec_ok = t >= 2 && t <= NT - 3 && cell_ok(I, v);
-  if (rec_ok) records<NT>(I, L, v, E, O, w);
+  if (rec_ok) records(I, L, v, E, O, w);
   __syncthreads();  // fluxes are dead
   if (rec_ok) {
     L.phi[t] = w.phi;
     L.tt[t] = w.T;
-    rev_back<NT>(I, L, v, aU, w);
+    rev_back(I, L, v, aU, w);
   }
   __syncthreads();
-  // gather of the back-substitution parts, and the reverse rows:
-  // A^a = -lam hbar^T, rhs^a = lam
-  double SA0 = 0.0, BETAA0 = 0.0, BAB = 0.0;
-  double rc[5] = {0, 0, 0, 0, 0}, HOA = 0.0;
-  const bool row_ok = t >= 3 && t <= NT - 4 && cell_ok(I, v);
-  if (row_ok) {
-    double HBA;
-    gather_back<NT>(I, L, v, w, SA0, BETAA0, HBA, BAB);
-    const int sL = slot(I, v - 1), sR = slot(I, v + 1);
-    double loA = -lamv * L.hb[sL], diA = -lamv * L.hb[t], upA = -lamv * L.hb[sR];
-    const double rhsA = lamv;
-    if (I.bc != 0 && v == 0) loA = diA;        // folded: di = di_raw + lo_raw
-    if (I.bc != 0 && v == I.n - 1) upA = diA;  // folded: di = di_raw + up_raw
-    const double rr = I.rr;
-    const double bLA = -rr * loA, bRA = -rr * upA, bCA = 2.0 * rr * diA;
-    double eLA = 0.0, eCA = 0.0, eRA = 0.0, dbmA = 0.0, dbpA = 0.0;
-    double tLA = 0.0, tCA = 0.0, tRA = 0.0;
-    if (I.has_b) {
-      const double hg = 0.5 * I.g;
-      const double bL = L.bb[sL], bC = L.bb[t], bR = L.bb[sR];
-      const double dbm = bC - bL, dbp = bR - bC;
-      const double eL = hg + 0.75 * L.phi[sL], eC = hg + 0.75 * L.phi[t], eR = hg + 0.75 * L.phi[sR];
-      eLA = rr * dbm * loA;
-      dbmA = rr * eL * loA;
-      eRA = -rr * dbp * upA;
-      dbpA = -rr * eR * upA;
-      eCA = -rr * (dbp - dbm) * diA;
-      dbpA += -rr * eC * diA;
-      dbmA += rr * eC * diA;
-      tCA = 0.75 * rr * (dbp - dbm) * rhsA;
-      tRA = 0.75 * rr * dbp * rhsA;
-      tLA = -0.75 * rr * dbm * rhsA;
-      dbpA += 0.75 * rr * (L.tt[t] + L.tt[sR]) * rhsA;
-      dbmA += -0.75 * rr * (L.tt[sL] + L.tt[t]) * rhsA;
-    }
-    // parts of row v that belong to the records (beta, S, q+, phi, T) of
-    // cells v-1 (rl), v+1 (rr) and v (rc)
-    L.u.rrow.rl[0][t] = bLA; L.u.rrow.rl[1][t] = rr * rhsA; L.u.rrow.rl[2][t] = I.tdx2 * rhsA;
-    L.u.rrow.rl[3][t] = 0.75 * eLA; L.u.rrow.rl[4][t] = tLA;
-    L.u.rrow.rr[0][t] = bRA; L.u.rrow.rr[1][t] = rr * rhsA; L.u.rrow.rr[2][t] = -I.tdx2 * rhsA;
-    L.u.rrow.rr[3][t] = 0.75 * eRA; L.u.rrow.rr[4][t] = tRA;
-    rc[0] = bCA; rc[1] = -2.0 * rr * rhsA; rc[2] = 0.0; rc[3] = 0.75 * eCA; rc[4] = tCA;
-    HOA = rhsA;
-    L.u.rrow.dbm[t] = dbmA;
-    L.u.rrow.dbp[t] = dbpA;
-  }
-  __syncthreads();
-  // gather of the row parts, then the reverse records
+  // gathers of the back-substitution parts and of the reverse rows (rows
+  // j-1, j, j+1 recomputed from lam), then the reverse records
   const bool grec_ok = t >= 4 && t <= NT - 5 && cell_ok(I, v);
-  double OA[4] = {0, 0, 0, 0}, EA0[3] = {0, 0, 0}, BAR = 0.0, DbA = 0.0;
+  double OA[4] = {0, 0, 0, 0}, EA0[3] = {0, 0, 0}, BAR = 0.0, DbA = 0.0, BAB = 0.0;
   double FLv[3] = {0, 0, 0}, FRv[3] = {0, 0, 0};
   if (grec_ok) {
+    double SA0, BETAA0, HBA;
+    gather_back(I, L, v, w, SA0, BETAA0, HBA, BAB);
     double bt = BETAA0, st = SA0, qt = w.QDA0, pt = w.PHIA0, tt = w.TA0;
     double bA = 0.0;
 #pragma unroll
     for (int d = -1; d <= 1; ++d) {
       const int i = v + d;
       if (!cell_ok(I, i)) continue;
-      const int s = i - I.lo0;
+      const RowParts rp = row_parts(I, L, i);
       if (i == v) {
-        bt += rc[0]; st += rc[1]; qt += rc[2]; pt += rc[3]; tt += rc[4];
-        bA += L.u.rrow.dbm[s] - L.u.rrow.dbp[s];
+        bt += rp.c[0]; st += rp.c[1]; qt += rp.c[2]; pt += rp.c[3]; tt += rp.c[4];
+        bA += rp.dbm - rp.dbp;
       }
       if (vcl(I, i - 1) == v) {
-        bt += L.u.rrow.rl[0][s]; st += L.u.rrow.rl[1][s]; qt += L.u.rrow.rl[2][s];
-        pt += L.u.rrow.rl[3][s]; tt += L.u.rrow.rl[4][s];
-        bA -= L.u.rrow.dbm[s];
+        bt += rp.l[0]; st += rp.l[1]; qt += rp.l[2]; pt += rp.l[3]; tt += rp.l[4];
+        bA -= rp.dbm;
       }
       if (vcl(I, i + 1) == v) {
-        bt += L.u.rrow.rr[0][s]; st += L.u.rrow.rr[1][s]; qt += L.u.rrow.rr[2][s];
-        pt += L.u.rrow.rr[3][s]; tt += L.u.rrow.rr[4][s];
-        bA += L.u.rrow.dbp[s];
+        bt += rp.r[0]; st += rp.r[1]; qt += rp.r[2]; pt += rp.r[3]; tt += rp.r[4];
+        bA += rp.dbp;
       }
     }
     BAR = bA;
+    const double HOA = L.lam[t];
     // reverse of the coefficients at U_E and of the explicit predictor
     const double h = E[0], m = E[2], q = E[1], md = w.md;
     const Coef c = coefs(I, h, m, md);
@@ -553,8 +564,7 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
     EA0[1] = mA;
     EA0[2] = qEA;
   }
-  __syncthreads();  // row parts are dead: the union now holds face adjoints
-  if (grec_ok) {
+  if (grec_ok) {  // no barrier needed: the union last held fluxes
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       L.u.rface.fl[k][t] = FLv[k];
@@ -647,31 +657,30 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
       pa[4][2] += 0.5 * zfA;
     }
   }
-  __syncthreads();  // face adjoints are dead: the union now holds face partials
-  if (rf_ok) {
+  // gather of the face partials on the core, one stencil position k at a
+  // time (cell j takes position k of the faces f with f - 2 + k -> j)
+  const int j = v;
+  double ea[5] = {EA0[0], EA0[2], EA0[1], 0.0, 0.0};  // h, q, m, W, b
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < 4; ++k) {
+    __syncthreads();  // the previous round (or the face adjoints) is read
+    if (rf_ok) {
 #pragma unroll
-      for (int fl = 0; fl < 5; ++fl) L.u.pf[5 * k + fl][t] = pa[fl][k];
-  }
-  __syncthreads();
-  // cell gather of the face partials and the bed sources on the core
-  if (core) {
-    const int j = v;
-    double ea[5] = {EA0[0], EA0[2], EA0[1], 0.0, 0.0};  // h, q, m, W, b
+      for (int fl = 0; fl < 5; ++fl) L.u.pf[fl][t] = pa[fl][k];
+    }
+    __syncthreads();
+    if (core) {
 #pragma unroll
-    for (int d = -1; d <= 2; ++d) {
-      const int f = j + d;
-      if (!face_ok(I, f)) continue;
-      const int s = f - I.lo0;
+      for (int d = -1; d <= 2; ++d) {
+        const int f = j + d;
+        if (!face_ok(I, f) || vcl(I, f - 2 + k) != j) continue;
+        const int s = f - I.lo0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (vcl(I, f - 2 + k) == j) {
-#pragma unroll
-          for (int fl = 0; fl < 5; ++fl) ea[fl] += L.u.pf[5 * k + fl][s];
-        }
+        for (int fl = 0; fl < 5; ++fl) ea[fl] += L.u.pf[fl][s];
       }
     }
+  }
+  if (core) {
     double bA = BAB + BAR + ea[4];
     if (I.has_b) {
 #pragma unroll
@@ -797,14 +806,114 @@ struct AdjSolveArgs {
   double* sw;
 };
 
-template <int NT>
+// Register-resident solve of one instance of n <= NT * K rows: each thread
+// eliminates its chunk (consecutive rows, read straight from global memory)
+// into two rows of the level-1 system, which PCR solves in LDS (stopping
+// once every coupling is below 2^-66 of its diagonal); the chunk interiors
+// follow from the spikes.  Longer instances use the global-scratch solve.
+template <int NT, int K>
 __global__ __launch_bounds__(NT) void k_adj_r2(AdjSolveArgs P) {
   __shared__ Lds<NT> S;
   const InstDesc D = P.inst[blockIdx.x];
   if (!(P.dt[blockIdx.x] > 0.0)) return;  // frozen: lam is not used
   const int64_t o = D.off;
-  wg_tri_solve<NT>(S, P.lot + o, P.dit + o, P.upt + o, P.hba + o, P.lam + o, D.n, D.bc == 0,
-                   P.scp + o, P.sy + o, P.sv + o, P.sw + o);
+  const int n = D.n;
+  const bool cyclic = D.bc == 0;
+  if (n > NT * K) {
+    wg_tri_solve<NT>(S, P.lot + o, P.dit + o, P.upt + o, P.hba + o, P.lam + o, n, cyclic,
+                     P.scp + o, P.sy + o, P.sv + o, P.sw + o);
+    return;
+  }
+  const int t = threadIdx.x;
+  const Chunk ch = chunk_of(n, NT, t);
+  const int k = ch.k;  // 2 <= k <= K for active threads
+  const int f = ch.first;
+  const bool act = t < ch.active;
+  const double* lo = P.lot + o;
+  const double* di = P.dit + o;
+  const double* up = P.upt + o;
+  const double* rhs = P.hba + o;
+  double y[K], v[K], w[K];
+  if (act) {
+    double cp[K];
+    double cprev = 0.0, yprev = 0.0, vprev = 1.0, wprev = 0.0;
+#pragma unroll
+    for (int i = 1; i < K - 1; ++i) {
+      if (i <= k - 2) {
+        const double l = lo[f + i], d = di[f + i], u = up[f + i], r = rhs[f + i];
+        const double inv = 1.0 / (d - l * cprev);
+        const bool lastint = (i == k - 2);
+        cprev = lastint ? 0.0 : u * inv;
+        yprev = (r - l * yprev) * inv;
+        vprev = (-l * vprev) * inv;
+        wprev = (-l * wprev) * inv - (lastint ? u * inv : 0.0);
+        cp[i] = cprev;
+        y[i] = yprev;
+        v[i] = vprev;
+        w[i] = wprev;
+      }
+    }
+    double yn = 0.0, vn = 0.0, wn = 0.0;
+#pragma unroll
+    for (int i = K - 2; i >= 1; --i) {
+      if (i <= k - 2) {
+        const double c = cp[i];
+        yn = y[i] - c * yn;
+        vn = v[i] - c * vn;
+        wn = w[i] - c * wn;
+        y[i] = yn;
+        v[i] = vn;
+        w[i] = wn;
+      }
+    }
+    const int l = f + k - 1;
+    double R0[4] = {lo[f], di[f], up[f], rhs[f]};
+    double R1[4] = {lo[l], di[l], up[l], rhs[l]};
+    if (k > 2) {
+      double vk = 0.0, wk = 0.0, yk = 0.0;
+#pragma unroll
+      for (int i = 1; i < K - 1; ++i) {
+        if (i == k - 2) { vk = v[i]; wk = w[i]; yk = y[i]; }
+      }
+      R0[1] = R0[1] + R0[2] * v[1];
+      R0[3] = R0[3] - R0[2] * y[1];
+      R0[2] = R0[2] * w[1];
+      R1[1] = R1[1] + R1[0] * wk;
+      R1[3] = R1[3] - R1[0] * yk;
+      R1[0] = R1[0] * vk;
+    }
+    S.a[2 * t] = R0[0]; S.b[2 * t] = R0[1]; S.c[2 * t] = R0[2]; S.d0[2 * t] = R0[3];
+    S.d1[2 * t] = 0.0; S.d2[2 * t] = 0.0;
+    S.a[2 * t + 1] = R1[0]; S.b[2 * t + 1] = R1[1]; S.c[2 * t + 1] = R1[2];
+    S.d0[2 * t + 1] = R1[3]; S.d1[2 * t + 1] = 0.0; S.d2[2 * t + 1] = 0.0;
+  }
+  __syncthreads();
+  const int n1 = 2 * ch.active;
+  level1_interior_fast<NT>(S, n1);
+  if (t == 0) {
+    double R0[4], R1[4], z0, zl;
+    tile_rows<NT>(S, n1, R0, R1);
+    if (!cyclic) {
+      R0[0] = 0.0;
+      R1[2] = 0.0;
+    }
+    solve_ends(R0, R1, cyclic, z0, zl);
+    S.s[0] = z0;
+    S.s[1] = zl;
+  }
+  __syncthreads();
+  if (act) {
+    const double z0 = S.s[0], zl = S.s[1];
+    const int j0 = 2 * t, j1 = 2 * t + 1;
+    const double zf = (j0 == 0) ? z0 : S.d0[j0] + S.d1[j0] * z0 + S.d2[j0] * zl;
+    const double zb = (j1 == n1 - 1) ? zl : S.d0[j1] + S.d1[j1] * z0 + S.d2[j1] * zl;
+    double* x = P.lam + o;
+    x[f] = zf;
+    x[f + k - 1] = zb;
+#pragma unroll
+    for (int i = 1; i < K - 1; ++i)
+      if (i <= k - 2) x[f + i] = y[i] + v[i] * zf + w[i] * zb;
+  }
 }
 
 }  // namespace hsgn
