@@ -180,7 +180,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-instance", action="store_true")
     ap.add_argument("--timed-steps", type=int, default=10)
-    ap.add_argument("--solver", default="auto", choices=["auto", "exact", "auto_small", "auto_k4"])
+    ap.add_argument("--solver", default="auto", choices=["auto", "exact", "auto_small"])
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: a plain copy of known size, then eager steps")

@@ -124,13 +124,11 @@ int hsgn_run(hsgn_ctx* ctx, int32_t nsteps, int32_t block);
  *    2048 cells: tiles reduce to two rows each, a per-instance reduced
  *    system is solved, and the tiles finish (no truncation anywhere).
  *  HSGN_SOLVER_AUTO_SMALL: AUTO with 2048-row windows (256 threads x 8 rows).
- *  HSGN_SOLVER_AUTO_K4: AUTO with 2048-row windows (512 threads x 4 rows).
  * The plan is made from the state loaded by hsgn_set_state (speed bound
  * and maximum depth per instance); hsgn_set_solver re-plans at once. */
 #define HSGN_SOLVER_AUTO 0
 #define HSGN_SOLVER_EXACT 1
 #define HSGN_SOLVER_AUTO_SMALL 2
-#define HSGN_SOLVER_AUTO_K4 3
 int hsgn_set_solver(hsgn_ctx* ctx, int32_t mode);
 
 /* Plan of the loaded state (host arrays, any may be NULL): h_mode[j] = 0

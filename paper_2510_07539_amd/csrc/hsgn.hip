@@ -90,7 +90,6 @@ struct hsgn_ctx {
   // execution plan (rebuilt by hsgn_set_state / hsgn_set_solver)
   int32_t solver = HSGN_SOLVER_AUTO;
   int win_nt = 512;
-  int win_k = kWK;  // rows per thread of the windowed kernel (4 or 8)
   std::vector<double> h_smax, h_hmax;  // speed bound and depth maximum of the loaded state
   std::vector<int32_t> h_mode;         // per instance: 0 window, 1 two-pass
   std::vector<int32_t> h_halo;         // per instance window halo L (0 if none)
@@ -282,9 +281,8 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
       w.xcd_stride = (c->nwin + 7) / 8;
       const int grid = 8 * w.xcd_stride;
       mark(stage == 1 ? HSGN_K_WIN1 : HSGN_K_WIN2, true);
-      if (c->win_nt == 512 && c->win_k == 8) launch_win<512, 8>(c, w, grid, stage);
-      else if (c->win_nt == 512) launch_win<512, 4>(c, w, grid, stage);
-      else launch_win<256, 8>(c, w, grid, stage);
+      if (c->win_nt == 512) launch_win<512, kWK>(c, w, grid, stage);
+      else launch_win<256, kWK>(c, w, grid, stage);
       mark(stage == 1 ? HSGN_K_WIN1 : HSGN_K_WIN2, false);
     }
   }
@@ -353,7 +351,7 @@ int make_plan(hsgn_ctx* c) {
   std::vector<TileDesc> ex_all, ex_multi;
   std::vector<int32_t> ex_inst;
   std::vector<WinDesc> win;
-  const int WN = c->win_nt * c->win_k;
+  const int WN = c->win_nt * kWK;
   const int Lmax = WN / 4;
   c->h_mode.assign(c->n_inst, 1);
   c->h_halo.assign(c->n_inst, 0);
@@ -691,12 +689,10 @@ int hsgn_get_dt(hsgn_ctx* c, double* d_dt) {
 
 int hsgn_set_solver(hsgn_ctx* c, int32_t mode) {
   if (!c) return HSGN_EINVAL;
-  if (mode != HSGN_SOLVER_AUTO && mode != HSGN_SOLVER_EXACT && mode != HSGN_SOLVER_AUTO_SMALL &&
-      mode != HSGN_SOLVER_AUTO_K4)
+  if (mode != HSGN_SOLVER_AUTO && mode != HSGN_SOLVER_EXACT && mode != HSGN_SOLVER_AUTO_SMALL)
     return fail(c, HSGN_EINVAL, "hsgn_set_solver: unknown mode %d", mode);
   c->solver = mode == HSGN_SOLVER_EXACT ? HSGN_SOLVER_EXACT : HSGN_SOLVER_AUTO;
   c->win_nt = mode == HSGN_SOLVER_AUTO_SMALL ? 256 : 512;
-  c->win_k = mode == HSGN_SOLVER_AUTO_K4 ? 4 : kWK;
   int rc = enter(c);
   if (rc) return rc;
   rc = make_plan(c);
@@ -712,7 +708,7 @@ int hsgn_plan_info(hsgn_ctx* c, int32_t* h_mode, int32_t* h_halo, int32_t* h_cou
     h_counts[0] = c->nwin;
     h_counts[1] = c->n_ex_tiles;
     h_counts[2] = c->n_ex_multi;
-    h_counts[3] = c->win_nt * c->win_k;
+    h_counts[3] = c->win_nt * kWK;
   }
   return HSGN_OK;
 }

@@ -18,9 +18,8 @@ LIB_PATH = os.path.join(HERE, "libhsgn.so")
 HSGN_OK, HSGN_EINVAL, HSGN_EHIP, HSGN_ENONPHYS, HSGN_ENONCOERCIVE, HSGN_ENOMEM = 0, -1, -2, -3, -4, -5
 FLAG_NONPHYS, FLAG_NONCOERCIVE = 1, 2
 KERNEL_KINDS = ("dt", "reduce1", "rsolve1", "stage1", "reduce2", "rsolve2", "stage2", "win1", "win2")
-SOLVER_AUTO, SOLVER_EXACT, SOLVER_AUTO_SMALL, SOLVER_AUTO_K4 = 0, 1, 2, 3
-SOLVERS = {"auto": SOLVER_AUTO, "exact": SOLVER_EXACT, "auto_small": SOLVER_AUTO_SMALL,
-           "auto_k4": SOLVER_AUTO_K4}
+SOLVER_AUTO, SOLVER_EXACT, SOLVER_AUTO_SMALL = 0, 1, 2
+SOLVERS = {"auto": SOLVER_AUTO, "exact": SOLVER_EXACT, "auto_small": SOLVER_AUTO_SMALL}
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 
 
@@ -116,8 +115,8 @@ class Solver:
 
     def set_solver(self, mode):
         """mode: "auto" (windowed single pass where certified), "exact"
-        (two-pass partition solve), "auto_small" (2048-row windows, 256
-        threads) or "auto_k4" (2048-row windows, 512 threads x 4 rows)."""
+        (two-pass partition solve) or "auto_small" (2048-row windows, 256
+        threads)."""
         m = SOLVERS[mode] if isinstance(mode, str) else int(mode)
         self._check(lib().hsgn_set_solver(self._h, m), "hsgn_set_solver")
 

@@ -102,7 +102,7 @@ def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", 
     return worst
 
 
-SOLVERS = ["auto", "exact", "auto_small", "auto_k4"]
+SOLVERS = ["auto", "exact", "auto_small"]
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
@@ -233,7 +233,7 @@ def test_window_plan_covers_every_cell_once():
     assert (info["halo"][info["mode"] == 0] > 0).all()
 
 
-@pytest.mark.parametrize("solver", ["auto", "exact", "auto_k4"])
+@pytest.mark.parametrize("solver", ["auto", "exact"])
 def test_coercivity_loss_flagged_at_the_oracle_step(solver):
     """Instance 84 of the batched bar (N = 586, lambda = 1e3): its solitary
     wave steepens over the bar crest and the oracle's stage 2 of step 368
