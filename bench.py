@@ -22,14 +22,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+# sources of the windowed stage kernel (the dominant kernel of the benchmark)
 CSRC = [os.path.join(ROOT, "paper_2510_07539_amd", "csrc", f)
-        for f in ("hsgn.hip", "hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp")]
+        for f in ("hsgn_kernels.hpp", "hsgn_window.hpp")]
 
 # HBM traffic of the dominant kernel measured with rocprofv3 --pmc (FETCH_SIZE
-# and WRITE_SIZE in separate runs), scaled by the same counters on a plain
-# copy of known size.  Keyed by the hash of the kernel sources it was taken
-# on; reported as null once the sources change.
-TRAFFIC = {}
+# and WRITE_SIZE in separate runs, `bench.py --probe`), scaled by the same
+# counters on a plain 512 MiB copy (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0).
+# Keyed by the hash of the kernel's sources; reported as null once they change.
+TRAFFIC = {
+    "cf6a4e07ace53dc2": {"kernel": "win2", "workload": "batched_bar",
+                         "fetch_bytes": 4594529921, "write_bytes": 3170134763,
+                         "bytes_per_launch": 7764664683},
+}
 
 
 def src_hash():
@@ -182,6 +187,8 @@ def main():
     ap.add_argument("--timed-steps", type=int, default=10)
     ap.add_argument("--solver", default="auto", choices=["auto", "exact", "auto_small"])
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the gradient workload (one timed adjoint), one JSON line")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: a plain copy of known size, then eager steps")
     args = ap.parse_args()
@@ -197,6 +204,9 @@ def main():
     import torch
     from paper_2510_07539_amd.hsgn import Solver
 
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_cost(reps=1)}))
+        return
     wl, desc = make_workload(args.workload)
     bed = wl.b is not None
     s = Solver.from_workload(wl, solver=args.solver)
