@@ -75,6 +75,7 @@ struct hsgn_ctx {
   double* const* io_un = nullptr;
   double* const* io_u1 = nullptr;
   double* const* io_out = nullptr;
+  bool io_stage1_only = false;  // the step stops after stage 1 (U^(1) only)
   double* d_dt = nullptr;
   double* d_t = nullptr;
   unsigned long long* d_smax = nullptr;
@@ -252,7 +253,8 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
   hipLaunchKernelGGL(hsgn::k_dt, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_inst, c->d_dt,
                      c->d_t, c->d_smax, c->d_umax, c->d_status);
   mark(HSGN_K_DT, false);
-  for (int stage = 1; stage <= 2; ++stage) {
+  const int last_stage = c->io_stage1_only ? 1 : 2;
+  for (int stage = 1; stage <= last_stage; ++stage) {
     StageArgs a = stage_args(c, stage);
     if (c->n_ex_multi > 0) {
       a.tiles = c->d_ex_tiles_multi;
@@ -294,14 +296,17 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
 }
 
 
-// One step between explicit buffers (no rotation of the state buffers).
+// One step between explicit buffers (no rotation of the state buffers);
+// with out == NULL only stage 1 runs.
 int enqueue_step_io(hsgn_ctx* c, double* const* un, double* const* u1, double* const* out) {
   c->io_un = un;
   c->io_u1 = u1;
   c->io_out = out;
+  c->io_stage1_only = out == nullptr;
   const int cur = c->cur, nxt = c->nxt;
   const int rc = enqueue_step(c);
   c->io_un = c->io_u1 = c->io_out = nullptr;
+  c->io_stage1_only = false;
   c->cur = cur;
   c->nxt = nxt;
   return rc;
@@ -1085,8 +1090,9 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
     for (int k = 0; k < ks && seg != nseg - 1; ++k) {
       double* un[4] = {un_of(k, 0), un_of(k, 1), un_of(k, 2), un_of(k, 3)};
       double* u1[4] = {tape(k, 4), tape(k, 5), tape(k, 6), tape(k, 7)};
-      double* const* out = (k + 1 < ks) ? nullptr : c->buf[c->nxt];
+      // the last step needs only U^(1): its U^{n+1} is the next checkpoint
       double* nx[4];
+      double* const* out = nullptr;
       if (k + 1 < ks) {
         for (int f = 0; f < 4; ++f) nx[f] = tape(k + 1, f);
         out = nx;

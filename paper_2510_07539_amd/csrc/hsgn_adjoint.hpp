@@ -835,12 +835,24 @@ __global__ __launch_bounds__(NT) void k_adj_r2(AdjSolveArgs P) {
   const double* rhs = P.hba + o;
   double y[K], v[K], w[K];
   if (act) {
+    // every row of the chunk is loaded before the elimination starts (the
+    // K loads of one lane share cache lines; issued together they are
+    // served by one fetch)
+    double Lo[K], Di[K], Up[K], Rh[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int r = f + (i < k ? i : k - 1);
+      Lo[i] = lo[r];
+      Di[i] = di[r];
+      Up[i] = up[r];
+      Rh[i] = rhs[r];
+    }
     double cp[K];
     double cprev = 0.0, yprev = 0.0, vprev = 1.0, wprev = 0.0;
 #pragma unroll
     for (int i = 1; i < K - 1; ++i) {
       if (i <= k - 2) {
-        const double l = lo[f + i], d = di[f + i], u = up[f + i], r = rhs[f + i];
+        const double l = Lo[i], d = Di[i], u = Up[i], r = Rh[i];
         const double inv = 1.0 / (d - l * cprev);
         const bool lastint = (i == k - 2);
         cprev = lastint ? 0.0 : u * inv;
@@ -866,9 +878,8 @@ __global__ __launch_bounds__(NT) void k_adj_r2(AdjSolveArgs P) {
         w[i] = wn;
       }
     }
-    const int l = f + k - 1;
-    double R0[4] = {lo[f], di[f], up[f], rhs[f]};
-    double R1[4] = {lo[l], di[l], up[l], rhs[l]};
+    double R0[4] = {Lo[0], Di[0], Up[0], Rh[0]};
+    double R1[4] = {Lo[K - 1], Di[K - 1], Up[K - 1], Rh[K - 1]};  // row k-1 (clamped)
     if (k > 2) {
       double vk = 0.0, wk = 0.0, yk = 0.0;
 #pragma unroll

@@ -17,8 +17,8 @@ def declared():
 
 def test_header_declares_the_boundary():
     names = declared()
-    for need in ("hsgn_init", "hsgn_step", "hsgn_run", "hsgn_set_state", "hsgn_get_state",
-                 "hsgn_status", "hsgn_last_error", "hsgn_destroy"):
+    for need in ("hsgn_init", "hsgn_step", "hsgn_run", "hsgn_adjoint", "hsgn_set_state",
+                 "hsgn_get_state", "hsgn_status", "hsgn_last_error", "hsgn_destroy"):
         assert need in names
 
 
@@ -40,6 +40,9 @@ def test_null_arguments_are_rejected_without_a_device():
     h = ctypes.c_void_p()
     assert L.hsgn_init(ctypes.byref(h), 0, None, None, None, None) == -1
     assert L.hsgn_step(None, 1) == -1
+    assert L.hsgn_run(None, 1, 2) == -1
+    assert L.hsgn_adjoint(None, 1, 1, 1, None, None, None, None, None, None) == -1
+    assert L.hsgn_set_solver(None, 0) == -1
     L.hsgn_destroy(None)
 
 
