@@ -185,7 +185,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-instance", action="store_true")
     ap.add_argument("--timed-steps", type=int, default=10)
-    ap.add_argument("--solver", default="auto", choices=["auto", "exact", "auto_small"])
+    ap.add_argument("--solver", default="tune", choices=["tune", "auto", "exact", "auto_small"],
+                    help="tune: the library times every mode on the workload and keeps the fastest")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the gradient workload (one timed adjoint), one JSON line")
@@ -209,7 +210,11 @@ def main():
         return
     wl, desc = make_workload(args.workload)
     bed = wl.b is not None
-    s = Solver.from_workload(wl, solver=args.solver)
+    s = Solver.from_workload(wl, solver=None if args.solver == "tune" else args.solver)
+    tuned = None
+    if args.solver == "tune" and not args.probe:
+        chosen, tms = s.autotune(4)
+        tuned = {"kept": chosen, "ms_per_step": {k: round(v, 4) for k, v in tms.items()}}
     plan = s.plan_info()
 
     if args.probe:
@@ -279,7 +284,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n_inst": wl.n_inst, "cells": wl.n_cells,
-                   "graph_block_steps": args.block, "solver": args.solver,
+                   "graph_block_steps": args.block,
+                   "solver": tuned["kept"] if tuned else args.solver, "autotune": tuned,
                    "windows": plan["windows"], "window_rows": plan["window_rows"],
                    "two_pass_tiles": plan["exact_tiles"]},
         "roofline": roof,

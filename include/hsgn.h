@@ -131,6 +131,15 @@ int hsgn_run(hsgn_ctx* ctx, int32_t nsteps, int32_t block);
 #define HSGN_SOLVER_AUTO_SMALL 2
 int hsgn_set_solver(hsgn_ctx* ctx, int32_t mode);
 
+/* Autotuner: time each solver mode (HSGN_SOLVER_AUTO, HSGN_SOLVER_EXACT,
+ * HSGN_SOLVER_AUTO_SMALL) for nsteps eager steps on the loaded state, keep
+ * the fastest, and leave the state (with time, status and speed bounds)
+ * as it was.  h_ms (host, 3 doubles or NULL): milliseconds per step of each
+ * mode, indexed by the mode's value; h_mode (host or NULL): the mode kept.
+ * The modes agree with each other to rounding.  Allocates a copy of the
+ * state for its duration; synchronises the stream. */
+int hsgn_autotune(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_mode);
+
 /* Plan of the loaded state (host arrays, any may be NULL): h_mode[j] = 0
  * windowed / 1 exact two-pass; h_halo[j] = halo rows L of instance j;
  * h_counts[4] = {windows, two-pass tiles, two-pass instances with more than

@@ -788,6 +788,89 @@ int hsgn_step_timed(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_count)
   return leave(c);
 }
 
+// Autotuner: time every solver configuration on the loaded state and keep
+// the fastest.  The state (and time, status, speed bounds) is saved before
+// the trials and restored after each of them.
+int hsgn_autotune(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_mode) {
+  if (!c) return HSGN_EINVAL;
+  if (nsteps < 1) return fail(c, HSGN_EINVAL, "hsgn_autotune: nsteps < 1");
+  int rc = enter(c);
+  if (rc) return rc;
+  const size_t nc = (size_t)c->ncell, ni = (size_t)c->n_inst;
+  double *s_state = nullptr, *s_t = nullptr;
+  unsigned long long* s_sp = nullptr;
+  int32_t* s_st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (s_state) hipFree(s_state);
+    if (s_t) hipFree(s_t);
+    if (s_sp) hipFree(s_sp);
+    if (s_st) hipFree(s_st);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  rc = dmalloc(c, &s_state, 4 * nc);
+  if (!rc) rc = dmalloc(c, &s_t, ni);
+  if (!rc) rc = dmalloc(c, &s_sp, 3 * ni);
+  if (!rc) rc = dmalloc(c, &s_st, ni);
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = fail(c, HSGN_EHIP, "hsgn_autotune: hipEventCreate failed");
+  if (rc) {
+    cleanup();
+    return rc;
+  }
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
+  };
+  const size_t fb = nc * sizeof(double), ib = ni * sizeof(double), ub = ni * sizeof(unsigned long long);
+  auto save = [&]() {
+    bool ok = true;
+    for (int f = 0; f < 4; ++f) ok &= cp(s_state + f * nc, c->buf[c->cur][f], fb);
+    ok &= cp(s_t, c->d_t, ib) && cp(s_sp, c->d_smax, ub) && cp(s_sp + ni, c->d_umax, ub) &&
+          cp(s_sp + 2 * ni, c->d_hmax, ub) && cp(s_st, c->d_status, ni * sizeof(int32_t));
+    return ok;
+  };
+  auto restore = [&]() {
+    bool ok = true;
+    for (int f = 0; f < 4; ++f) ok &= cp(c->buf[c->cur][f], s_state + f * nc, fb);
+    ok &= cp(c->d_t, s_t, ib) && cp(c->d_smax, s_sp, ub) && cp(c->d_umax, s_sp + ni, ub) &&
+          cp(c->d_hmax, s_sp + 2 * ni, ub) && cp(c->d_status, s_st, ni * sizeof(int32_t));
+    return ok;
+  };
+  auto set_mode = [&](int mode) {
+    c->solver = mode == HSGN_SOLVER_EXACT ? HSGN_SOLVER_EXACT : HSGN_SOLVER_AUTO;
+    c->win_nt = mode == HSGN_SOLVER_AUTO_SMALL ? 256 : 512;
+    return make_plan(c);
+  };
+  const int modes[3] = {HSGN_SOLVER_AUTO, HSGN_SOLVER_EXACT, HSGN_SOLVER_AUTO_SMALL};
+  double ms[3] = {0, 0, 0};
+  if (!save()) rc = fail(c, HSGN_EHIP, "hsgn_autotune: state copy failed");
+  for (int k = 0; k < 3 && !rc; ++k) {
+    rc = set_mode(modes[k]);
+    if (!rc) rc = enqueue_step(c);  // first launch of this configuration
+    if (!rc && !restore()) rc = fail(c, HSGN_EHIP, "hsgn_autotune: state copy failed");
+    if (!rc && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(c, HSGN_EHIP, "hipEventRecord");
+    for (int s = 0; s < nsteps && !rc; ++s) rc = enqueue_step(c);
+    if (!rc && hipEventRecord(e1, c->stream) != hipSuccess) rc = fail(c, HSGN_EHIP, "hipEventRecord");
+    float f = 0.0f;
+    if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&f, e0, e1) != hipSuccess))
+      rc = fail(c, HSGN_EHIP, "hsgn_autotune: event timing failed");
+    ms[modes[k]] = (double)f / nsteps;
+    if (!rc && !restore()) rc = fail(c, HSGN_EHIP, "hsgn_autotune: state copy failed");
+  }
+  int best = HSGN_SOLVER_AUTO;
+  for (int m : modes)
+    if (ms[m] < ms[best]) best = m;
+  if (!rc) rc = set_mode(best);
+  if (!rc && hipStreamSynchronize(c->stream) != hipSuccess)
+    rc = fail(c, HSGN_EHIP, "hsgn_autotune: hipStreamSynchronize failed");
+  cleanup();
+  if (rc) return rc;
+  if (h_ms) std::memcpy(h_ms, ms, sizeof ms);
+  if (h_mode) *h_mode = best;
+  return leave(c);
+}
+
 int hsgn_status(hsgn_ctx* c, int32_t* h_flags) {
   if (!c) return HSGN_EINVAL;
   std::vector<int32_t> f(c->n_inst);

@@ -59,6 +59,8 @@ def lib():
         L.hsgn_set_solver.argtypes = [vp, C.c_int32]
         L.hsgn_plan_info.restype = C.c_int
         L.hsgn_plan_info.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.hsgn_autotune.restype = C.c_int
+        L.hsgn_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.hsgn_adjoint.restype = C.c_int
         L.hsgn_adjoint.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp]
         L.hsgn_status.restype = C.c_int
@@ -119,6 +121,15 @@ class Solver:
         threads)."""
         m = SOLVERS[mode] if isinstance(mode, str) else int(mode)
         self._check(lib().hsgn_set_solver(self._h, m), "hsgn_set_solver")
+
+    def autotune(self, nsteps=4):
+        """Time every solver mode on the loaded state, keep the fastest, leave
+        the state unchanged.  Returns (kept mode name, {mode name: ms/step})."""
+        ms = (C.c_double * 3)()
+        mode = C.c_int32(0)
+        self._check(lib().hsgn_autotune(self._h, int(nsteps), ms, C.byref(mode)), "hsgn_autotune")
+        names = {v: k for k, v in SOLVERS.items()}
+        return names[mode.value], {names[m]: ms[m] for m in range(3)}
 
     def plan_info(self):
         mode = np.zeros(self.n_inst, dtype=np.int32)

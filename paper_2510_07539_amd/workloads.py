@@ -277,3 +277,72 @@ def adjoint_bar(n_inst=1024, N=4096, dx=0.04, h0=0.4, lam=1000.0, seed=5, seed_t
     gauges = np.array([[int((gi + 0.5) * N / n_gauge) for gi in range(n_gauge)]] * n_inst,
                       dtype=np.int32)
     return AdjointCase(wl, np.concatenate(zs), np.concatenate(zts), gauges, nsteps, K)
+
+
+# --------------------------------------------------------------------------
+# The paper's other test problems (Sec. 6.1, 6.2, 6.4, 7) as seeded-free
+# synthetic inputs.  Their reference solutions are not available; the
+# library is checked against the oracle on them.  The paper runs them at
+# larger CFL numbers with a Rusanov speed of |u|; with the speed
+# |u| + sqrt(g h) used here they run at CFL 0.9.
+# --------------------------------------------------------------------------
+def gaussian_bell(N=5000, xa=-200.0, xb=200.0, A=1.0, h_inf=1.0, lam=100.0, nsteps=100,
+                  bc=BC_TRANSMISSIVE) -> Workload:
+    """Sec. 6.1: h = h_inf + A exp(-x^2 / 20) at rest over a flat bed."""
+    dx = (xb - xa) / N
+    x = xa + (np.arange(N) + 0.5) * dx
+    h = h_inf + A * np.exp(-x * x / 20.0)
+    z = np.zeros(N)
+    return _pack("gaussian_bell", [_part(N, dx, lam, bc, h, z, z)], nsteps, dict(lam=lam))
+
+
+def smooth_hump(N=5000, xa=-150.0, xb=150.0, A=1.0, h0=1.0, u0=1e-2, lam=500.0,
+                nsteps=100) -> Workload:
+    """Sec. 6.2: b = (h0 + A exp(-2 (x + 50)^2)) / 20, free surface
+    h0 + A exp(-x^2), uniform velocity u0, transmissive."""
+    dx = (xb - xa) / N
+    x = xa + (np.arange(N) + 0.5) * dx
+    b = (h0 + A * np.exp(-2.0 * (x + 50.0) ** 2)) / 20.0
+    h = h0 + A * np.exp(-x * x) - b
+    u = np.full(N, u0)
+    z = np.zeros(N)
+    return _pack("smooth_hump", [_part(N, dx, lam, BC_TRANSMISSIVE, h, u, z, b=b)], nsteps,
+                 dict(lam=lam))
+
+
+def favre(eps=1.1, N=5000, xa=-50.0, xb=50.0, h0=0.2, lam=100.0, nsteps=100, g=G) -> Workload:
+    """Sec. 6.4: undular bore.  Upstream depth h1 = eps h0, jump velocity
+    from the Rankine-Hugoniot condition, tanh transition of width 5 h0:
+    h = h0 + (h1 - h0) s / 2, u = u1 s / 2, s = 1 - tanh(x / (5 h0))."""
+    dx = (xb - xa) / N
+    x = xa + (np.arange(N) + 0.5) * dx
+    h1 = eps * h0
+    u1 = np.sqrt(g * (h1 + h0) / (2.0 * h0 * h1)) * (h1 - h0)
+    al = 5.0 * h0
+    s = 1.0 - np.tanh(x / al)
+    ds = -(1.0 - np.tanh(x / al) ** 2) / al
+    h = h0 + 0.5 * (h1 - h0) * s
+    u = 0.5 * u1 * s
+    ux = 0.5 * u1 * ds
+    return _pack("favre", [_part(N, dx, lam, BC_TRANSMISSIVE, h, u, ux, g=g)], nsteps,
+                 dict(eps=eps, lam=lam))
+
+
+def shelf(N=5000, L=280.0, h0=1.0, A=0.2, x0=80.0, lam=500.0, nsteps=100) -> Workload:
+    """Sec. 7: solitary wave (crest at x0) travelling onto a 1:20 ramp from
+    depth h0 to h0 - 0.5 between x = 130 and 140 m; transmissive."""
+    dx = L / N
+    x = (np.arange(N) + 0.5) * dx
+    b = np.clip((x - 130.0) / 20.0, 0.0, 0.5)
+    hs, u, ux = soliton(x, h0, A, x0)
+    h = hs - b
+    return _pack("shelf", [_part(N, dx, lam, BC_TRANSMISSIVE, h, u, ux, b=b)], nsteps,
+                 dict(lam=lam))
+
+
+def paper_tests(nsteps=100) -> Workload:
+    """One batch of the four test problems above, at several lambda and bore
+    amplitudes."""
+    parts = [gaussian_bell(lam=100.0), gaussian_bell(lam=5000.0), smooth_hump(lam=500.0),
+             favre(eps=1.1, lam=100.0), favre(eps=1.3, lam=500.0), shelf(lam=500.0)]
+    return concat("paper_tests", parts, nsteps=nsteps)

@@ -269,3 +269,36 @@ def test_coercivity_loss_flagged_at_the_oracle_step(solver):
     for a, c in ((h1, h2), (q1, q2), (m1, m2), (W1, W2)):
         assert torch.equal(a, c)
     s.close()
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_paper_test_problems(solver):
+    """The paper's Gaussian bell (lambda 100 and 5000), smooth hump, Favre
+    bores (eps 1.1 and 1.3) and shelf, 5000 cells each, 300 steps."""
+    compare(WL.paper_tests(), 300, label="paper tests", solver=solver)
+
+
+def test_autotune_keeps_state_and_fastest_mode():
+    """The autotuner leaves the loaded state, time and status untouched
+    (bitwise), keeps the mode with the smallest measured time, and the
+    solver then still matches the oracle."""
+    Solver = _solver()
+    wl = WL.concat("tune", [WL.batched_bar(n_inst=6, seed=9, n_lo=600, n_hi=9000, nsteps=20),
+                            WL.solitary(N=3000, L=750.0, lam=1000.0, t_end=0.0, nsteps=20)],
+                   nsteps=20)
+    s = Solver.from_workload(wl)
+    (h0, q0, m0, W0), t0 = s.get_state()
+    kept, ms = s.autotune(3)
+    note("autotune: kept %s, ms/step %s" % (kept, ms))
+    assert kept == min(ms, key=ms.get)
+    (h1, q1, m1, W1), t1 = s.get_state()
+    for a, b in ((h0, h1), (q0, q1), (m0, m1), (W0, W1), (t0, t1)):
+        assert torch.equal(a, b)
+    rc, flags = s.status()
+    assert rc == 0
+    s.step(20)
+    (h, q, m, W), t = s.get_state()
+    U = [x.cpu().numpy() for x in (h, q, m, W)]
+    for j in range(wl.n_inst):
+        check_instance(j, U, wl, 20)
+    s.close()
