@@ -16,6 +16,8 @@
  * tridiagonal (cyclic when periodic) system for the new depth from the
  * linearised pressure (Sec. 3.1, eq. hnew; differenced in conservative
  * pressure form), and back-substitution of momentum, h*eta and h*w.
+ * With order = 1 a step is that Stage alone, with tau = dt and no
+ * reconstruction (first order in time and space).
  * The time step is CFL dx / max(|u| + sqrt(g h)), capped by the material
  * CFL max|u| dt/dx <= mcfl (Sec. 3.3 eq. MCFL and Sec. 5).
  *
@@ -71,6 +73,10 @@ typedef struct {
   double t_end;          /* > 0: clamp the last step to t_end, then freeze  */
   int32_t bc;            /* hsgn_bc                                         */
   int32_t has_bathymetry;/* 1: use the bed b of this instance; 0: flat      */
+  int32_t order;         /* 2 (or 0): the two-stage IMEX step; 1: the
+                            first-order scheme of Sec. 4.2 as printed: one
+                            stage with tau = dt and no reconstruction (face
+                            values = cell values).  Same for every instance. */
 } hsgn_params;
 
 typedef struct hsgn_ctx hsgn_ctx;
@@ -180,7 +186,8 @@ int hsgn_step_timed(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_coun
  *  d_loss: device [n_inst]; d_grad_zeta0, d_grad_b: device, offsets[n_inst]
  *    doubles or NULL; when both are NULL only the loss is computed (no
  *    reverse sweep, no adjoint workspace).
- * Every instance must use a fixed step (dt_fixed > 0, t_end <= 0), so that
+ * Only for the two-stage step (order 2).  Every instance must use a fixed
+ * step (dt_fixed > 0, t_end <= 0), so that
  * the step map is differentiable, and every gauge cell must lie in its
  * instance (else HSGN_EINVAL).  Forward steps use the solver plan made from
  * the initial state (the status flags are cleared first, as by

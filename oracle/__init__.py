@@ -54,7 +54,8 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [("g", C.c_double), ("lam", C.c_double), ("dx", C.c_double),
                 ("cfl", C.c_double), ("mcfl", C.c_double), ("dt_fixed", C.c_double),
-                ("t_end", C.c_double), ("bc", C.c_int), ("has_b", C.c_int)]
+                ("t_end", C.c_double), ("bc", C.c_int), ("has_b", C.c_int),
+                ("order", C.c_int)]
 
 
 class StageDbg(C.Structure):
@@ -106,8 +107,8 @@ def _p(a):
 
 
 def make_params(g=9.81, lam=100.0, dx=1.0, cfl=0.9, mcfl=0.5, dt_fixed=0.0,
-                t_end=0.0, bc=BC_PERIODIC, has_b=0) -> Params:
-    return Params(g, lam, dx, cfl, mcfl, dt_fixed, t_end, int(bc), int(has_b))
+                t_end=0.0, bc=BC_PERIODIC, has_b=0, order=2) -> Params:
+    return Params(g, lam, dx, cfl, mcfl, dt_fixed, t_end, int(bc), int(has_b), int(order))
 
 
 def gamma() -> float:

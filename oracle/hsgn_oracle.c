@@ -224,20 +224,22 @@ int FN(or_stage)(int n, const or_params* p, double tau, const real_t* bin,
 
   /* (1) Explicit Rusanov fluxes of q u, m u, W u at every face, from the
    * unlimited component-wise linear reconstruction of U_E (Sec. 4.1:
-   * slope (v_{i+1} - v_{i-1})/(2 dx), face values v_i +- slope dx/2). */
+   * slope (v_{i+1} - v_{i-1})/(2 dx), face values v_i +- slope dx/2); the
+   * first-order scheme uses the cell values (sl = 0). */
+  const double sl = p->order == 1 ? 0.0 : 0.25;
   for (int k = 0; k <= n; ++k) {
     int im1 = gidx(k - 2, n, bc), i0 = gidx(k - 1, n, bc);
     int i1 = gidx(k, n, bc), i2 = gidx(k + 1, n, bc);
     /* left state: cell k-1 at its right face; right state: cell k at its
      * left face. */
-    real_t hL = hE[i0] + 0.25 * (hE[i1] - hE[im1]);
-    real_t hR = hE[i1] - 0.25 * (hE[i2] - hE[i0]);
-    real_t qL = qE[i0] + 0.25 * (qE[i1] - qE[im1]);
-    real_t qR = qE[i1] - 0.25 * (qE[i2] - qE[i0]);
-    real_t mL = mE[i0] + 0.25 * (mE[i1] - mE[im1]);
-    real_t mR = mE[i1] - 0.25 * (mE[i2] - mE[i0]);
-    real_t WL = WE[i0] + 0.25 * (WE[i1] - WE[im1]);
-    real_t WR = WE[i1] - 0.25 * (WE[i2] - WE[i0]);
+    real_t hL = hE[i0] + sl * (hE[i1] - hE[im1]);
+    real_t hR = hE[i1] - sl * (hE[i2] - hE[i0]);
+    real_t qL = qE[i0] + sl * (qE[i1] - qE[im1]);
+    real_t qR = qE[i1] - sl * (qE[i2] - qE[i0]);
+    real_t mL = mE[i0] + sl * (mE[i1] - mE[im1]);
+    real_t mR = mE[i1] - sl * (mE[i2] - mE[i0]);
+    real_t WL = WE[i0] + sl * (WE[i1] - WE[im1]);
+    real_t WR = WE[i1] - sl * (WE[i2] - WE[i0]);
     if (!(RE(hL) > 0.0) || !(RE(hR) > 0.0)) rc = OR_ENONPHYS;
     real_t uL = qL / hL, uR = qR / hR;
     real_t sL = RABS(uL) + RSQRT(g * hL), sR = RABS(uR) + RSQRT(g * hR);
@@ -250,8 +252,8 @@ int FN(or_stage)(int n, const or_params* p, double tau, const real_t* bin,
     real_t r_0 = (zf - b[i0]) * (zf - b[i0]);
     real_t r_1 = (zf - b[i1]) * (zf - b[i1]);
     real_t r_2 = (zf - b[i2]) * (zf - b[i2]);
-    real_t mhL = r_0 + 0.25 * (r_1 - r_m1);
-    real_t mhR = r_1 - 0.25 * (r_2 - r_0);
+    real_t mhL = r_0 + sl * (r_1 - r_m1);
+    real_t mhR = r_1 - sl * (r_2 - r_0);
     Fq[k] = 0.5 * (qL * uL + qR * uR - a * (qR - qL));
     FW[k] = 0.5 * (WL * uL + WR * uR - a * (WR - WL));
     Fm[k] = 0.5 * (mL * uL + mR * uR - a * ((mR - mL) - (mhR - mhL)));
@@ -408,6 +410,22 @@ int FN(or_step)(int n, const or_params* p, const real_t* b,
   double dt = FN(or_dt)(n, p, h, q, *t);
   if (dt_out) *dt_out = dt;
   if (!(dt > 0.0)) return OR_OK; /* frozen instance */
+  if (p->order == 1) {
+    /* first-order scheme (Sec. 4.2 as printed): one stage with tau = dt,
+     * explicit terms and old values both from U^n */
+    size_t n1 = (size_t)n;
+    real_t* o = (real_t*)malloc(4 * n1 * sizeof(real_t));
+    if (!o) return OR_EINVAL;
+    int rc1 = FN(or_stage)(n, p, dt, b, h, q, m, W, h, q, m, W, o, o + n1, o + 2 * n1,
+                           o + 3 * n1, NULL);
+    memcpy(h, o, n1 * sizeof(real_t));
+    memcpy(q, o + n1, n1 * sizeof(real_t));
+    memcpy(m, o + 2 * n1, n1 * sizeof(real_t));
+    memcpy(W, o + 3 * n1, n1 * sizeof(real_t));
+    free(o);
+    *t += dt;
+    return rc1;
+  }
   double tau = OR_GAMMA * dt;
   size_t nc = (size_t)n;
   real_t* buf = (real_t*)malloc(12 * nc * sizeof(real_t));

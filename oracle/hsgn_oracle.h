@@ -28,6 +28,8 @@ typedef struct {
   double t_end;    /* > 0: clamp the last step to t_end; <= 0: no clamp */
   int bc;          /* 0 periodic, 1 transmissive */
   int has_b;       /* 1: bed b is used; 0: flat bottom (b ignored) */
+  int order;       /* 1: first-order scheme (one stage, tau = dt, no
+                      reconstruction); otherwise the two-stage IMEX step */
 } or_params;
 
 /* Optional per-stage intermediates (any pointer may be NULL). Cell arrays

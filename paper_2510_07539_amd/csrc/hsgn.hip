@@ -76,6 +76,7 @@ struct hsgn_ctx {
   double* const* io_u1 = nullptr;
   double* const* io_out = nullptr;
   bool io_stage1_only = false;  // the step stops after stage 1 (U^(1) only)
+  int order = 2;                // 2: two-stage IMEX step; 1: one first-order stage
   double* d_dt = nullptr;
   double* d_t = nullptr;
   unsigned long long* d_smax = nullptr;
@@ -207,13 +208,18 @@ StageArgs stage_args(hsgn_ctx* c, int stage) {
   std::memset(&a, 0, sizeof a);
   double* const* un = c->io_un ? c->io_un : c->buf[c->cur];
   double* const* u1 = c->io_u1 ? c->io_u1 : c->buf[c->s1];
-  double* const* out = stage == 1 ? u1 : (c->io_out ? c->io_out : c->buf[c->nxt]);
+  // first-order scheme: its single stage writes U^{n+1}
+  double* const* out = (stage == 1 && c->order != 1)
+                           ? u1
+                           : (c->io_out ? c->io_out : c->buf[c->nxt]);
   a.un_h = un[0]; a.un_q = un[1]; a.un_m = un[2]; a.un_W = un[3];
   a.u1_h = u1[0]; a.u1_q = u1[1]; a.u1_m = u1[2]; a.u1_W = u1[3];
   a.o_h = out[0]; a.o_q = out[1]; a.o_m = out[2]; a.o_W = out[3];
   a.b = c->d_b;
   a.inst = c->d_inst;
   a.dt = c->d_dt;
+  a.tau_factor = c->order == 1 ? 1.0 : hsgn::kGamma;
+  a.slope = c->order == 1 ? 0.0 : 0.25;
   a.rlo = c->d_rlo; a.rdi = c->d_rdi; a.rup = c->d_rup; a.rrhs = c->d_rrhs;
   a.rx = c->d_rx;
   a.smax = c->d_smax;
@@ -253,7 +259,7 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
   hipLaunchKernelGGL(hsgn::k_dt, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_inst, c->d_dt,
                      c->d_t, c->d_smax, c->d_umax, c->d_status);
   mark(HSGN_K_DT, false);
-  const int last_stage = c->io_stage1_only ? 1 : 2;
+  const int last_stage = (c->io_stage1_only || c->order == 1) ? 1 : 2;
   for (int stage = 1; stage <= last_stage; ++stage) {
     StageArgs a = stage_args(c, stage);
     if (c->n_ex_multi > 0) {
@@ -288,6 +294,11 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
       mark(stage == 1 ? HSGN_K_WIN1 : HSGN_K_WIN2, false);
     }
   }
+  if (c->order == 1) {  // speed bound of the new state for the next step's dt
+    double* const* un = c->io_out ? c->io_out : c->buf[c->nxt];
+    hipLaunchKernelGGL(hsgn::k_speed<256>, dim3(c->ntiles_all), dim3(256), 0, c->stream,
+                       c->d_inst, c->d_tiles_all, un[0], un[1], c->d_smax, c->d_umax, c->d_hmax);
+  }
   HIPCHK(c, hipGetLastError());
   const int old = c->cur;
   c->cur = c->nxt;
@@ -319,9 +330,9 @@ int enqueue_step_io(hsgn_ctx* c, double* const* un, double* const* u1, double* c
 // (g h + (2 lambda / 3) / beta_1) at the deepest cell, times a margin.  The
 // halo makes rho^L <= 2^-60.  The kernel verifies the truncation on every
 // tile and flags the instance if it is not negligible.
-int halo_width(const hsgn_params& p, double smax, double hmax) {
+int halo_width(const hsgn_params& p, double smax, double hmax, double tau_factor) {
   const double dt = p.dt_fixed > 0 ? p.dt_fixed : p.cfl * p.dx / smax;
-  const double tau = hsgn::kGamma * dt;
+  const double tau = tau_factor * dt;
   const double b1 = 1.0 + p.lambda * tau * tau / (hmax * hmax);
   const double beta = p.g * hmax + (2.0 * p.lambda / 3.0) / b1;
   const double R = kWinMargin * (tau / p.dx) * (tau / p.dx) * beta;
@@ -369,7 +380,7 @@ int make_plan(hsgn_ctx* c) {
     std::vector<WinDesc> wj;
     if (c->solver != HSGN_SOLVER_EXACT && !c->h_smax.empty() && c->h_smax[j] > 0 &&
         c->h_hmax[j] > 0) {
-      const int L = halo_width(p, c->h_smax[j], c->h_hmax[j]);
+      const int L = halo_width(p, c->h_smax[j], c->h_hmax[j], c->order == 1 ? 1.0 : hsgn::kGamma);
       auto add = [&](int ws, int wl, int cs, int cl, int flags) {
         WinDesc d;
         d.inst = j; d.ws = ws; d.wl = wl; d.cs = cs; d.cl = cl; d.flags = flags;
@@ -484,6 +495,13 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
       rc = fail(c, HSGN_EINVAL, "instance %d uses a bed but d_b is NULL", j);
       break;
     }
+    const int ord = p.order == 1 ? 1 : 2;
+    if ((p.order != 0 && p.order != 1 && p.order != 2) || (j > 0 && ord != c->order)) {
+      rc = fail(c, HSGN_EINVAL, "instance %d: order must be 1 or 2 and the same for every "
+                "instance", j);
+      break;
+    }
+    c->order = ord;
     InstDesc& d = inst[j];
     std::memset(&d, 0, sizeof d);
     d.off = offsets[j];
@@ -1046,6 +1064,8 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   if (!c) return HSGN_EINVAL;
   if (nsteps < 1 || K < 1 || ng < 1 || !d_gauge || !d_target || !d_zeta0 || !d_loss)
     return fail(c, HSGN_EINVAL, "hsgn_adjoint: bad arguments");
+  if (c->order != 2)
+    return fail(c, HSGN_EINVAL, "hsgn_adjoint: the adjoint is of the two-stage IMEX step");
   for (int j = 0; j < c->n_inst; ++j) {
     if (!(c->params[j].dt_fixed > 0) || c->params[j].t_end > 0)
       return fail(c, HSGN_EINVAL,

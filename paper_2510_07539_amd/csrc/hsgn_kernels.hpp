@@ -80,6 +80,8 @@ struct StageArgs {
   double* __restrict__ rup;
   double* __restrict__ rrhs;
   const double* __restrict__ rx;  // reduced solution (read by the finish pass)
+  double tau_factor;  // stage step tau = tau_factor dt (gamma for the IMEX step, 1 first order)
+  double slope;       // reconstruction slope factor (1/4, or 0 first order)
   unsigned long long* __restrict__ smax;  // stage-2 speed bound accumulators
   unsigned long long* __restrict__ umax;
   int32_t* __restrict__ status;
@@ -146,21 +148,23 @@ __device__ __forceinline__ Cell load_old(const StageArgs& A, int64_t gi) {
 }
 
 // Rusanov flux at the face between cells c0 and c1 from the unlimited
-// component-wise linear reconstruction (slope (v_{i+1} - v_{i-1}) / (2 dx)).
+// component-wise linear reconstruction (slope (v_{i+1} - v_{i-1}) / (2 dx)):
+// face values v_i +/- sl (v_{i+1} - v_{i-1}) with sl = 1/4, or sl = 0 for
+// the first-order scheme (cell values).
 // The m-diffusion subtracts the jump of the face-local lake-at-rest moment
 // (zeta_f - b_j)^2, zeta_f = mean free surface of the two face cells.
 template <bool BED>
 __device__ __forceinline__ Flux face_flux(const Cell& cm, const Cell& c0, const Cell& c1,
                                           const Cell& c2, double bm, double b0, double b1,
-                                          double b2, double g, bool& bad) {
-  const double hL = c0.h + 0.25 * (c1.h - cm.h);
-  const double hR = c1.h - 0.25 * (c2.h - c0.h);
-  const double qL = c0.q + 0.25 * (c1.q - cm.q);
-  const double qR = c1.q - 0.25 * (c2.q - c0.q);
-  const double mL = c0.m + 0.25 * (c1.m - cm.m);
-  const double mR = c1.m - 0.25 * (c2.m - c0.m);
-  const double WL = c0.W + 0.25 * (c1.W - cm.W);
-  const double WR = c1.W - 0.25 * (c2.W - c0.W);
+                                          double b2, double g, double sl, bool& bad) {
+  const double hL = c0.h + sl * (c1.h - cm.h);
+  const double hR = c1.h - sl * (c2.h - c0.h);
+  const double qL = c0.q + sl * (c1.q - cm.q);
+  const double qR = c1.q - sl * (c2.q - c0.q);
+  const double mL = c0.m + sl * (c1.m - cm.m);
+  const double mR = c1.m - sl * (c2.m - c0.m);
+  const double WL = c0.W + sl * (c1.W - cm.W);
+  const double WR = c1.W - sl * (c2.W - c0.W);
   bad |= !(hL > 0.0) || !(hR > 0.0);
   const double uL = qL / hL;
   const double uR = qR / hR;
@@ -174,8 +178,8 @@ __device__ __forceinline__ Flux face_flux(const Cell& cm, const Cell& c0, const 
     const double r0 = (zf - b0) * (zf - b0);
     const double r1 = (zf - b1) * (zf - b1);
     const double r2 = (zf - b2) * (zf - b2);
-    const double mhL = r0 + 0.25 * (r1 - rm);
-    const double mhR = r1 - 0.25 * (r2 - r0);
+    const double mhL = r0 + sl * (r1 - rm);
+    const double mhR = r1 - sl * (r2 - r0);
     jm = jm - (mhR - mhL);
   }
   Flux F;
@@ -187,6 +191,7 @@ __device__ __forceinline__ Flux face_flux(const Cell& cm, const Cell& c0, const 
 
 struct PhysC {
   double g, lam, dx, tau, tdx, lt2, rr, tdx2;
+  double sl;  // reconstruction slope factor (1/4, or 0 for the first-order scheme)
 };
 
 // Dagger updates (Sec. 4.2, first three lines, with tau for dt) and frozen
@@ -278,8 +283,8 @@ __device__ Rec single_record(const StageArgs& A, int64_t base, int n, int bc, bo
     c[d] = load_E<STAGE>(A, base + jj);
     bb[d] = loadb<BED>(A, useb, base + jj);
   }
-  const Flux Fl = face_flux<BED>(c[0], c[1], c[2], c[3], bb[0], bb[1], bb[2], bb[3], P.g, bad);
-  const Flux Fr = face_flux<BED>(c[1], c[2], c[3], c[4], bb[1], bb[2], bb[3], bb[4], P.g, bad);
+  const Flux Fl = face_flux<BED>(c[0], c[1], c[2], c[3], bb[0], bb[1], bb[2], bb[3], P.g, P.sl, bad);
+  const Flux Fr = face_flux<BED>(c[1], c[2], c[3], c[4], bb[1], bb[2], bb[3], bb[4], P.g, P.sl, bad);
   const Cell o = load_old<STAGE>(A, base + wrap_idx(ir, n, bc));
   return cell_record<BED>(c[2], o, Fl, Fr, bb[1], bb[2], bb[3], P, bad, noncoer);
 }
@@ -465,7 +470,8 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs A) {
   P.g = I.g;
   P.lam = I.lam;
   P.dx = I.dx;
-  P.tau = kGamma * dt;
+  P.tau = A.tau_factor * dt;
+  P.sl = A.slope;
   P.tdx = P.tau / P.dx;
   P.lt2 = P.lam * P.tau * P.tau;
   P.rr = P.tdx * P.tdx;
@@ -489,14 +495,14 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs A) {
     double b1 = loadb<BED>(A, useb, base + wrap_idx(c0 - 1, n, bc));
     double b2 = loadb<BED>(A, useb, base + wrap_idx(c0, n, bc));
     double b3 = loadb<BED>(A, useb, base + wrap_idx(c0 + 1, n, bc));
-    Flux Fl = face_flux<BED>(w0, w1, w2, w3, b0, b1, b2, b3, P.g, bad);
+    Flux Fl = face_flux<BED>(w0, w1, w2, w3, b0, b1, b2, b3, P.g, P.sl, bad);
 #pragma unroll
     for (int j = 0; j < KMAX; ++j) {
       if (j < k) {
         const int64_t g4 = base + wrap_idx(c0 + j + 2, n, bc);
         const Cell w4 = load_E<STAGE>(A, g4);
         const double b4 = loadb<BED>(A, useb, g4);
-        const Flux Fr = face_flux<BED>(w1, w2, w3, w4, b1, b2, b3, b4, P.g, bad);
+        const Flux Fr = face_flux<BED>(w1, w2, w3, w4, b1, b2, b3, b4, P.g, P.sl, bad);
         const Cell o = load_old<STAGE>(A, base + c0 + j);
         ho[j] = o.h;
         rec[j] = cell_record<BED>(w2, o, Fl, Fr, b1, b2, b3, P, bad, noncoer);

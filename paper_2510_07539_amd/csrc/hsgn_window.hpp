@@ -54,15 +54,15 @@ __device__ __forceinline__ double frcp(double x) {
 template <bool BED>
 __device__ __forceinline__ Flux face_flux_fast(const Cell& cm, const Cell& c0, const Cell& c1,
                                                const Cell& c2, double bm, double b0, double b1,
-                                               double b2, double g, bool& bad) {
-  const double hL = c0.h + 0.25 * (c1.h - cm.h);
-  const double hR = c1.h - 0.25 * (c2.h - c0.h);
-  const double qL = c0.q + 0.25 * (c1.q - cm.q);
-  const double qR = c1.q - 0.25 * (c2.q - c0.q);
-  const double mL = c0.m + 0.25 * (c1.m - cm.m);
-  const double mR = c1.m - 0.25 * (c2.m - c0.m);
-  const double WL = c0.W + 0.25 * (c1.W - cm.W);
-  const double WR = c1.W - 0.25 * (c2.W - c0.W);
+                                               double b2, double g, double sl, bool& bad) {
+  const double hL = c0.h + sl * (c1.h - cm.h);
+  const double hR = c1.h - sl * (c2.h - c0.h);
+  const double qL = c0.q + sl * (c1.q - cm.q);
+  const double qR = c1.q - sl * (c2.q - c0.q);
+  const double mL = c0.m + sl * (c1.m - cm.m);
+  const double mR = c1.m - sl * (c2.m - c0.m);
+  const double WL = c0.W + sl * (c1.W - cm.W);
+  const double WR = c1.W - sl * (c2.W - c0.W);
   bad |= !(hL > 0.0) || !(hR > 0.0);
   const double uL = qL * frcp(hL);
   const double uR = qR * frcp(hR);
@@ -76,8 +76,8 @@ __device__ __forceinline__ Flux face_flux_fast(const Cell& cm, const Cell& c0, c
     const double r0 = (zf - b0) * (zf - b0);
     const double r1 = (zf - b1) * (zf - b1);
     const double r2 = (zf - b2) * (zf - b2);
-    const double mhL = r0 + 0.25 * (r1 - rm);
-    const double mhR = r1 - 0.25 * (r2 - r0);
+    const double mhL = r0 + sl * (r1 - rm);
+    const double mhR = r1 - sl * (r2 - r0);
     jm = jm - (mhR - mhL);
   }
   Flux F;
@@ -278,7 +278,8 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
   P.g = I.g;
   P.lam = I.lam;
   P.dx = I.dx;
-  P.tau = kGamma * dt;
+  P.tau = A.tau_factor * dt;
+  P.sl = A.slope;
   P.tdx = P.tau / P.dx;
   P.lt2 = P.lam * P.tau * P.tau;
   P.rr = P.tdx * P.tdx;
@@ -404,13 +405,13 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
   Rec recL, recR;
   if (act) {
     bool fb = false;
-    Flux Fl = face_flux_fast<BED>(E[1], E[2], E[3], E[4], Bv[1], Bv[2], Bv[3], Bv[4], P.g, fb);
+    Flux Fl = face_flux_fast<BED>(E[1], E[2], E[3], E[4], Bv[1], Bv[2], Bv[3], Bv[4], P.g, P.sl, fb);
     bad |= fb;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       bool bj = false, nj = false;  // flags of padding rows are dropped
       const Flux Fr = face_flux_fast<BED>(E[j + 2], E[j + 3], E[j + 4], E[j + 5], Bv[j + 2],
-                                          Bv[j + 3], Bv[j + 4], Bv[j + 5], P.g, bj);
+                                          Bv[j + 3], Bv[j + 4], Bv[j + 5], P.g, P.sl, bj);
       rec[j] = cell_record_fast<BED>(E[j + 3], O[j], Fl, Fr, Bv[j + 2], Bv[j + 3], Bv[j + 4], P,
                                      i2dx, bj, nj);
       if (p0 + j < wd.wl) {
@@ -426,9 +427,9 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
       recL = rec[0];
     } else {
       const Flux Fa = face_flux_fast<BED>(E[0], E[1], E[2], E[3], Bv[0], Bv[1], Bv[2], Bv[3],
-                                          P.g, bad);
+                                          P.g, P.sl, bad);
       const Flux Fb = face_flux_fast<BED>(E[1], E[2], E[3], E[4], Bv[1], Bv[2], Bv[3], Bv[4],
-                                          P.g, bad);
+                                          P.g, P.sl, bad);
       const int64_t gi = base + wrap_any(wd.ws - 1, n, bc);
       const Cell o = STAGE == 1 ? load_old<1>(A, gi) : load_old<2>(A, gi);
       recL = cell_record_fast<BED>(E[2], o, Fa, Fb, Bv[1], Bv[2], Bv[3], P, i2dx, bad, noncoer);
@@ -452,8 +453,8 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
       recR = last;
     } else {
       // row wl: faces between rows wl-1|wl and wl|wl+1
-      const Flux Fa = face_flux_fast<BED>(e2, e3, e4, e5, b2, b3, b4, b5, P.g, bad);
-      const Flux Fb = face_flux_fast<BED>(e3, e4, e5, e6, b3, b4, b5, b6, P.g, bad);
+      const Flux Fa = face_flux_fast<BED>(e2, e3, e4, e5, b2, b3, b4, b5, P.g, P.sl, bad);
+      const Flux Fb = face_flux_fast<BED>(e3, e4, e5, e6, b3, b4, b5, b6, P.g, P.sl, bad);
       const int64_t gi = base + wrap_any(wd.ws + wd.wl, n, bc);
       const Cell o = STAGE == 1 ? load_old<1>(A, gi) : load_old<2>(A, gi);
       recR = cell_record_fast<BED>(e4, o, Fa, Fb, b3, b4, b5, P, i2dx, bad, noncoer);

@@ -26,7 +26,7 @@ BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 class HsgnParams(C.Structure):
     _fields_ = [("g", C.c_double), ("lam", C.c_double), ("dx", C.c_double), ("cfl", C.c_double),
                 ("mcfl", C.c_double), ("dt_fixed", C.c_double), ("t_end", C.c_double),
-                ("bc", C.c_int32), ("has_bathymetry", C.c_int32)]
+                ("bc", C.c_int32), ("has_bathymetry", C.c_int32), ("order", C.c_int32)]
 
 
 _lib = None
@@ -102,7 +102,7 @@ class Solver:
         pa = (HsgnParams * self.n_inst)()
         for j, p in enumerate(params):
             pa[j] = HsgnParams(p["g"], p["lam"], p["dx"], p["cfl"], p["mcfl"], p["dt_fixed"],
-                               p["t_end"], int(p["bc"]), int(p["has_b"]))
+                               p["t_end"], int(p["bc"]), int(p["has_b"]), int(p.get("order", 2)))
         if b is not None:
             b = b.to(self.device, torch.float64).contiguous()
         self._b = b
@@ -142,9 +142,11 @@ class Solver:
                     exact_multi=int(cnt[2]), window_rows=int(cnt[3]))
 
     @classmethod
-    def from_workload(cls, wl, device="cuda", solver=None):
+    def from_workload(cls, wl, device="cuda", solver=None, order=2):
+        """order 2: the two-stage IMEX step; 1: the first-order scheme."""
         params = [dict(g=wl.g[j], lam=wl.lam[j], dx=wl.dx[j], cfl=wl.cfl[j], mcfl=wl.mcfl[j],
-                       dt_fixed=wl.dt_fixed[j], t_end=wl.t_end[j], bc=wl.bc[j], has_b=wl.has_b[j])
+                       dt_fixed=wl.dt_fixed[j], t_end=wl.t_end[j], bc=wl.bc[j], has_b=wl.has_b[j],
+                       order=order)
                   for j in range(wl.n_inst)]
         b = None if wl.b is None else torch.from_numpy(wl.b).to(device)
         s = cls(wl.offsets, params, b, device=device)

@@ -42,13 +42,13 @@ def field_err(a, ref):
     return d / scale if scale > 0 else d
 
 
-def check_instance(j, U, wl, nsteps, tol=TOL, seed=0, state_sens=False):
+def check_instance(j, U, wl, nsteps, tol=TOL, seed=0, state_sens=False, order=2):
     """Bars (1) and (2) for instance j; returns (state error, worst field ratio).
     state_sens: bar (1) becomes max(tol, 8 s) with s the oracle's own relative
     state sensitivity to a half-ulp perturbation (for runs that approach a
     loss of coercivity, where that sensitivity itself exceeds tol)."""
     n, prm, b, U0 = wl.instance(j)
-    p = O.make_params(**prm)
+    p = O.make_params(**prm, order=order)
     orc, Uo, to = O.run(p, b, U0, 0.0, nsteps)
     assert orc == 0, ("oracle", j, orc)
     rng = np.random.default_rng(seed + j)
@@ -72,11 +72,12 @@ def check_instance(j, U, wl, nsteps, tol=TOL, seed=0, state_sens=False):
     return state_err, worst, to
 
 
-def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", solver="auto"):
-    note("parity %s [%s]: %s, %d instances, %d cells, %d steps" % (
-        label, solver, wl.name, wl.n_inst, wl.n_cells, nsteps))
+def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", solver="auto",
+            order=2):
+    note("parity %s [%s, order %d]: %s, %d instances, %d cells, %d steps" % (
+        label, solver, order, wl.name, wl.n_inst, wl.n_cells, nsteps))
     Solver = _solver()
-    s = Solver.from_workload(wl, solver=solver)
+    s = Solver.from_workload(wl, solver=solver, order=order)
     info = s.plan_info()
     note("  plan: %d windows, %d two-pass tiles, halo max %d" % (
         info["windows"], info["exact_tiles"], int(info["halo"].max())))
@@ -94,7 +95,7 @@ def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", 
     worst = 0.0
     worst_ratio = 0.0
     for j in insts:
-        e, r, to = check_instance(j, U, wl, nsteps, tol)
+        e, r, to = check_instance(j, U, wl, nsteps, tol, order=order)
         assert abs(tg[j] - to) <= 1e-12 * max(1.0, abs(to)), (j, tg[j], to)
         worst = max(worst, e)
         worst_ratio = max(worst_ratio, r)
@@ -301,4 +302,30 @@ def test_autotune_keeps_state_and_fastest_mode():
     U = [x.cpu().numpy() for x in (h, q, m, W)]
     for j in range(wl.n_inst):
         check_instance(j, U, wl, 20)
+    s.close()
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_first_order_scheme(solver):
+    """The first-order scheme (one stage, tau = dt, no reconstruction) on a
+    mix: periodic solitary waves (one tile, several windows), the bar batch,
+    the dam break and the paper's shelf, 100 steps, through hsgn_run."""
+    wl = WL.concat("first-order", [
+        WL.solitary(N=800, lam=100.0, t_end=0.0),
+        WL.solitary(N=9000, L=2250.0, lam=1000.0, t_end=0.0),
+        WL.batched_bar(n_inst=4, seed=12, n_lo=700, n_hi=7000),
+        WL.dam_break(N=6000, xa=-90.0, xb=90.0),
+        WL.shelf()], nsteps=100)
+    compare(wl, 100, use_run=True, block=20, label="first order", solver=solver, order=1)
+
+
+def test_first_order_adjoint_is_rejected():
+    from paper_2510_07539_amd.hsgn import HsgnError
+    Solver = _solver()
+    wl = WL.solitary(N=200, L=50.0, t_end=0.0)
+    wl.dt_fixed[:] = 0.01
+    s = Solver.from_workload(wl, order=1)
+    z = torch.from_numpy(wl.h).cuda()
+    with pytest.raises(HsgnError):
+        s.adjoint(3, 2, torch.zeros((1, 1), dtype=torch.int32), torch.zeros((1, 3, 1)), z)
     s.close()

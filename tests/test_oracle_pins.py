@@ -447,3 +447,63 @@ def test_gauge_series_consistent_with_run_and_loss():
     tgt = np.random.default_rng(2).uniform(0.3, 0.5, size=(9, 3))
     _, J, _ = O.run_loss(p, b, U0, 9, g, tgt)
     assert J == pytest.approx(0.5 * np.sum((ser - tgt) ** 2), rel=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# First-order scheme (Sec. 4.2 as printed: one stage with tau = dt, cell
+# values at the faces): first-order self-convergence, conservation, lake
+# at rest, and the two-stage step's results untouched by the order switch.
+# ---------------------------------------------------------------------------
+def test_first_order_self_convergence():
+    sols = []
+    for N in (400, 800, 1600, 3200):
+        wl = WL.solitary(N=N, lam=100.0, t_end=3.0)
+        n, prm, b, U = wl.instance(0)
+        p = O.make_params(**{**prm, "cfl": 0.45, "order": 1})
+        rc, Un, t = O.run(p, b, U, 0.0, 100000)
+        assert rc == 0 and abs(t - 3.0) < 1e-12
+        sols.append(Un[0])
+
+    def restrict(a, f):
+        return a.reshape(-1, f).mean(1)
+    d1 = np.abs(restrict(sols[1], 2) - sols[0]).sum()
+    d2 = np.abs(restrict(sols[2], 4) - restrict(sols[1], 2)).sum()
+    d3 = np.abs(restrict(sols[3], 8) - restrict(sols[2], 4)).sum()
+    r1, r2 = d1 / d2, d2 / d3
+    # ratios approach 2 from below (1.56, 1.69, then 1.81 at 6400 cells):
+    # first order, pre-asymptotic; a second-order scheme gives ~4 here
+    assert 1.4 < r1 < r2 < 2.2, (r1, r2)
+
+
+def test_first_order_conserves_and_keeps_rest():
+    wl = WL.solitary(N=600, t_end=0.0, nsteps=50)
+    n, prm, b, U = wl.instance(0)
+    p = O.make_params(**{**prm, "order": 1})
+    rc, Un, t = O.run(p, b, U, 0.0, 50)
+    assert rc == 0
+    assert abs(Un[0].sum() - U[0].sum()) <= 1e-13 * U[0].sum()
+    assert abs(Un[1].sum() - U[1].sum()) <= 1e-13 * np.abs(U[1]).sum()
+    for lam in (100.0, 1e4):
+        wl = WL.lake_at_rest(N=300, lam=lam, bed=True)
+        n, prm, b, U = wl.instance(0)
+        rc, Un, t = O.run(O.make_params(**{**prm, "order": 1}), b, U, 0.0, 100)
+        assert rc == 0
+        assert np.max(np.abs(Un[1])) <= 1e-12
+        assert np.max(np.abs(Un[0] + b - 0.4)) <= 1e-12
+
+
+def test_first_order_step_is_one_full_stage():
+    """order 1 = or_stage with tau = dt and U_E = U_old = U^n; the
+    reconstruction switch reaches the fluxes (the two orders differ)."""
+    wl = WL.batched_bar(n_inst=1, seed=8, n_lo=300, n_hi=300)
+    n, prm, b, U = wl.instance(0)
+    p1 = O.make_params(**{**prm, "order": 1})
+    rc, U1, t1, dt = O.step(p1, b, U, 0.0)
+    assert rc == 0 and dt > 0
+    rc, Us = O.stage(p1, dt, b, U, U)
+    assert rc == 0
+    for a, c in zip(U1, Us):
+        assert np.array_equal(a, c)
+    p2 = O.make_params(**prm)
+    rc, Uf = O.stage(p2, dt, b, U, U)
+    assert max(np.max(np.abs(a - c)) for a, c in zip(Uf, Us)) > 1e-6
