@@ -72,16 +72,19 @@ def make_workload(name):
     if name == "solitary":
         w = WL.solitary(t_end=0.0)
         return w, "solitary: N=800 on [0,200] m, h0=1, a=0.2, lambda=100, periodic"
+    if name == "paper_tests":
+        return WL.paper_tests(), ("paper_tests: Gaussian bell (lambda 100, 5000), smooth hump, "
+                                  "Favre bores (eps 1.1, 1.3), shelf; 5000 cells each")
     raise SystemExit("unknown workload " + name)
 
 
-def per_instance_rate(wl, n_sample, steps):
+def per_instance_rate(wl, n_sample, steps, order=2):
     """Same kernels, one context per instance, eager launches in a host loop."""
     import numpy as np
     import torch
     from paper_2510_07539_amd.hsgn import Solver
     idx = np.linspace(0, wl.n_inst - 1, n_sample).astype(int)
-    solvers = [Solver.from_workload(wl.subset([int(j)])) for j in idx]
+    solvers = [Solver.from_workload(wl.subset([int(j)]), order=order) for j in idx]
     for s in solvers:
         s.step(1)
     torch.cuda.synchronize()
@@ -94,10 +97,10 @@ def per_instance_rate(wl, n_sample, steps):
     cells = int(sum(wl.sizes()[idx]))
     for s in solvers:
         s.close()
-    return 2.0 * cells * steps / el, el, n_sample
+    return float(order) * cells * steps / el, el, n_sample
 
 
-def cpu_baseline(wl, budget_s=15.0, n_sample=1024, max_steps=200):
+def cpu_baseline(wl, budget_s=15.0, n_sample=1024, max_steps=200, order=2):
     """The oracle (OpenMP over instances, all host threads) on a bounded
     sample: the first n_sample instances, in chunks of 5 steps until the time
     budget is spent or max_steps are done (past about 370 steps one
@@ -105,7 +108,7 @@ def cpu_baseline(wl, budget_s=15.0, n_sample=1024, max_steps=200):
     range the benchmark times)."""
     import oracle as O
     sub = wl.subset(range(min(n_sample, wl.n_inst)))
-    plist = [O.make_params(**sub.instance(j)[1]) for j in range(sub.n_inst)]
+    plist = [O.make_params(**sub.instance(j)[1], order=order) for j in range(sub.n_inst)]
     U = sub.state()
     t = [0.0] * sub.n_inst
     steps, el = 0, 0.0
@@ -118,7 +121,7 @@ def cpu_baseline(wl, budget_s=15.0, n_sample=1024, max_steps=200):
         if rc != 0:
             break
     cores = min(O.max_threads(), sub.n_inst)
-    rate = 2.0 * sub.n_cells * steps / el
+    rate = float(order) * sub.n_cells * steps / el
     return {"value": rate, "unit": "cell-stage updates/s", "cores": cores, "kind": "oracle",
             "sample": "first %d instances (%d cells) of the same workload, %d IMEX steps, %.1f s"
                       % (sub.n_inst, sub.n_cells, steps, el)}
@@ -188,6 +191,8 @@ def main():
     ap.add_argument("--solver", default="tune", choices=["tune", "auto", "exact", "auto_small"],
                     help="tune: the library times every mode on the workload and keeps the fastest")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--order", type=int, default=2, choices=[1, 2],
+                    help="2: the two-stage IMEX step; 1: the first-order scheme (one stage)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the gradient workload (one timed adjoint), one JSON line")
     ap.add_argument("--probe", action="store_true",
@@ -210,7 +215,8 @@ def main():
         return
     wl, desc = make_workload(args.workload)
     bed = wl.b is not None
-    s = Solver.from_workload(wl, solver=None if args.solver == "tune" else args.solver)
+    s = Solver.from_workload(wl, solver=None if args.solver == "tune" else args.solver,
+                             order=args.order)
     tuned = None
     if args.solver == "tune" and not args.probe:
         chosen, tms = s.autotune(4)
@@ -240,7 +246,7 @@ def main():
     if rc != 0:
         print("solver flagged %d instances" % int((flags != 0).sum()), file=sys.stderr)
         sys.exit(1)
-    cell_stages = 2.0 * wl.n_cells * args.steps
+    cell_stages = float(args.order) * wl.n_cells * args.steps  # stages per step = order
     value = cell_stages / el
     ms_step = 1e3 * el / args.steps
 
@@ -269,7 +275,8 @@ def main():
             "avg_launch_ms": round(ms_avg, 4),
             "alg_bytes_per_launch": alg_bytes,
             "alg_bytes_per_cell": bytes_per_cell(dom, bed)}
-    step_bytes = (bytes_per_cell("stage1", bed) + bytes_per_cell("stage2", bed)) / 2.0
+    step_bytes = (bytes_per_cell("stage1", bed) if args.order == 1 else
+                  (bytes_per_cell("stage1", bed) + bytes_per_cell("stage2", bed)) / 2.0)
     out = {
         "metric": "cell-stage updates/s (FP64, batched vs per-instance) at 1e-11 oracle match",
         "value": value,
@@ -284,7 +291,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n_inst": wl.n_inst, "cells": wl.n_cells,
-                   "graph_block_steps": args.block,
+                   "graph_block_steps": args.block, "order": args.order,
                    "solver": tuned["kept"] if tuned else args.solver, "autotune": tuned,
                    "windows": plan["windows"], "window_rows": plan["window_rows"],
                    "two_pass_tiles": plan["exact_tiles"]},
@@ -293,16 +300,16 @@ def main():
         "kernel_ms_per_step": {k: round(v[0] / args.timed_steps, 4) for k, v in kt.items() if v[1]},
     }
     if not args.no_per_instance and wl.n_inst > 1:
-        r, pel, ns = per_instance_rate(wl, 32, 3)
+        r, pel, ns = per_instance_rate(wl, 32, 3, order=args.order)
         out["per_instance"] = {"value": r, "unit": "cell-stage updates/s",
                                "sample": "%d instances spread over the batch, one context each, "
                                          "eager launches, 3 steps" % ns}
         out["batched_over_per_instance"] = value / r
     s.close()
-    if not args.no_adjoint and args.workload == "batched_bar":
+    if not args.no_adjoint and args.workload == "batched_bar" and args.order == 2:
         out["adjoint"] = adjoint_cost()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline(wl, order=args.order)
     print(json.dumps(out))
 
 

@@ -380,10 +380,10 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
         else if (f == 3) E[j].W = v;
         else Bv[j] = v;
       }
-      if (f < 4) {
+      if (STAGE == 2 && f < 4) {  // stage 1: the old state is U_E itself
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-          const double v = STAGE == 1 ? L.u.st.e[spad(p0 + 3 + j)] : L.u.st.o[spad(p0 + 3 + j)];
+          const double v = L.u.st.o[spad(p0 + 3 + j)];
           if (f == 0) O[j].h = v;
           else if (f == 1) O[j].q = v;
           else if (f == 2) O[j].m = v;
@@ -412,7 +412,8 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
       bool bj = false, nj = false;  // flags of padding rows are dropped
       const Flux Fr = face_flux_fast<BED>(E[j + 2], E[j + 3], E[j + 4], E[j + 5], Bv[j + 2],
                                           Bv[j + 3], Bv[j + 4], Bv[j + 5], P.g, P.sl, bj);
-      rec[j] = cell_record_fast<BED>(E[j + 3], O[j], Fl, Fr, Bv[j + 2], Bv[j + 3], Bv[j + 4], P,
+      rec[j] = cell_record_fast<BED>(E[j + 3], STAGE == 1 ? E[j + 3] : O[j], Fl, Fr, Bv[j + 2],
+                                     Bv[j + 3], Bv[j + 4], P,
                                      i2dx, bj, nj);
       if (p0 + j < wd.wl) {
         bad |= bj;
@@ -494,7 +495,7 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
       const Rec Lr = (j == 0) ? recL : rec[j > 0 ? j - 1 : 0];
       const Rec Rr = (j == K - 1 || j == jl) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
       double lo, di, up, rhs;
-      make_row<BED>(Lr, rec[j], Rr, O[j].h, P, lo, di, up, rhs);
+      make_row<BED>(Lr, rec[j], Rr, STAGE == 1 ? E[j + 3].h : O[j].h, P, lo, di, up, rhs);
       if (t == 0 && j == 0) {
         if (physL) {
           di += lo;
