@@ -242,16 +242,16 @@ void launch_win(hsgn_ctx* c, const hsgn::WinArgs& w, int grid, int stage) {
 }
 
 int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* tm = nullptr) {
+  bool marks_ok = true;  // timing events (measurement variant only)
   auto mark = [&](int kind, bool begin) {
-    if (!tm) return;
+    if (!tm || !marks_ok) return;
     if (begin) {
-      hipEvent_t a, b;
-      hipEventCreate(&a);
-      hipEventCreate(&b);
+      hipEvent_t a = nullptr, b = nullptr;
+      marks_ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
       tm->push_back({kind, {a, b}});
-      hipEventRecord(a, c->stream);
+      if (marks_ok) marks_ok = hipEventRecord(a, c->stream) == hipSuccess;
     } else {
-      hipEventRecord(tm->back().second.second, c->stream);
+      marks_ok = hipEventRecord(tm->back().second.second, c->stream) == hipSuccess;
     }
   };
   const int nb = (c->n_inst + 255) / 256;
@@ -300,6 +300,7 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
                        c->d_inst, c->d_tiles_all, un[0], un[1], c->d_smax, c->d_umax, c->d_hmax);
   }
   HIPCHK(c, hipGetLastError());
+  if (!marks_ok) return fail(c, HSGN_EHIP, "hsgn_step_timed: timing events failed");
   const int old = c->cur;
   c->cur = c->nxt;
   c->nxt = old;
@@ -919,7 +920,7 @@ const char* hsgn_last_error(const hsgn_ctx* c) { return c ? c->err.c_str() : "nu
 
 void hsgn_destroy(hsgn_ctx* c) {
   if (!c) return;
-  hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);  // nothing to report to: the context goes away
   free_all(c);
   delete c;
 }
