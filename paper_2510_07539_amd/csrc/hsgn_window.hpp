@@ -87,22 +87,15 @@ __device__ __forceinline__ Flux face_flux_fast(const Cell& cm, const Cell& c0, c
   return F;
 }
 
+// Frozen coefficients of a row (beta, S and, with a bed, phi and T) from
+// h_E, m_E and m-dagger (already in r.md); the bed value goes along.
 template <bool BED>
-__device__ __forceinline__ Rec cell_record_fast(const Cell& e, const Cell& o, const Flux& Fl,
-                                                const Flux& Fr, double bm, double bc, double bp,
-                                                const PhysC& P, double i2dx, bool& bad,
-                                                bool& noncoer) {
-  Rec r;
-  r.Wd = o.W - P.tdx * (Fr.W - Fl.W) + P.lam * P.tau;
-  double md = o.m - P.tdx * (Fr.m - Fl.m);
-  if (BED) md -= P.tau * 1.5 * e.q * ((bp - bm) * i2dx);
-  md += P.tau * r.Wd;
-  r.md = md;
-  r.qd = o.q - P.tdx * (Fr.q - Fl.q);
-  const double h = e.h;
+__device__ __forceinline__ void rec_coefs_fast(Rec& r, double h, double em, double bc,
+                                               const PhysC& P, bool& bad, bool& noncoer) {
+  const double md = r.md;
   bad |= !(h > 0.0);
   const double ih = frcp(h);
-  const double eh = e.m * ih * ih;
+  const double eh = em * ih * ih;
   const double alpha = -(2.0 * eh - 1.0) * ih * (1.0 / 3.0);
   const double a2 = P.g * h + P.lam * eh * eh - (P.lam / 3.0) * eh;
   const double b1 = 1.0 + P.lt2 * ih * ih;
@@ -122,6 +115,21 @@ __device__ __forceinline__ Rec cell_record_fast(const Cell& e, const Cell& o, co
     r.T = 0.0;
   }
   r.b = bc;
+}
+
+template <bool BED>
+__device__ __forceinline__ Rec cell_record_fast(const Cell& e, const Cell& o, const Flux& Fl,
+                                                const Flux& Fr, double bm, double bc, double bp,
+                                                const PhysC& P, double i2dx, bool& bad,
+                                                bool& noncoer) {
+  Rec r;
+  r.Wd = o.W - P.tdx * (Fr.W - Fl.W) + P.lam * P.tau;
+  double md = o.m - P.tdx * (Fr.m - Fl.m);
+  if (BED) md -= P.tau * 1.5 * e.q * ((bp - bm) * i2dx);
+  md += P.tau * r.Wd;
+  r.md = md;
+  r.qd = o.q - P.tdx * (Fr.q - Fl.q);
+  rec_coefs_fast<BED>(r, e.h, e.m, bc, P, bad, noncoer);
   return r;
 }
 
@@ -221,15 +229,17 @@ __device__ __forceinline__ int wrap_any(int i, int n, int bc) {
   return i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
 }
 
-template <int NT, int K>
+template <int NT, int K, bool BED>
 struct WinLds {
   static constexpr int WN = NT * K;
   static constexpr int SL = WN + 8;              // staged cells: window + 3 halo each side (+2)
   static constexpr int SP = SL + (SL >> 3) + 1;  // padded length
   union {
     struct {
-      double e[SP];   // staged explicit-state field (window + halo)
-      double o[SP];   // staged old-state field (stage 2)
+      double e[SP];             // staged explicit-state field (window + halo)
+      double o[SP];             // staged old-state field (stage 2)
+      double b[BED ? SP : 1];   // staged bed (kept through the sweep)
+      double ho[SP];            // old depth (kept until the rows are built)
     } st;
     Lds<NT> sys;
     struct {
@@ -241,7 +251,7 @@ struct WinLds {
 
 template <int NT, int K, bool BED, int STAGE>
 __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
-  __shared__ WinLds<NT, K> L;
+  __shared__ WinLds<NT, K, BED> L;
   const StageArgs& A = W.s;
   // consecutive windows of an instance run on the same XCD (blocks are
   // dealt round-robin over the 8 XCDs)
@@ -288,8 +298,13 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
   const bool useb = BED && I.has_b;
   bool bad = false, noncoer = false;
 
-  // ---- staging: window rows [ws, ws+wl) plus 3 halo cells each side.
-  // Staged index i <-> window row i - 3.  Rows past the window's real end
+  // ---- staging and explicit sweep, one field per round: h (with the bed),
+  // q, m, W.  A round stages the explicit state E (stage 2: kE0 U^n + kE1 U(1))
+  // and the old state O (stage 2: kT0 U^n + kT1 U(1)) of window rows
+  // [-3, wl + 3) through LDS with coalesced loads; each thread then reads the
+  // values of its K + 1 faces and K rows and keeps only per-face and per-row
+  // partial results.  The loads of the next round are in flight meanwhile.
+  // Staged index i <-> window row i - 3; rows past the window's real end
   // repeat row wl + 2 (their values only feed identity padding rows).
   if (t == 0) {
     L.misc[0] = 0.0;  // depth guesses beyond truncated edges (0 if physical)
@@ -308,22 +323,15 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
     if (bc == 0) return c < 0 ? c + n : (c >= n ? c - n : c);
     return c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
   };
-  // per-thread registers: explicit state at rows p0-3 .. p0+K+2 (K+6)
-  Cell E[K + 6];
-  double Bv[K + 6];
-  Cell O[K];
-  constexpr int NR = (WinLds<NT, K>::SL + NT - 1) / NT;  // staged elements per thread
-  const int nf = useb ? 5 : 4;
+  constexpr int NR = (WinLds<NT, K, BED>::SL + NT - 1) / NT;  // staged elements per thread
   auto fld = [&](int f, bool second) -> const double* {
     if (second) return f == 0 ? A.u1_h : f == 1 ? A.u1_q : f == 2 ? A.u1_m : A.u1_W;
-    return f == 0 ? A.un_h : f == 1 ? A.un_q : f == 2 ? A.un_m : f == 3 ? A.un_W : A.b;
+    return f == 0 ? A.un_h : f == 1 ? A.un_q : f == 2 ? A.un_m : A.un_W;
   };
-  // software pipeline over the fields: the loads of field f+1 are in flight
-  // while field f goes through LDS
-  double va[NR], vb[NR];
-  {
-    const double* un = fld(0, false);
-    const double* u1 = fld(0, true);
+  double va[NR], vb[NR], vc[NR];
+  auto load_round = [&](int f) {
+    const double* un = fld(f, false);
+    const double* u1 = fld(f, true);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int i = t + r * NT;
@@ -331,137 +339,214 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
         const int64_t gi = base + cell_of(i);
         va[r] = un[gi];
         if (STAGE == 2) vb[r] = u1[gi];
+        if (BED && f == 0 && useb) vc[r] = A.b[gi];
       }
     }
-  }
-#pragma unroll
-  for (int f = 0; f < 5; ++f) {
-    if (f >= nf) break;
-    double ea[NR], ob[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      if (STAGE == 1 || f == 4) {
-        ea[r] = va[r];
-        ob[r] = 0.0;
-      } else {
-        ea[r] = kE0 * va[r] + kE1 * vb[r];
-        ob[r] = kT0 * va[r] + kT1 * vb[r];
-      }
-    }
-    if (f + 1 < nf) {
-      const double* un = fld(f + 1, false);
-      const double* u1 = fld(f + 1, true);
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int i = t + r * NT;
-        if (i < SLn) {
-          const int64_t gi = base + cell_of(i);
-          va[r] = un[gi];
-          if (STAGE == 2 && f + 1 < 4) vb[r] = u1[gi];
-        }
-      }
-    }
+  };
+  auto put_round = [&](int f) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int i = t + r * NT;
       if (i < SLn) {
-        L.u.st.e[spad(i)] = ea[r];
-        if (STAGE == 2 && f < 4) L.u.st.o[spad(i)] = ob[r];
-      }
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int j = 0; j < K + 6; ++j) {
-        const double v = L.u.st.e[spad(p0 + j)];
-        if (f == 0) E[j].h = v;
-        else if (f == 1) E[j].q = v;
-        else if (f == 2) E[j].m = v;
-        else if (f == 3) E[j].W = v;
-        else Bv[j] = v;
-      }
-      if (STAGE == 2 && f < 4) {  // stage 1: the old state is U_E itself
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          const double v = L.u.st.o[spad(p0 + 3 + j)];
-          if (f == 0) O[j].h = v;
-          else if (f == 1) O[j].q = v;
-          else if (f == 2) O[j].m = v;
-          else O[j].W = v;
+        double* od = f == 0 ? L.u.st.ho : L.u.st.o;  // the old depth stays until the rows
+        if (STAGE == 1) {
+          L.u.st.e[spad(i)] = va[r];
+          if (f == 0) od[spad(i)] = va[r];
+        } else {
+          L.u.st.e[spad(i)] = kE0 * va[r] + kE1 * vb[r];
+          od[spad(i)] = kT0 * va[r] + kT1 * vb[r];
         }
+        if (BED && f == 0 && useb) L.u.st.b[spad(i)] = vc[r];
       }
     }
-    __syncthreads();
-  }
-  if (!useb) {
+  };
+  // face f (0..K) lies between rows p0 + f - 1 and p0 + f; its stencil is
+  // x[f .. f + 3] with x[i] the staged value of row p0 + i - 2
+  auto read_x = [&](double* x, const double* src) {
 #pragma unroll
-    for (int j = 0; j < K + 6; ++j) Bv[j] = 0.0;
-  }
-  // E[j] <-> window row p0 + j - 3; own rows are E[3..K+2]
+    for (int i = 0; i < K + 4; ++i) x[i] = src[spad(p0 + 1 + i)];
+  };
+  auto old_of = [&](const double* x, int j) -> double {
+    return STAGE == 1 ? x[j + 2] : L.u.st.o[spad(p0 + 3 + j)];
+  };
+  // bed of row p0 - 1 + i (i = 0..K+1); the staged bed stays in LDS
+  auto bed_row = [&](int i) -> double {
+    return (BED && useb) ? L.u.st.b[spad(p0 + 2 + i)] : 0.0;
+  };
 
-  // ---- sweep: records of own rows, plus the outer neighbour rows for the
-  // first and last active thread (needed by the edge rows).
+  load_round(0);
+  put_round(0);
+  load_round(1);
+  __syncthreads();
+  // round h (+ bed): face depths, the bed's rest-moment jump, own depths
+  double hL[K + 1], hR[K + 1], dmh[K + 1], eh[K];
+  unsigned badf = 0;  // bit f: a face depth of face f is not positive
+  if (act) {
+    double xh[K + 4], xb[K + 4];
+    read_x(xh, L.u.st.e);
+    if (BED && useb) {
+      read_x(xb, L.u.st.b);
+    } else {
+#pragma unroll
+      for (int i = 0; i < K + 4; ++i) xb[i] = 0.0;
+    }
+#pragma unroll
+    for (int f = 0; f <= K; ++f) {
+      hL[f] = xh[f + 1] + P.sl * (xh[f + 2] - xh[f]);
+      hR[f] = xh[f + 2] - P.sl * (xh[f + 3] - xh[f + 1]);
+      if (!(hL[f] > 0.0) || !(hR[f] > 0.0)) badf |= 1u << f;
+      dmh[f] = 0.0;
+      if (BED) {
+        const double zf = 0.5 * ((xh[f + 1] + xb[f + 1]) + (xh[f + 2] + xb[f + 2]));
+        const double rm = (zf - xb[f]) * (zf - xb[f]);
+        const double r0 = (zf - xb[f + 1]) * (zf - xb[f + 1]);
+        const double r1 = (zf - xb[f + 2]) * (zf - xb[f + 2]);
+        const double r2 = (zf - xb[f + 3]) * (zf - xb[f + 3]);
+        const double mhL = r0 + P.sl * (r1 - rm);
+        const double mhR = r1 - P.sl * (r2 - r0);
+        dmh[f] = mhR - mhL;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) eh[j] = xh[j + 2];
+  }
+  __syncthreads();
+  put_round(1);
+  load_round(2);
+  __syncthreads();
+  // round q: face velocities and Rusanov speeds, q-dagger
+  double uL[K + 1], uR[K + 1], ap[K + 1], qd[K], eq[K];
+  if (act) {
+    double xq[K + 4], Fq[K + 1];
+    read_x(xq, L.u.st.e);
+#pragma unroll
+    for (int f = 0; f <= K; ++f) {
+      const double qL = xq[f + 1] + P.sl * (xq[f + 2] - xq[f]);
+      const double qR = xq[f + 2] - P.sl * (xq[f + 3] - xq[f + 1]);
+      uL[f] = qL * frcp(hL[f]);
+      uR[f] = qR * frcp(hR[f]);
+      const double sL = fabs(uL[f]) + sqrt(P.g * hL[f]);
+      const double sR = fabs(uR[f]) + sqrt(P.g * hR[f]);
+      ap[f] = fmax(sL, sR);
+      Fq[f] = 0.5 * (qL * uL[f] + qR * uR[f] - ap[f] * (qR - qL));
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      qd[j] = old_of(xq, j) - P.tdx * (Fq[j + 1] - Fq[j]);
+      eq[j] = xq[j + 2];
+    }
+  }
+  __syncthreads();
+  put_round(2);
+  load_round(3);
+  __syncthreads();
+  // round m: m-dagger before the relaxation term
+  double mdp[K], em[K];
+  if (act) {
+    double xm[K + 4], Fm[K + 1];
+    read_x(xm, L.u.st.e);
+#pragma unroll
+    for (int f = 0; f <= K; ++f) {
+      const double mL = xm[f + 1] + P.sl * (xm[f + 2] - xm[f]);
+      const double mR = xm[f + 2] - P.sl * (xm[f + 3] - xm[f + 1]);
+      double jm = mR - mL;
+      if (BED) jm = jm - dmh[f];
+      Fm[f] = 0.5 * (mL * uL[f] + mR * uR[f] - ap[f] * jm);
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      double md = old_of(xm, j) - P.tdx * (Fm[j + 1] - Fm[j]);
+      if (BED) md -= P.tau * 1.5 * eq[j] * ((bed_row(j + 2) - bed_row(j)) * i2dx);
+      mdp[j] = md;
+      em[j] = xm[j + 2];
+    }
+  }
+  __syncthreads();
+  put_round(3);
+  __syncthreads();
+  // round W: W-dagger, m-dagger, and the rows' frozen coefficients
   Rec rec[K];
   Rec recL, recR;
   if (act) {
-    bool fb = false;
-    Flux Fl = face_flux_fast<BED>(E[1], E[2], E[3], E[4], Bv[1], Bv[2], Bv[3], Bv[4], P.g, P.sl, fb);
-    bad |= fb;
+    double xw[K + 4], Fw[K + 1];
+    read_x(xw, L.u.st.e);
+#pragma unroll
+    for (int f = 0; f <= K; ++f) {
+      const double WL = xw[f + 1] + P.sl * (xw[f + 2] - xw[f]);
+      const double WR = xw[f + 2] - P.sl * (xw[f + 3] - xw[f + 1]);
+      Fw[f] = 0.5 * (WL * uL[f] + WR * uR[f] - ap[f] * (WR - WL));
+    }
+    bad |= (badf & 1u) != 0;
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      bool bj = false, nj = false;  // flags of padding rows are dropped
-      const Flux Fr = face_flux_fast<BED>(E[j + 2], E[j + 3], E[j + 4], E[j + 5], Bv[j + 2],
-                                          Bv[j + 3], Bv[j + 4], Bv[j + 5], P.g, P.sl, bj);
-      rec[j] = cell_record_fast<BED>(E[j + 3], STAGE == 1 ? E[j + 3] : O[j], Fl, Fr, Bv[j + 2],
-                                     Bv[j + 3], Bv[j + 4], P,
-                                     i2dx, bj, nj);
+      Rec r;
+      r.Wd = old_of(xw, j) - P.tdx * (Fw[j + 1] - Fw[j]) + P.lam * P.tau;
+      r.md = mdp[j] + P.tau * r.Wd;
+      r.qd = qd[j];
+      bool bj = ((badf >> (j + 1)) & 1u) != 0, nj = false;  // flags of padding rows are dropped
+      rec_coefs_fast<BED>(r, eh[j], em[j], bed_row(j + 1), P, bj, nj);
+      rec[j] = r;
       if (p0 + j < wd.wl) {
         bad |= bj;
         noncoer |= nj;
       }
-      Fl = Fr;
     }
   }
-  // outer neighbours (row -1 and row wl); their old state comes from global
+  // outer neighbours (row -1 and row wl) of truncated edges: record of the
+  // row at staged index i0 + 2 from cells i0 .. i0 + 4, read from global
+  // memory with the staging's arithmetic
+  auto outer_record = [&](int i0, double& hrow) -> Rec {
+    Cell c[5];
+    double bb[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      const int64_t gi = base + cell_of(i0 + d);
+      if (STAGE == 1) {
+        c[d].h = A.un_h[gi];
+        c[d].q = A.un_q[gi];
+        c[d].m = A.un_m[gi];
+        c[d].W = A.un_W[gi];
+      } else {
+        c[d].h = kE0 * A.un_h[gi] + kE1 * A.u1_h[gi];
+        c[d].q = kE0 * A.un_q[gi] + kE1 * A.u1_q[gi];
+        c[d].m = kE0 * A.un_m[gi] + kE1 * A.u1_m[gi];
+        c[d].W = kE0 * A.un_W[gi] + kE1 * A.u1_W[gi];
+      }
+      bb[d] = (BED && useb) ? A.b[gi] : 0.0;
+    }
+    const Flux Fa = face_flux_fast<BED>(c[0], c[1], c[2], c[3], bb[0], bb[1], bb[2], bb[3], P.g,
+                                        P.sl, bad);
+    const Flux Fb = face_flux_fast<BED>(c[1], c[2], c[3], c[4], bb[1], bb[2], bb[3], bb[4], P.g,
+                                        P.sl, bad);
+    const int64_t go = base + wrap_any(wd.ws + i0 - 1, n, bc);
+    const Cell o = STAGE == 1 ? load_old<1>(A, go) : load_old<2>(A, go);
+    hrow = c[2].h;
+    return cell_record_fast<BED>(c[2], o, Fa, Fb, bb[1], bb[2], bb[3], P, i2dx, bad, noncoer);
+  };
   if (act && t == 0) {
     if (physL) {
       recL = rec[0];
     } else {
-      const Flux Fa = face_flux_fast<BED>(E[0], E[1], E[2], E[3], Bv[0], Bv[1], Bv[2], Bv[3],
-                                          P.g, P.sl, bad);
-      const Flux Fb = face_flux_fast<BED>(E[1], E[2], E[3], E[4], Bv[1], Bv[2], Bv[3], Bv[4],
-                                          P.g, P.sl, bad);
-      const int64_t gi = base + wrap_any(wd.ws - 1, n, bc);
-      const Cell o = STAGE == 1 ? load_old<1>(A, gi) : load_old<2>(A, gi);
-      recL = cell_record_fast<BED>(E[2], o, Fa, Fb, Bv[1], Bv[2], Bv[3], P, i2dx, bad, noncoer);
-      L.misc[0] = E[2].h;  // depth guess beyond the left edge
+      double hg;
+      recL = outer_record(0, hg);
+      L.misc[0] = hg;  // depth guess beyond the left edge
     }
   }
   if (act && t == na - 1) {
     const int jl = wd.wl - 1 - p0;  // last real row in this thread (0..K-1)
     Rec last = rec[0];
-    Cell e2 = E[0], e3 = E[0], e4 = E[0], e5 = E[0], e6 = E[0];
-    double b2 = 0, b3 = 0, b4 = 0, b5 = 0, b6 = 0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-      if (j == jl) {
-        last = rec[j];
-        e2 = E[j + 2]; e3 = E[j + 3]; e4 = E[j + 4]; e5 = E[j + 5]; e6 = E[j + 6 < K + 6 ? j + 6 : K + 5];
-        b2 = Bv[j + 2]; b3 = Bv[j + 3]; b4 = Bv[j + 4]; b5 = Bv[j + 5]; b6 = Bv[j + 6 < K + 6 ? j + 6 : K + 5];
-      }
-    }
+    for (int j = 0; j < K; ++j)
+      if (j == jl) last = rec[j];
     if (physR) {
       recR = last;
     } else {
-      // row wl: faces between rows wl-1|wl and wl|wl+1
-      const Flux Fa = face_flux_fast<BED>(e2, e3, e4, e5, b2, b3, b4, b5, P.g, P.sl, bad);
-      const Flux Fb = face_flux_fast<BED>(e3, e4, e5, e6, b3, b4, b5, b6, P.g, P.sl, bad);
-      const int64_t gi = base + wrap_any(wd.ws + wd.wl, n, bc);
-      const Cell o = STAGE == 1 ? load_old<1>(A, gi) : load_old<2>(A, gi);
-      recR = cell_record_fast<BED>(e4, o, Fa, Fb, b3, b4, b5, P, i2dx, bad, noncoer);
-      L.misc[1] = e4.h;  // depth guess beyond the right edge
+      double hg;
+      recR = outer_record(wd.wl + 1, hg);
+      L.misc[1] = hg;  // depth guess beyond the right edge
     }
   }
+  __syncthreads();  // the staging buffers are reused below
   // share chunk-end records
   if (act) {
     L.u.nb.beta[0][t] = rec[0].beta; L.u.nb.S[0][t] = rec[0].S; L.u.nb.qd[0][t] = rec[0].qd;
@@ -495,7 +580,7 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
       const Rec Lr = (j == 0) ? recL : rec[j > 0 ? j - 1 : 0];
       const Rec Rr = (j == K - 1 || j == jl) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
       double lo, di, up, rhs;
-      make_row<BED>(Lr, rec[j], Rr, STAGE == 1 ? E[j + 3].h : O[j].h, P, lo, di, up, rhs);
+      make_row<BED>(Lr, rec[j], Rr, L.u.st.ho[spad(p0 + 3 + j)], P, lo, di, up, rhs);
       if (t == 0 && j == 0) {
         if (physL) {
           di += lo;
