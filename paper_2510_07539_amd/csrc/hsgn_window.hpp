@@ -250,8 +250,16 @@ struct WinLds {
 };
 
 template <int NT, int K, bool BED, int STAGE>
-__global__ __launch_bounds__(NT) void k_win(WinArgs W) {
+__global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   __shared__ WinLds<NT, K, BED> L;
+  // Register budget: 256 per lane (two waves per SIMD).  Stage 1 fits it
+  // when it also (i) addresses the staged loads with 32-bit offsets from
+  // per-instance base pointers, (ii) forms the bed's rest-moment jump in
+  // the m round from the depths it keeps, and (iii) reads neighbour beds
+  // from the staged bed instead of carrying them in the records.  For
+  // stage 2 these choices measured slower (its spills move, not vanish),
+  // so it keeps the plain forms.  Both give the same values.
+  constexpr bool kLean = STAGE == 1;
   const StageArgs& A = W.s;
   // consecutive windows of an instance run on the same XCD (blocks are
   // dealt round-robin over the 8 XCDs)
@@ -329,6 +337,12 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
     return f == 0 ? A.un_h : f == 1 ? A.un_q : f == 2 ? A.un_m : A.un_W;
   };
   double va[NR], vb[NR], vc[NR];
+  int cidx[NR];  // instance-relative cells of the staged elements (lean form)
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int i = t + r * NT;
+    cidx[r] = (kLean && i < SLn) ? cell_of(i) : 0;
+  }
   auto load_round = [&](int f) {
     const double* un = fld(f, false);
     const double* u1 = fld(f, true);
@@ -336,10 +350,16 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
     for (int r = 0; r < NR; ++r) {
       const int i = t + r * NT;
       if (i < SLn) {
-        const int64_t gi = base + cell_of(i);
-        va[r] = un[gi];
-        if (STAGE == 2) vb[r] = u1[gi];
-        if (BED && f == 0 && useb) vc[r] = A.b[gi];
+        if constexpr (kLean) {
+          va[r] = (un + base)[cidx[r]];
+          if (STAGE == 2) vb[r] = (u1 + base)[cidx[r]];
+          if (BED && f == 0 && useb) vc[r] = (A.b + base)[cidx[r]];
+        } else {
+          const int64_t gi = base + cell_of(i);
+          va[r] = un[gi];
+          if (STAGE == 2) vb[r] = u1[gi];
+          if (BED && f == 0 && useb) vc[r] = A.b[gi];
+        }
       }
     }
   };
@@ -378,13 +398,14 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
   put_round(0);
   load_round(1);
   __syncthreads();
-  // round h (+ bed): face depths, the bed's rest-moment jump, own depths
-  double hL[K + 1], hR[K + 1], dmh[K + 1], eh[K];
+  // round h (+ bed): face depths, the bed's rest-moment jump (plain form),
+  // depths of rows p0 - 1 .. p0 + K
+  double hL[K + 1], hR[K + 1], dmh[K + 1], hf[K + 2];
   unsigned badf = 0;  // bit f: a face depth of face f is not positive
   if (act) {
     double xh[K + 4], xb[K + 4];
     read_x(xh, L.u.st.e);
-    if (BED && useb) {
+    if (BED && useb && !kLean) {
       read_x(xb, L.u.st.b);
     } else {
 #pragma unroll
@@ -396,7 +417,7 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
       hR[f] = xh[f + 2] - P.sl * (xh[f + 3] - xh[f + 1]);
       if (!(hL[f] > 0.0) || !(hR[f] > 0.0)) badf |= 1u << f;
       dmh[f] = 0.0;
-      if (BED) {
+      if (BED && !kLean) {
         const double zf = 0.5 * ((xh[f + 1] + xb[f + 1]) + (xh[f + 2] + xb[f + 2]));
         const double rm = (zf - xb[f]) * (zf - xb[f]);
         const double r0 = (zf - xb[f + 1]) * (zf - xb[f + 1]);
@@ -408,7 +429,7 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
       }
     }
 #pragma unroll
-    for (int j = 0; j < K; ++j) eh[j] = xh[j + 2];
+    for (int i = 0; i < K + 2; ++i) hf[i] = xh[i + 1];
   }
   __syncthreads();
   put_round(1);
@@ -440,23 +461,45 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
   put_round(2);
   load_round(3);
   __syncthreads();
-  // round m: m-dagger before the relaxation term
+  // round m: m-dagger before the relaxation term; with a bed the m-diffusion
+  // subtracts the jump of the face-local rest moment (zeta_f - b)^2, formed
+  // here in the lean form
   double mdp[K], em[K];
   if (act) {
-    double xm[K + 4], Fm[K + 1];
+    double xm[K + 4], xb[K + 4], Fm[K + 1];
     read_x(xm, L.u.st.e);
+    if (BED && useb && kLean) {
+      read_x(xb, L.u.st.b);
+    } else {
+#pragma unroll
+      for (int i = 0; i < K + 4; ++i) xb[i] = 0.0;
+    }
 #pragma unroll
     for (int f = 0; f <= K; ++f) {
       const double mL = xm[f + 1] + P.sl * (xm[f + 2] - xm[f]);
       const double mR = xm[f + 2] - P.sl * (xm[f + 3] - xm[f + 1]);
       double jm = mR - mL;
-      if (BED) jm = jm - dmh[f];
+      if (BED && kLean) {
+        const double zf = 0.5 * ((hf[f] + xb[f + 1]) + (hf[f + 1] + xb[f + 2]));
+        const double rm = (zf - xb[f]) * (zf - xb[f]);
+        const double r0 = (zf - xb[f + 1]) * (zf - xb[f + 1]);
+        const double r1 = (zf - xb[f + 2]) * (zf - xb[f + 2]);
+        const double r2 = (zf - xb[f + 3]) * (zf - xb[f + 3]);
+        const double mhL = r0 + P.sl * (r1 - rm);
+        const double mhR = r1 - P.sl * (r2 - r0);
+        jm = jm - (mhR - mhL);
+      } else if (BED) {
+        jm = jm - dmh[f];
+      }
       Fm[f] = 0.5 * (mL * uL[f] + mR * uR[f] - ap[f] * jm);
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
       double md = old_of(xm, j) - P.tdx * (Fm[j + 1] - Fm[j]);
-      if (BED) md -= P.tau * 1.5 * eq[j] * ((bed_row(j + 2) - bed_row(j)) * i2dx);
+      if (BED) {
+        const double db = kLean ? xb[j + 3] - xb[j + 1] : bed_row(j + 2) - bed_row(j);
+        md -= P.tau * 1.5 * eq[j] * (db * i2dx);
+      }
       mdp[j] = md;
       em[j] = xm[j + 2];
     }
@@ -484,7 +527,7 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
       r.md = mdp[j] + P.tau * r.Wd;
       r.qd = qd[j];
       bool bj = ((badf >> (j + 1)) & 1u) != 0, nj = false;  // flags of padding rows are dropped
-      rec_coefs_fast<BED>(r, eh[j], em[j], bed_row(j + 1), P, bj, nj);
+      rec_coefs_fast<BED>(r, hf[j + 1], em[j], bed_row(j + 1), P, bj, nj);
       rec[j] = r;
       if (p0 + j < wd.wl) {
         bad |= bj;
@@ -550,19 +593,23 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
   // share chunk-end records
   if (act) {
     L.u.nb.beta[0][t] = rec[0].beta; L.u.nb.S[0][t] = rec[0].S; L.u.nb.qd[0][t] = rec[0].qd;
-    L.u.nb.phi[0][t] = rec[0].phi; L.u.nb.T[0][t] = rec[0].T; L.u.nb.b[0][t] = rec[0].b;
+    L.u.nb.phi[0][t] = rec[0].phi; L.u.nb.T[0][t] = rec[0].T;
+    if (!kLean) L.u.nb.b[0][t] = rec[0].b;
     L.u.nb.beta[1][t] = rec[K - 1].beta; L.u.nb.S[1][t] = rec[K - 1].S;
     L.u.nb.qd[1][t] = rec[K - 1].qd; L.u.nb.phi[1][t] = rec[K - 1].phi;
-    L.u.nb.T[1][t] = rec[K - 1].T; L.u.nb.b[1][t] = rec[K - 1].b;
+    L.u.nb.T[1][t] = rec[K - 1].T;
+    if (!kLean) L.u.nb.b[1][t] = rec[K - 1].b;
   }
   __syncthreads();
   if (act && t > 0) {
     recL.beta = L.u.nb.beta[1][t - 1]; recL.S = L.u.nb.S[1][t - 1]; recL.qd = L.u.nb.qd[1][t - 1];
-    recL.phi = L.u.nb.phi[1][t - 1]; recL.T = L.u.nb.T[1][t - 1]; recL.b = L.u.nb.b[1][t - 1];
+    recL.phi = L.u.nb.phi[1][t - 1]; recL.T = L.u.nb.T[1][t - 1];
+    if (!kLean) recL.b = L.u.nb.b[1][t - 1];
   }
   if (act && t < na - 1) {
     recR.beta = L.u.nb.beta[0][t + 1]; recR.S = L.u.nb.S[0][t + 1]; recR.qd = L.u.nb.qd[0][t + 1];
-    recR.phi = L.u.nb.phi[0][t + 1]; recR.T = L.u.nb.T[0][t + 1]; recR.b = L.u.nb.b[0][t + 1];
+    recR.phi = L.u.nb.phi[0][t + 1]; recR.T = L.u.nb.T[0][t + 1];
+    if (!kLean) recR.b = L.u.nb.b[0][t + 1];
   }
   const double gL = L.misc[0], gR = L.misc[1];
   __syncthreads();  // nb region is reused by the level-1 system below
@@ -580,7 +627,15 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
       const Rec Lr = (j == 0) ? recL : rec[j > 0 ? j - 1 : 0];
       const Rec Rr = (j == K - 1 || j == jl) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
       double lo, di, up, rhs;
-      make_row<BED>(Lr, rec[j], Rr, L.u.st.ho[spad(p0 + 3 + j)], P, lo, di, up, rhs);
+      // lean form: the beds of the row and its neighbours come from the
+      // staged bed (the records carry no copy of it)
+      Rec Lb = Lr, Cb = rec[j], Rb = Rr;
+      if (kLean) {
+        Lb.b = bed_row(j);
+        Cb.b = bed_row(j + 1);
+        Rb.b = bed_row(j + 2);
+      }
+      make_row<BED>(Lb, Cb, Rb, L.u.st.ho[spad(p0 + 3 + j)], P, lo, di, up, rhs);
       if (t == 0 && j == 0) {
         if (physL) {
           di += lo;
@@ -737,7 +792,7 @@ __global__ __launch_bounds__(NT) void k_win(WinArgs W) {
         const double Pp = Rr.S + Rr.beta * hp;
         double force = (Pp - Pm) * i2dx;
         if (BED) {
-          const double dbc = (Rr.b - Lr.b) * i2dx;
+          const double dbc = (kLean ? bed_row(j + 2) - bed_row(j) : Rr.b - Lr.b) * i2dx;
           const double pti = rec[j].T + rec[j].phi * h;
           force += 0.5 * P.g * (hp + hm) * dbc + 1.5 * pti * dbc;
         }
