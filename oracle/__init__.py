@@ -55,7 +55,7 @@ class Params(C.Structure):
     _fields_ = [("g", C.c_double), ("lam", C.c_double), ("dx", C.c_double),
                 ("cfl", C.c_double), ("mcfl", C.c_double), ("dt_fixed", C.c_double),
                 ("t_end", C.c_double), ("bc", C.c_int), ("has_b", C.c_int),
-                ("order", C.c_int)]
+                ("order", C.c_int), ("scheme", C.c_int)]
 
 
 class StageDbg(C.Structure):
@@ -75,6 +75,8 @@ def lib():
         L.or_stage.argtypes = [C.c_int, C.POINTER(Params), C.c_double, dp] + [dp] * 12 + [C.POINTER(StageDbg)]
         L.or_dt.restype = C.c_double
         L.or_dt.argtypes = [C.c_int, C.POINTER(Params), dp, dp, C.c_double]
+        L.or_dt_ex.restype = C.c_double
+        L.or_dt_ex.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, C.c_double]
         L.or_step.restype = C.c_int
         L.or_step.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, dp, dp]
         L.or_run.restype = C.c_int
@@ -106,9 +108,13 @@ def _p(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+SCHEME_SI, SCHEME_EXPLICIT = 0, 1
+
+
 def make_params(g=9.81, lam=100.0, dx=1.0, cfl=0.9, mcfl=0.5, dt_fixed=0.0,
-                t_end=0.0, bc=BC_PERIODIC, has_b=0, order=2) -> Params:
-    return Params(g, lam, dx, cfl, mcfl, dt_fixed, t_end, int(bc), int(has_b), int(order))
+                t_end=0.0, bc=BC_PERIODIC, has_b=0, order=2, scheme=SCHEME_SI) -> Params:
+    return Params(g, lam, dx, cfl, mcfl, dt_fixed, t_end, int(bc), int(has_b), int(order),
+                  int(scheme))
 
 
 def gamma() -> float:
@@ -157,8 +163,13 @@ def dt(p: Params, h, q, t=0.0) -> float:
     return lib().or_dt(len(h), C.byref(p), _p(h), _p(q), float(t))
 
 
+def dt_ex(p: Params, h, q, m, t=0.0) -> float:
+    h, q, m = _f(h), _f(q), _f(m)
+    return lib().or_dt_ex(len(h), C.byref(p), _p(h), _p(q), _p(m), float(t))
+
+
 def step(p: Params, b, U, t=0.0):
-    """One IMEX step; returns (rc, Unew, t_new, dt)."""
+    """One step (scheme and order from p); returns (rc, Unew, t_new, dt)."""
     U = [np.array(a, dtype=np.float64, copy=True) for a in U]
     tt = C.c_double(t)
     dtt = C.c_double(0.0)

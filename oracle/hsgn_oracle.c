@@ -30,6 +30,16 @@
  *    face-local lake-at-rest moment so that rest is preserved;
  *  - boundary conditions: periodic, or transmissive (zero-order copy into
  *    two ghost cells, zero implicit force at the boundary face).
+ *
+ * The fully explicit hSGN scheme of Sec. 4.1 (eq. GN_hyp_eq_explicit) with
+ * Heun's method is here too (scheme = 1, flat bottom), with two departures
+ * from the print, both needed for linear stability at rest: the mass flux is
+ * a Rusanov flux like the other three (the print differences q centrally),
+ * and the Rusanov speed is max(|u| + c) over the two face states with the
+ * hSGN celerity c^2 = g h + (lambda/3) (eta/h)^2 (eq. hSGN_c), the
+ * eigenvalues of the system it treats explicitly (the print has |u|).  As
+ * printed, one step at rest grows by a factor 1.011 (lambda = 100) to 1.029
+ * (lambda = 1000) at CFL 0.4; the pressure terms stay central as printed.
  */
 #include "hsgn_oracle.h"
 
@@ -376,6 +386,127 @@ done:
 }
 
 /* ---------------------------------------------------------------------- */
+/* Explicit hSGN space operator (Sec. 4.1, eq. GN_hyp_eq_explicit), flat    */
+/* bottom, U = (h, q, m = h eta, W = h w):                                  */
+/*   L_h = -Dhat_x(q)      (Rusanov; the print has the central D_x(q))      */
+/*   L_q = -Dhat_x(q u) - a^2 D_x(h) - lambda alpha D_x(m)                  */
+/*   L_m = -Dhat_x(m u) + W                                                 */
+/*   L_W = -Dhat_x(W u) - lambda (m / h^2 - 1)                              */
+/* D_x: central difference (mean of the cell fluxes at the faces); Dhat_x:  */
+/* Rusanov flux difference on the unlimited linear reconstruction of U,     */
+/* speed max(|u| + c) over the face states, c^2 = g h + (lambda/3)(m/h^2)^2.*/
+/* a^2 = dp/dh and lambda alpha = dp/d(h eta) of the pressure (eq. hSGN_p): */
+/* a^2 = g h + lambda (eta/h)^2 - (lambda/3) eta/h, alpha = -(2 eta/h - 1)/(3 h). */
+/* ---------------------------------------------------------------------- */
+static int FN(or_ex_rhs)(int n, const or_params* p, const real_t* h, const real_t* q,
+                         const real_t* m, const real_t* W, real_t* Lh, real_t* Lq,
+                         real_t* Lm, real_t* LW) {
+  const double g = p->g, lam = p->lambda, dx = p->dx;
+  const int bc = p->bc;
+  size_t nf = (size_t)n + 1;
+  real_t* Fq = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* Fm = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* FW = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* Fh = (real_t*)malloc(nf * sizeof(real_t)); /* mass flux */
+  int rc = OR_OK;
+  if (!Fq || !Fm || !FW || !Fh) { rc = OR_EINVAL; goto done; }
+  /* face k lies between cells k-1 and k */
+  for (int k = 0; k <= n; ++k) {
+    int a = gidx(k - 2, n, bc), b0 = gidx(k - 1, n, bc), b1 = gidx(k, n, bc), c = gidx(k + 1, n, bc);
+    real_t hL = h[b0] + 0.25 * (h[b1] - h[a]), hR = h[b1] - 0.25 * (h[c] - h[b0]);
+    real_t qL = q[b0] + 0.25 * (q[b1] - q[a]), qR = q[b1] - 0.25 * (q[c] - q[b0]);
+    real_t mL = m[b0] + 0.25 * (m[b1] - m[a]), mR = m[b1] - 0.25 * (m[c] - m[b0]);
+    real_t WL = W[b0] + 0.25 * (W[b1] - W[a]), WR = W[b1] - 0.25 * (W[c] - W[b0]);
+    if (!(RE(hL) > 0.0) || !(RE(hR) > 0.0)) { rc = OR_ENONPHYS; goto done; }
+    real_t uL = qL / hL, uR = qR / hR;
+    real_t eL = mL / (hL * hL), eR = mR / (hR * hR); /* eta/h */
+    real_t cL = RSQRT(g * hL + (lam / 3.0) * eL * eL);
+    real_t cR = RSQRT(g * hR + (lam / 3.0) * eR * eR);
+    real_t sL = RABS(uL) + cL, sR = RABS(uR) + cR;
+    real_t al = RMAX(sL, sR);
+    Fh[k] = 0.5 * (qL + qR - al * (hR - hL));
+    Fq[k] = 0.5 * (qL * uL + qR * uR - al * (qR - qL));
+    Fm[k] = 0.5 * (mL * uL + mR * uR - al * (mR - mL));
+    FW[k] = 0.5 * (WL * uL + WR * uR - al * (WR - WL));
+  }
+  for (int i = 0; i < n; ++i) {
+    int im = gidx(i - 1, n, bc), ip = gidx(i + 1, n, bc);
+    if (!(RE(h[i]) > 0.0)) { rc = OR_ENONPHYS; goto done; }
+    real_t eh = m[i] / (h[i] * h[i]);
+    real_t a2 = g * h[i] + lam * eh * eh - (lam / 3.0) * eh;
+    real_t alpha = -(2.0 * eh - 1.0) / (3.0 * h[i]);
+    real_t dh = (h[ip] - h[im]) / (2.0 * dx);
+    real_t dm = (m[ip] - m[im]) / (2.0 * dx);
+    Lh[i] = -(Fh[i + 1] - Fh[i]) / dx;
+    Lq[i] = -(Fq[i + 1] - Fq[i]) / dx - a2 * dh - lam * alpha * dm;
+    Lm[i] = -(Fm[i + 1] - Fm[i]) / dx + W[i];
+    LW[i] = -(FW[i + 1] - FW[i]) / dx - lam * (eh - 1.0);
+  }
+done:
+  free(Fq); free(Fm); free(FW); free(Fh);
+  return rc;
+}
+
+/* Time step of the explicit scheme (Sec. 5: dt = CFL dx / max mu, with mu =
+ * |u| + c the spectral radius of the hSGN system, eq. CFL_ex), then the
+ * same material cap and t_end clamp as the semi-implicit step. */
+double FN(or_dt_ex)(int n, const or_params* p, const real_t* h, const real_t* q,
+                    const real_t* m, double t) {
+  double dt;
+  if (p->dt_fixed > 0.0) {
+    dt = p->dt_fixed;
+  } else {
+    double smax = 0.0, umax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double hh = RE(h[i]);
+      double u = fabs(RE(q[i]) / hh);
+      double e = RE(m[i]) / (hh * hh);
+      double s = u + sqrt(p->g * hh + (p->lambda / 3.0) * e * e);
+      if (s > smax) smax = s;
+      if (u > umax) umax = u;
+    }
+    dt = p->cfl * p->dx / smax;
+    if (p->mcfl > 0.0 && umax * dt / p->dx > p->mcfl) dt = p->mcfl * p->dx / umax;
+  }
+  if (p->t_end > 0.0) {
+    if (t >= p->t_end) dt = 0.0;
+    else if (t + dt > p->t_end) dt = p->t_end - t;
+  }
+  return dt;
+}
+
+/* One explicit step with Heun's method (second order, Sec. 4.1):
+ * U1 = U^n + dt L(U^n);  U^{n+1} = (U^n + U1 + dt L(U1)) / 2. */
+static int FN(or_ex_step)(int n, const or_params* p, real_t* h, real_t* q, real_t* m,
+                          real_t* W, double dt) {
+  size_t nc = (size_t)n;
+  real_t* buf = (real_t*)malloc(8 * nc * sizeof(real_t));
+  if (!buf) return OR_EINVAL;
+  real_t *Lh = buf, *Lq = buf + nc, *Lm = buf + 2 * nc, *LW = buf + 3 * nc;
+  real_t *h1 = buf + 4 * nc, *q1 = buf + 5 * nc, *m1 = buf + 6 * nc, *W1 = buf + 7 * nc;
+  int rc = FN(or_ex_rhs)(n, p, h, q, m, W, Lh, Lq, Lm, LW);
+  if (rc == OR_OK) {
+    for (size_t i = 0; i < nc; ++i) {
+      h1[i] = h[i] + dt * Lh[i];
+      q1[i] = q[i] + dt * Lq[i];
+      m1[i] = m[i] + dt * Lm[i];
+      W1[i] = W[i] + dt * LW[i];
+    }
+    rc = FN(or_ex_rhs)(n, p, h1, q1, m1, W1, Lh, Lq, Lm, LW);
+  }
+  if (rc == OR_OK) {
+    for (size_t i = 0; i < nc; ++i) {
+      h[i] = 0.5 * (h[i] + (h1[i] + dt * Lh[i]));
+      q[i] = 0.5 * (q[i] + (q1[i] + dt * Lq[i]));
+      m[i] = 0.5 * (m[i] + (m1[i] + dt * Lm[i]));
+      W[i] = 0.5 * (W[i] + (W1[i] + dt * LW[i]));
+    }
+  }
+  free(buf);
+  return rc;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Time step (Sec. 5: dt = CFL dx / max speed, then the material CFL cap).  */
 /* The speed is |u| + sqrt(g h): the lambda-independent rule of the remark  */
 /* after the coercivity proposition (Sec. 3.1).                             */
@@ -407,6 +538,15 @@ double FN(or_dt)(int n, const or_params* p, const real_t* h, const real_t* q, do
 /* ---------------------------------------------------------------------- */
 int FN(or_step)(int n, const or_params* p, const real_t* b,
             real_t* h, real_t* q, real_t* m, real_t* W, double* t, double* dt_out) {
+  if (p->scheme == 1) {
+    if (p->has_b) return OR_EINVAL; /* the explicit scheme is for a flat bottom */
+    double dte = FN(or_dt_ex)(n, p, h, q, m, *t);
+    if (dt_out) *dt_out = dte;
+    if (!(dte > 0.0)) return OR_OK;
+    int rce = FN(or_ex_step)(n, p, h, q, m, W, dte);
+    *t += dte;
+    return rce;
+  }
   double dt = FN(or_dt)(n, p, h, q, *t);
   if (dt_out) *dt_out = dt;
   if (!(dt > 0.0)) return OR_OK; /* frozen instance */

@@ -30,6 +30,8 @@ typedef struct {
   int has_b;       /* 1: bed b is used; 0: flat bottom (b ignored) */
   int order;       /* 1: first-order scheme (one stage, tau = dt, no
                       reconstruction); otherwise the two-stage IMEX step */
+  int scheme;      /* 0: semi-implicit (above); 1: fully explicit hSGN with
+                      Heun's method (flat bottom; cfl applies to |u| + c) */
 } or_params;
 
 /* Optional per-stage intermediates (any pointer may be NULL). Cell arrays
@@ -61,8 +63,14 @@ int or_stage(int n, const or_params* p, double tau, const double* b,
 /* Time step from the state (CFL, material-CFL cap, t_end clamp). */
 double or_dt(int n, const or_params* p, const double* h, const double* q, double t);
 
-/* One full two-stage IMEX step, in place.  *t advances by the step used;
- * *dt_out (may be NULL) receives it.  A zero step leaves the state frozen. */
+/* Time step of the explicit scheme: CFL on |u| + c, c^2 = g h + (lambda/3)(m/h^2)^2. */
+double or_dt_ex(int n, const or_params* p, const double* h, const double* q, const double* m,
+                double t);
+
+/* One full step, in place: the two-stage IMEX step, the first-order
+ * semi-implicit step (order 1), or the explicit Heun step (scheme 1).
+ * *t advances by the step used; *dt_out (may be NULL) receives it.  A zero
+ * step leaves the state frozen. */
 int or_step(int n, const or_params* p, const double* b,
             double* h, double* q, double* m, double* W, double* t, double* dt_out);
 

@@ -507,3 +507,143 @@ def test_first_order_step_is_one_full_stage():
     p2 = O.make_params(**prm)
     rc, Uf = O.stage(p2, dt, b, U, U)
     assert max(np.max(np.abs(a - c)) for a, c in zip(Uf, Us)) > 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Fully explicit hSGN scheme with Heun's method (Sec. 4.1, scheme 1, flat
+# bottom; Rusanov fluxes with speed |u| + c on all four fields).
+# ---------------------------------------------------------------------------
+EX = O.SCHEME_EXPLICIT
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_explicit_lake_at_rest(bc):
+    n = 64
+    h = np.full(n, 0.7)
+    U = (h, np.zeros(n), h * h, np.zeros(n))
+    for lam in (100.0, 1e4):
+        p = O.make_params(lam=lam, dx=0.05, cfl=0.4, bc=bc, scheme=EX)
+        rc, Un, t = O.run(p, None, U, 0.0, 200)
+        assert rc == 0 and t > 0
+        for a, b in zip(U, Un):
+            assert np.array_equal(a, b)
+
+
+def test_explicit_heun_on_uniform_state():
+    """A uniform state has no spatial terms: h' = 0, q' = 0, m' = W,
+    W' = -lambda (m / h^2 - 1).  One Heun step of this affine system is its
+    second-order Taylor polynomial y + dt f + dt^2/2 A f (A = df/dy)."""
+    n, h0, q0, m0, W0, lam, dt = 16, 0.8, 0.3, 0.7, 0.2, 500.0, 1e-3
+    U = tuple(np.full(n, v) for v in (h0, q0, m0, W0))
+    p = O.make_params(lam=lam, dx=0.1, bc=0, dt_fixed=dt, scheme=EX)
+    rc, Un, t, dt_used = O.step(p, None, U)
+    assert rc == 0 and dt_used == dt
+    fm, fW = W0, -lam * (m0 / h0 ** 2 - 1.0)
+    Afm, AfW = fW, -lam / h0 ** 2 * fm
+    m2 = m0 + dt * fm + 0.5 * dt * dt * Afm
+    W2 = W0 + dt * fW + 0.5 * dt * dt * AfW
+    assert np.all(Un[0] == h0) and np.all(Un[1] == q0)
+    assert np.max(np.abs(Un[2] - m2)) < 1e-15 and np.max(np.abs(Un[3] - W2)) < 1e-13
+
+
+def test_explicit_dt_rule():
+    """dt = CFL dx / max(|u| + c), c^2 = g h + (lambda/3)(eta/h)^2 (Sec. 5,
+    eq. CFL_ex), clamped to t_end."""
+    h = np.array([1.0, 0.5, 2.0])
+    q = np.array([0.2, -0.4, 0.1])
+    m = np.array([1.1, 0.2, 4.4])
+    lam, g, dx, cfl = 300.0, 9.81, 0.1, 0.4
+    p = O.make_params(lam=lam, dx=dx, cfl=cfl, scheme=EX)
+    mu = max(abs(q[i] / h[i]) + math.sqrt(g * h[i] + lam / 3 * (m[i] / h[i] ** 2) ** 2) for i in range(3))
+    assert abs(O.dt_ex(p, h, q, m) - cfl * dx / mu) < 1e-17
+    p2 = O.make_params(lam=lam, dx=dx, cfl=cfl, t_end=0.01, scheme=EX)
+    assert O.dt_ex(p2, h, q, m, t=0.0095) == pytest.approx(0.0005, abs=1e-15)
+
+
+def test_explicit_conserves_mass_and_is_mirror_symmetric():
+    (h, q, m, W), _ = rand_state(128, 21, amp=0.1)
+    p = O.make_params(lam=300.0, dx=0.05, cfl=0.4, bc=0, scheme=EX)
+    rc, Un, t = O.run(p, None, (h, q, m, W), 0.0, 50)
+    assert rc == 0
+    assert abs(Un[0].sum() - h.sum()) / h.sum() < 1e-14
+    # x -> -x: h, m, W even, q odd; cell i <-> cell n - 1 - i
+    rcm, Um, tm = O.run(p, None, (h[::-1].copy(), -q[::-1].copy(), m[::-1].copy(), W[::-1].copy()),
+                        0.0, 50)
+    assert rcm == 0 and tm == t
+    for a, b, s in zip(Un, Um, (1, -1, 1, 1)):
+        assert np.max(np.abs(a - s * b[::-1])) < 1e-12 * max(1.0, np.max(np.abs(a)))
+
+
+def test_explicit_rest_state_is_linearly_stable():
+    """Spectral radius of one step's Jacobian at rest (central differences of
+    the oracle): at most 1 to the accuracy of the differences, for CFL 0.4."""
+    N = 32
+    h = np.ones(N)
+    z = np.zeros(N)
+    for lam in (100.0, 1000.0):
+        p = O.make_params(lam=lam, dx=0.04, cfl=0.4, bc=0, scheme=EX)
+        eps = 1e-6
+        J = np.zeros((4 * N, 4 * N))
+        for k in range(4 * N):
+            Up = [h.copy(), z.copy(), h * h, z.copy()]
+            Um = [h.copy(), z.copy(), h * h, z.copy()]
+            Up[k // N][k % N] += eps
+            Um[k // N][k % N] -= eps
+            J[:, k] = (np.concatenate(O.step(p, None, Up)[1]) - np.concatenate(O.step(p, None, Um)[1])) / (2 * eps)
+        rho = np.max(np.abs(np.linalg.eigvals(J)))
+        assert rho < 1 + 1e-7, (lam, rho)
+
+
+def test_explicit_converges_to_the_semi_implicit_solution():
+    """Both schemes discretise the same hSGN system to second order, so their
+    difference at a fixed time falls like dx^2 (solitary wave, lambda = 100)."""
+    diffs = []
+    for N in (200, 400, 800):
+        wl = WL.solitary(N=N, L=100.0, h0=1.0, a=0.2, lam=100.0, t_end=1.0)
+        n, prm, b, U = wl.instance(0)
+        rce, Ue, te = O.run(O.make_params(**{**prm, "cfl": 0.4}, scheme=EX), None, U, 0.0, 100000)
+        rcs, Us, ts = O.run(O.make_params(**prm), None, U, 0.0, 100000)
+        assert rce == 0 and rcs == 0 and te == 1.0 and ts == 1.0
+        diffs.append(np.sum(np.abs(Ue[0] - Us[0])) * prm["dx"])
+    r1, r2 = math.log2(diffs[0] / diffs[1]), math.log2(diffs[1] / diffs[2])
+    assert 1.8 < r1 < 2.4 and 1.8 < r2 < 2.4, diffs
+
+
+def test_explicit_linear_dispersion_relation():
+    """A small sinusoid propagates with the hSGN linear phase speed; the phase
+    error after one period falls at second order and its extrapolation is far
+    below the gap to the SGN relation (as for the semi-implicit scheme)."""
+    h0, lam, Lw, g = 1.0, 100.0, 10.0, 9.81
+    k = 2 * math.pi / Lw
+    w = _omega(k, h0, lam)
+    eps = 1e-6
+    A = (lam / h0) / (lam / h0 ** 2 - w * w)
+    Tp = 2 * math.pi / w
+    phase_err = []
+    for N in (32, 64, 128):
+        dx = Lw / N
+        x = (np.arange(N) + 0.5) * dx
+        th = k * x
+        hp = eps * np.cos(th)
+        U = (h0 + hp, (w / k) * hp, h0 ** 2 + h0 * hp + A * hp, w * A * eps * np.sin(th))
+        nsteps = 8 * N
+        p = O.make_params(lam=lam, dx=dx, bc=0, dt_fixed=Tp / nsteps, scheme=EX)
+        rc, Un, t = O.run(p, None, U, 0.0, nsteps)
+        assert rc == 0
+        d = Un[0] - h0
+        phase_err.append(math.atan2((d * np.sin(th)).sum(), (d * np.cos(th)).sum()))
+    r1 = abs(phase_err[0] / phase_err[1])
+    r2 = abs(phase_err[1] / phase_err[2])
+    assert r1 > 3.5 and r2 > 3.5, phase_err
+    wsgn = math.sqrt(g * h0 * k * k / (1 + k * k * h0 * h0 / 3))
+    gap = abs(w - wsgn) / w * 2 * math.pi
+    ext = (4 * phase_err[2] - phase_err[1]) / 3
+    assert abs(ext) < 0.01 * gap, (ext, gap)
+
+
+def test_explicit_rejects_a_bed():
+    n = 16
+    h = np.full(n, 0.5)
+    p = O.make_params(lam=100.0, dx=0.1, has_b=1, scheme=EX)
+    rc, _, _, _ = O.step(p, np.zeros(n), (h, np.zeros(n), h * h, np.zeros(n)))
+    assert rc == O.EINVAL
