@@ -20,6 +20,13 @@
  * reconstruction (first order in time and space).
  * The time step is CFL dx / max(|u| + sqrt(g h)), capped by the material
  * CFL max|u| dt/dx <= mcfl (Sec. 3.3 eq. MCFL and Sec. 5).
+ * With scheme = HSGN_SCHEME_EXPLICIT a step is instead the fully explicit
+ * hSGN scheme of Sec. 4.1 (eq. GN_hyp_eq_explicit) with Heun's method,
+ *   U1 = U^n + dt L(U^n),  U^{n+1} = (U^n + U1 + dt L(U1)) / 2,
+ * L = Rusanov fluxes (speed max(|u| + c) over the face states) on the same
+ * reconstruction for h, q u, m u, W u; central differences for the pressure
+ * terms a^2 h_x + lambda alpha (h eta)_x; sources h w and
+ * -lambda (eta/h - 1).  Its dt is CFL dx / max(|u| + c) (eq. CFL_ex).
  *
  * State per cell (all FP64, structure of arrays): h (depth), q = h u,
  * m = h eta, W = h w.  Independent instances ("batch") are concatenated:
@@ -77,7 +84,17 @@ typedef struct {
                             first-order scheme of Sec. 4.2 as printed: one
                             stage with tau = dt and no reconstruction (face
                             values = cell values).  Same for every instance. */
+  int32_t scheme;        /* HSGN_SCHEME_SEMI_IMPLICIT (0): the steps above;
+                            HSGN_SCHEME_EXPLICIT (1): the fully explicit
+                            hSGN scheme of Sec. 4.1 with Heun's method, flat
+                            bottom only (has_bathymetry = 0), order 0 or 2;
+                            cfl then applies to |u| + c with the hSGN
+                            celerity c^2 = g h + (lambda/3)(eta/h)^2
+                            (eq. hSGN_c).  Same for every instance.        */
 } hsgn_params;
+
+#define HSGN_SCHEME_SEMI_IMPLICIT 0
+#define HSGN_SCHEME_EXPLICIT 1
 
 typedef struct hsgn_ctx hsgn_ctx;
 
@@ -143,7 +160,8 @@ int hsgn_set_solver(hsgn_ctx* ctx, int32_t mode);
  * as it was.  h_ms (host, 3 doubles or NULL): milliseconds per step of each
  * mode, indexed by the mode's value; h_mode (host or NULL): the mode kept.
  * The modes agree with each other to rounding.  Allocates a copy of the
- * state for its duration; synchronises the stream. */
+ * state for its duration; synchronises the stream.  The explicit scheme has
+ * no solver: HSGN_EINVAL. */
 int hsgn_autotune(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_mode);
 
 /* Plan of the loaded state (host arrays, any may be NULL): h_mode[j] = 0
@@ -162,7 +180,9 @@ int hsgn_plan_info(hsgn_ctx* ctx, int32_t* h_mode, int32_t* h_halo, int32_t* h_c
 #define HSGN_K_STAGE2 6
 #define HSGN_K_WIN1 7         /* stage 1, windowed single pass               */
 #define HSGN_K_WIN2 8         /* stage 2, windowed single pass               */
-#define HSGN_NKERNEL 9
+#define HSGN_K_EX1 9          /* explicit scheme, first Heun stage           */
+#define HSGN_K_EX2 10         /* explicit scheme, second Heun stage          */
+#define HSGN_NKERNEL 11
 
 /* Measurement variant of hsgn_step: the same launches, each bracketed by HIP
  * events on the library's stream; synchronises at the end.  h_ms[k]
@@ -186,8 +206,8 @@ int hsgn_step_timed(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_coun
  *  d_loss: device [n_inst]; d_grad_zeta0, d_grad_b: device, offsets[n_inst]
  *    doubles or NULL; when both are NULL only the loss is computed (no
  *    reverse sweep, no adjoint workspace).
- * Only for the two-stage step (order 2).  Every instance must use a fixed
- * step (dt_fixed > 0, t_end <= 0), so that
+ * Only for the two-stage semi-implicit step (order 2, scheme 0).  Every
+ * instance must use a fixed step (dt_fixed > 0, t_end <= 0), so that
  * the step map is differentiable, and every gauge cell must lie in its
  * instance (else HSGN_EINVAL).  Forward steps use the solver plan made from
  * the initial state (the status flags are cleared first, as by

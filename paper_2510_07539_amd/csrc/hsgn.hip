@@ -25,6 +25,7 @@
 #include "hsgn_kernels.hpp"
 #include "hsgn_window.hpp"
 #include "hsgn_adjoint.hpp"
+#include "hsgn_explicit.hpp"
 
 namespace {
 
@@ -77,6 +78,9 @@ struct hsgn_ctx {
   double* const* io_out = nullptr;
   bool io_stage1_only = false;  // the step stops after stage 1 (U^(1) only)
   int order = 2;                // 2: two-stage IMEX step; 1: one first-order stage
+  int scheme = HSGN_SCHEME_SEMI_IMPLICIT;  // or the explicit Heun step
+  TileDesc* d_xtiles = nullptr;  // tiles of the explicit kernel (kExTile cells)
+  int nxtiles = 0;
   double* d_dt = nullptr;
   double* d_t = nullptr;
   unsigned long long* d_smax = nullptr;
@@ -156,7 +160,8 @@ void free_all(hsgn_ctx* c) {
   void* ptrs[] = {c->d_inst, c->d_tiles_all, c->d_tiles_multi, c->d_multi, c->d_b,
                   c->d_dt, c->d_t, c->d_smax, c->d_umax, c->d_status, c->d_rlo, c->d_rdi,
                   c->d_rup, c->d_rrhs, c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw,
-                  c->d_ex_tiles, c->d_ex_tiles_multi, c->d_ex_multi, c->d_win, c->d_hmax};
+                  c->d_ex_tiles, c->d_ex_tiles_multi, c->d_ex_multi, c->d_win, c->d_hmax,
+                  c->d_xtiles};
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (int i = 0; i < 3; ++i)
@@ -259,6 +264,39 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
   hipLaunchKernelGGL(hsgn::k_dt, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_inst, c->d_dt,
                      c->d_t, c->d_smax, c->d_umax, c->d_status);
   mark(HSGN_K_DT, false);
+  if (c->scheme == HSGN_SCHEME_EXPLICIT) {
+    // Heun: U1 = U^n + dt L(U^n), U^{n+1} = (U^n + U1 + dt L(U1)) / 2
+    double* const* un = c->buf[c->cur];
+    double* const* u1 = c->buf[c->s1];
+    double* const* out = c->buf[c->nxt];
+    hsgn::ExArgs x;
+    std::memset(&x, 0, sizeof x);
+    x.un_h = un[0]; x.un_q = un[1]; x.un_m = un[2]; x.un_W = un[3];
+    x.inst = c->d_inst;
+    x.tiles = c->d_xtiles;
+    x.dt = c->d_dt;
+    x.smax = c->d_smax;
+    x.umax = c->d_umax;
+    x.status = c->d_status;
+    x.in_h = un[0]; x.in_q = un[1]; x.in_m = un[2]; x.in_W = un[3];
+    x.o_h = u1[0]; x.o_q = u1[1]; x.o_m = u1[2]; x.o_W = u1[3];
+    mark(HSGN_K_EX1, true);
+    hipLaunchKernelGGL((hsgn::k_ex<hsgn::kExNT, hsgn::kExK, 1>), dim3(c->nxtiles),
+                       dim3(hsgn::kExNT), 0, c->stream, x);
+    mark(HSGN_K_EX1, false);
+    x.in_h = u1[0]; x.in_q = u1[1]; x.in_m = u1[2]; x.in_W = u1[3];
+    x.o_h = out[0]; x.o_q = out[1]; x.o_m = out[2]; x.o_W = out[3];
+    mark(HSGN_K_EX2, true);
+    hipLaunchKernelGGL((hsgn::k_ex<hsgn::kExNT, hsgn::kExK, 2>), dim3(c->nxtiles),
+                       dim3(hsgn::kExNT), 0, c->stream, x);
+    mark(HSGN_K_EX2, false);
+    HIPCHK(c, hipGetLastError());
+    if (!marks_ok) return fail(c, HSGN_EHIP, "hsgn_step_timed: timing events failed");
+    const int old = c->cur;
+    c->cur = c->nxt;
+    c->nxt = old;
+    return HSGN_OK;
+  }
   const int last_stage = (c->io_stage1_only || c->order == 1) ? 1 : 2;
   for (int stage = 1; stage <= last_stage; ++stage) {
     StageArgs a = stage_args(c, stage);
@@ -477,7 +515,7 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   c->user_stream = (hipStream_t)hip_stream;
   if (offsets[0] != 0) rc = fail(c, HSGN_EINVAL, "offsets[0] must be 0");
   std::vector<InstDesc> inst(n_inst);
-  std::vector<TileDesc> tall, tmulti;
+  std::vector<TileDesc> tall, tmulti, xt;
   std::vector<int32_t> multi;
   int64_t red = 0;
   for (int j = 0; j < n_inst && rc == HSGN_OK; ++j) {
@@ -503,6 +541,18 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
       break;
     }
     c->order = ord;
+    if ((p.scheme != HSGN_SCHEME_SEMI_IMPLICIT && p.scheme != HSGN_SCHEME_EXPLICIT) ||
+        (j > 0 && p.scheme != c->scheme)) {
+      rc = fail(c, HSGN_EINVAL, "instance %d: scheme must be 0 or 1 and the same for every "
+                "instance", j);
+      break;
+    }
+    c->scheme = p.scheme;
+    if (p.scheme == HSGN_SCHEME_EXPLICIT && (p.has_bathymetry || ord != 2)) {
+      rc = fail(c, HSGN_EINVAL, "instance %d: the explicit scheme needs a flat bottom and "
+                "order 0 or 2", j);
+      break;
+    }
     InstDesc& d = inst[j];
     std::memset(&d, 0, sizeof d);
     d.off = offsets[j];
@@ -527,6 +577,17 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
     if (nt > 1) {
       multi.push_back(j);
       red += 2 * nt;
+    }
+    if (p.scheme == HSGN_SCHEME_EXPLICIT) {  // tiles of the explicit kernel
+      const int nx = (int)((n + hsgn::kExTile - 1) / hsgn::kExTile);
+      for (int k = 0; k < nx; ++k) {
+        TileDesc t;
+        t.inst = j;
+        t.tidx = k;
+        t.start = (int32_t)((n * k) / nx);
+        t.len = (int32_t)((n * (k + 1)) / nx) - t.start;
+        xt.push_back(t);
+      }
     }
     c->ncell += n;
   }
@@ -557,6 +618,8 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_inst, inst.size());
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_tiles_all, tall.size());
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_tiles_multi, tmulti.size());
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_xtiles, xt.size());
+  c->nxtiles = (int)xt.size();
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_multi, multi.size());
   for (int i = 0; i < 3 && rc == HSGN_OK; ++i)
     for (int f = 0; f < 4 && rc == HSGN_OK; ++f) rc = dmalloc(c, &c->buf[i][f], nc);
@@ -581,6 +644,7 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   if (rc == HSGN_OK) rc = up(c->d_inst, inst.data(), inst.size() * sizeof(InstDesc));
   if (rc == HSGN_OK) rc = up(c->d_tiles_all, tall.data(), tall.size() * sizeof(TileDesc));
   if (rc == HSGN_OK) rc = up(c->d_tiles_multi, tmulti.data(), tmulti.size() * sizeof(TileDesc));
+  if (rc == HSGN_OK) rc = up(c->d_xtiles, xt.data(), xt.size() * sizeof(TileDesc));
   if (rc == HSGN_OK) rc = up(c->d_multi, multi.data(), multi.size() * sizeof(int32_t));
   if (rc == HSGN_OK && c->any_b) {
     hipError_t e = hipMemcpyAsync(c->d_b, d_b, nc * sizeof(double), hipMemcpyDeviceToDevice,
@@ -639,8 +703,13 @@ static int reset_and_plan(hsgn_ctx* c) {
                      0ull);
   hipLaunchKernelGGL(hsgn::k_fill_u64, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_hmax,
                      0ull);
-  hipLaunchKernelGGL(hsgn::k_speed<256>, dim3(c->ntiles_all), dim3(256), 0, c->stream, c->d_inst,
-                     c->d_tiles_all, U[0], U[1], c->d_smax, c->d_umax, c->d_hmax);
+  if (c->scheme == HSGN_SCHEME_EXPLICIT)
+    hipLaunchKernelGGL(hsgn::k_speed_ex<256>, dim3(c->ntiles_all), dim3(256), 0, c->stream,
+                       c->d_inst, c->d_tiles_all, U[0], U[1], U[2], c->d_smax, c->d_umax,
+                       c->d_hmax);
+  else
+    hipLaunchKernelGGL(hsgn::k_speed<256>, dim3(c->ntiles_all), dim3(256), 0, c->stream,
+                       c->d_inst, c->d_tiles_all, U[0], U[1], c->d_smax, c->d_umax, c->d_hmax);
   HIPCHK(c, hipGetLastError());
   // plan the solve from this state's speed bound and depth maximum
   std::vector<unsigned long long> sm(c->n_inst), hm(c->n_inst);
@@ -813,6 +882,8 @@ int hsgn_step_timed(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_count)
 int hsgn_autotune(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_mode) {
   if (!c) return HSGN_EINVAL;
   if (nsteps < 1) return fail(c, HSGN_EINVAL, "hsgn_autotune: nsteps < 1");
+  if (c->scheme == HSGN_SCHEME_EXPLICIT)
+    return fail(c, HSGN_EINVAL, "hsgn_autotune: the explicit scheme has no solver to tune");
   int rc = enter(c);
   if (rc) return rc;
   const size_t nc = (size_t)c->ncell, ni = (size_t)c->n_inst;
@@ -1065,8 +1136,9 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   if (!c) return HSGN_EINVAL;
   if (nsteps < 1 || K < 1 || ng < 1 || !d_gauge || !d_target || !d_zeta0 || !d_loss)
     return fail(c, HSGN_EINVAL, "hsgn_adjoint: bad arguments");
-  if (c->order != 2)
-    return fail(c, HSGN_EINVAL, "hsgn_adjoint: the adjoint is of the two-stage IMEX step");
+  if (c->order != 2 || c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
+    return fail(c, HSGN_EINVAL, "hsgn_adjoint: the adjoint is of the two-stage semi-implicit "
+                "step (order 2, scheme 0)");
   for (int j = 0; j < c->n_inst; ++j) {
     if (!(c->params[j].dt_fixed > 0) || c->params[j].t_end > 0)
       return fail(c, HSGN_EINVAL,

@@ -1,0 +1,221 @@
+// hsgn_explicit.hpp -- the fully explicit hSGN step with Heun's method
+// (Sec. 4.1, eq. GN_hyp_eq_explicit), flat bottom, for the cost comparison
+// the paper makes against the semi-implicit step.
+//
+// Space operator L(U), U = (h, q, m = h eta, W = h w):
+//   L_h = -Dhat_x(q)
+//   L_q = -Dhat_x(q u) - a^2 D_x(h) - lambda alpha D_x(m)
+//   L_m = -Dhat_x(m u) + W
+//   L_W = -Dhat_x(W u) - lambda (m / h^2 - 1)
+// Dhat_x: Rusanov flux difference on the unlimited linear reconstruction,
+// speed max(|u| + c) over the two face states with the hSGN celerity
+// c^2 = g h + (lambda/3) (m/h^2)^2 (eq. hSGN_c); D_x: central difference;
+// a^2 = g h + lambda (eta/h)^2 - (lambda/3) eta/h and
+// alpha = -(2 eta/h - 1) / (3 h) are the pressure derivatives (eq. hSGN_p).
+// The mass flux is a Rusanov flux and the speed includes c: with the
+// printed central mass flux and speed |u| one step at rest grows.
+// Heun: U1 = U^n + dt L(U^n);  U^{n+1} = (U^n + U1 + dt L(U1)) / 2.
+//
+// One workgroup owns a tile of NT * KX cells of one instance.  The four
+// fields of the stage operand are staged through LDS with coalesced loads
+// (tile plus two ghost cells per side: periodic wrap or zero-order copy);
+// each thread computes its KX cells from the KX + 1 faces around them.
+#pragma once
+
+#include "hsgn_kernels.hpp"
+
+namespace hsgn {
+
+constexpr int kExNT = 256;               // threads per tile
+constexpr int kExK = 4;                  // cells per thread
+constexpr int kExTile = kExNT * kExK;    // cells per tile
+
+struct ExArgs {
+  const double* __restrict__ un_h;  // U^n
+  const double* __restrict__ un_q;
+  const double* __restrict__ un_m;
+  const double* __restrict__ un_W;
+  const double* __restrict__ in_h;  // operand of L (stage 1: U^n, stage 2: U1)
+  const double* __restrict__ in_q;
+  const double* __restrict__ in_m;
+  const double* __restrict__ in_W;
+  double* __restrict__ o_h;         // stage output
+  double* __restrict__ o_q;
+  double* __restrict__ o_m;
+  double* __restrict__ o_W;
+  const InstDesc* __restrict__ inst;
+  const TileDesc* __restrict__ tiles;
+  const double* __restrict__ dt;
+  unsigned long long* __restrict__ smax;  // stage 2: speed bound of the new state
+  unsigned long long* __restrict__ umax;
+  int32_t* __restrict__ status;
+};
+
+// Staged index i of a thread's window: one pad double after every four, so
+// that threads reading KX + 4 consecutive values (stride KX) spread over
+// the banks.
+__device__ __forceinline__ int xpad(int i) { return i + (i >> 2); }
+
+template <int NT, int KX, int STAGE>
+__global__ __launch_bounds__(NT) void k_ex(ExArgs A) {
+  constexpr int TL = NT * KX;          // tile cells
+  constexpr int SL = TL + 4;           // staged cells (two ghosts per side)
+  constexpr int SP = SL + (SL >> 2) + 1;
+  __shared__ double X[4][SP];
+  const TileDesc td = A.tiles[blockIdx.x];
+  const InstDesc I = A.inst[td.inst];
+  const double dt = A.dt[td.inst];
+  const int t = threadIdx.x;
+  const int n = I.n, bc = I.bc;
+  const int64_t base = I.off;
+  const double* in[4] = {A.in_h, A.in_q, A.in_m, A.in_W};
+  const double* un[4] = {A.un_h, A.un_q, A.un_m, A.un_W};
+  double* out[4] = {A.o_h, A.o_q, A.o_m, A.o_W};
+  const int p0 = t * KX;  // first tile cell of this thread
+  const int own = td.len - p0 < KX ? (td.len - p0 > 0 ? td.len - p0 : 0) : KX;
+
+  if (!(dt > 0.0)) {  // frozen instance: the state stays
+    for (int i = t; i < td.len; i += NT) {
+      const int64_t gi = base + td.start + i;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) out[f][gi] = un[f][gi];
+    }
+    return;
+  }
+  // ---- staging: staged index i <-> instance cell start - 2 + i
+  const int SLn = td.len + 4;
+#pragma unroll
+  for (int r = 0; r < (SL + NT - 1) / NT; ++r) {
+    const int i = t + r * NT;
+    if (i < SLn) {
+      int c = td.start - 2 + i;
+      if (bc == 0) c = c < 0 ? c + n : (c >= n ? c - n : c);
+      else c = c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
+#pragma unroll
+      for (int f = 0; f < 4; ++f) X[f][xpad(i)] = in[f][base + c];
+    }
+  }
+  __syncthreads();
+
+  const double g = I.g, lam = I.lam, idx = 1.0 / I.dx, i2dx = 0.5 / I.dx;
+  // window of this thread: v[f][k] = staged p0 + k (cells p0 - 2 .. p0 + KX + 1)
+  // (threads past the tile's end keep zeros and only join the reductions)
+  double v[4][KX + 4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+#pragma unroll
+    for (int k = 0; k < KX + 4; ++k) v[f][k] = own > 0 ? X[f][xpad(p0 + k)] : 0.0;
+  // Rusanov fluxes at faces e = 0..KX: face e lies between cells p0 + e - 1
+  // and p0 + e; its stencil is v[.][e .. e + 3]
+  double Fh[KX + 1], Fq[KX + 1], Fm[KX + 1], FW[KX + 1];
+  bool bad = false;
+#pragma unroll
+  for (int e = 0; e <= KX; ++e) {
+    double L[4], R[4];
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      L[f] = v[f][e + 1] + 0.25 * (v[f][e + 2] - v[f][e]);
+      R[f] = v[f][e + 2] - 0.25 * (v[f][e + 3] - v[f][e + 1]);
+    }
+    // faces beyond a short tile's last cell read stale staging: no flag
+    if (own > 0 && e <= own) bad |= !(L[0] > 0.0) || !(R[0] > 0.0);
+    const double iL = 1.0 / L[0], iR = 1.0 / R[0];
+    const double uL = L[1] * iL, uR = R[1] * iR;
+    const double eL = L[2] * iL * iL, eR = R[2] * iR * iR;
+    const double sL = fabs(uL) + sqrt(g * L[0] + (lam / 3.0) * eL * eL);
+    const double sR = fabs(uR) + sqrt(g * R[0] + (lam / 3.0) * eR * eR);
+    const double al = fmax(sL, sR);
+    Fh[e] = 0.5 * (L[1] + R[1] - al * (R[0] - L[0]));
+    Fq[e] = 0.5 * (L[1] * uL + R[1] * uR - al * (R[1] - L[1]));
+    Fm[e] = 0.5 * (L[2] * uL + R[2] * uR - al * (R[2] - L[2]));
+    FW[e] = 0.5 * (L[3] * uL + R[3] * uR - al * (R[3] - L[3]));
+  }
+  double smx = 0.0, umx = 0.0;
+#pragma unroll
+  for (int j = 0; j < KX; ++j) {
+    if (j < own) {
+      const int k = j + 2;  // window index of cell p0 + j
+      const double h = v[0][k], m = v[2][k], W = v[3][k];
+      bad |= !(h > 0.0);
+      const double ih = 1.0 / h;
+      const double eh = m * ih * ih;
+      const double a2 = g * h + lam * eh * eh - (lam / 3.0) * eh;
+      const double alpha = -(2.0 * eh - 1.0) * ih * (1.0 / 3.0);
+      const double dh = (v[0][k + 1] - v[0][k - 1]) * i2dx;
+      const double dm = (v[2][k + 1] - v[2][k - 1]) * i2dx;
+      double Lv[4];
+      Lv[0] = -(Fh[j + 1] - Fh[j]) * idx;
+      Lv[1] = -(Fq[j + 1] - Fq[j]) * idx - a2 * dh - lam * alpha * dm;
+      Lv[2] = -(Fm[j + 1] - Fm[j]) * idx + W;
+      Lv[3] = -(FW[j + 1] - FW[j]) * idx - lam * (eh - 1.0);
+      const int64_t gi = base + td.start + p0 + j;
+      double o[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const double u1 = v[f][k] + dt * Lv[f];
+        o[f] = STAGE == 1 ? u1 : 0.5 * (un[f][gi] + u1);
+        bad |= !isfinite(o[f]);
+        out[f][gi] = o[f];
+      }
+      if (STAGE == 2) {
+        const double hn = o[0];
+        const double ihn = 1.0 / hn;
+        const double un_ = fabs(o[1] * ihn);
+        const double en = o[2] * ihn * ihn;
+        bad |= !(hn > 0.0);
+        smx = fmax(smx, un_ + sqrt(g * hn + (lam / 3.0) * en * en));
+        umx = fmax(umx, un_);
+      }
+    }
+  }
+  if (STAGE == 2) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      smx = fmax(smx, __shfl_xor(smx, off));
+      umx = fmax(umx, __shfl_xor(umx, off));
+    }
+    if ((t & 63) == 0 && smx > 0.0) {
+      atomicMax(&A.smax[td.inst], (unsigned long long)__double_as_longlong(smx));
+      atomicMax(&A.umax[td.inst], (unsigned long long)__double_as_longlong(umx));
+    }
+  }
+  if (bad) atomicOr(&A.status[td.inst], kFlagNonPhys);
+}
+
+// Speed bound |u| + c of a given state (first step after a state is loaded).
+template <int NT>
+__global__ __launch_bounds__(NT) void k_speed_ex(const InstDesc* __restrict__ inst,
+                                                 const TileDesc* __restrict__ tiles,
+                                                 const double* __restrict__ h,
+                                                 const double* __restrict__ q,
+                                                 const double* __restrict__ m,
+                                                 unsigned long long* __restrict__ smax,
+                                                 unsigned long long* __restrict__ umax,
+                                                 unsigned long long* __restrict__ hmax) {
+  const TileDesc td = tiles[blockIdx.x];
+  const InstDesc I = inst[td.inst];
+  double s = 0.0, u = 0.0, hx = 0.0;
+  for (int i = threadIdx.x; i < td.len; i += NT) {
+    const int64_t gi = I.off + td.start + i;
+    const double hh = h[gi];
+    const double ih = 1.0 / hh;
+    const double uu = fabs(q[gi] * ih);
+    const double e = m[gi] * ih * ih;
+    s = fmax(s, uu + sqrt(I.g * hh + (I.lam / 3.0) * e * e));
+    u = fmax(u, uu);
+    hx = fmax(hx, hh);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s = fmax(s, __shfl_xor(s, off));
+    u = fmax(u, __shfl_xor(u, off));
+    hx = fmax(hx, __shfl_xor(hx, off));
+  }
+  if ((threadIdx.x & 63) == 0 && s > 0.0) {
+    atomicMax(&smax[td.inst], (unsigned long long)__double_as_longlong(s));
+    atomicMax(&umax[td.inst], (unsigned long long)__double_as_longlong(u));
+    atomicMax(&hmax[td.inst], (unsigned long long)__double_as_longlong(hx));
+  }
+}
+
+}  // namespace hsgn

@@ -17,16 +17,19 @@ LIB_PATH = os.path.join(HERE, "libhsgn.so")
 
 HSGN_OK, HSGN_EINVAL, HSGN_EHIP, HSGN_ENONPHYS, HSGN_ENONCOERCIVE, HSGN_ENOMEM = 0, -1, -2, -3, -4, -5
 FLAG_NONPHYS, FLAG_NONCOERCIVE = 1, 2
-KERNEL_KINDS = ("dt", "reduce1", "rsolve1", "stage1", "reduce2", "rsolve2", "stage2", "win1", "win2")
+KERNEL_KINDS = ("dt", "reduce1", "rsolve1", "stage1", "reduce2", "rsolve2", "stage2", "win1", "win2",
+                "ex1", "ex2")
 SOLVER_AUTO, SOLVER_EXACT, SOLVER_AUTO_SMALL = 0, 1, 2
 SOLVERS = {"auto": SOLVER_AUTO, "exact": SOLVER_EXACT, "auto_small": SOLVER_AUTO_SMALL}
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
+SCHEME_SEMI_IMPLICIT, SCHEME_EXPLICIT = 0, 1
 
 
 class HsgnParams(C.Structure):
     _fields_ = [("g", C.c_double), ("lam", C.c_double), ("dx", C.c_double), ("cfl", C.c_double),
                 ("mcfl", C.c_double), ("dt_fixed", C.c_double), ("t_end", C.c_double),
-                ("bc", C.c_int32), ("has_bathymetry", C.c_int32), ("order", C.c_int32)]
+                ("bc", C.c_int32), ("has_bathymetry", C.c_int32), ("order", C.c_int32),
+                ("scheme", C.c_int32)]
 
 
 _lib = None
@@ -102,7 +105,8 @@ class Solver:
         pa = (HsgnParams * self.n_inst)()
         for j, p in enumerate(params):
             pa[j] = HsgnParams(p["g"], p["lam"], p["dx"], p["cfl"], p["mcfl"], p["dt_fixed"],
-                               p["t_end"], int(p["bc"]), int(p["has_b"]), int(p.get("order", 2)))
+                               p["t_end"], int(p["bc"]), int(p["has_b"]), int(p.get("order", 2)),
+                               int(p.get("scheme", SCHEME_SEMI_IMPLICIT)))
         if b is not None:
             b = b.to(self.device, torch.float64).contiguous()
         self._b = b
@@ -142,11 +146,15 @@ class Solver:
                     exact_multi=int(cnt[2]), window_rows=int(cnt[3]))
 
     @classmethod
-    def from_workload(cls, wl, device="cuda", solver=None, order=2):
-        """order 2: the two-stage IMEX step; 1: the first-order scheme."""
-        params = [dict(g=wl.g[j], lam=wl.lam[j], dx=wl.dx[j], cfl=wl.cfl[j], mcfl=wl.mcfl[j],
+    def from_workload(cls, wl, device="cuda", solver=None, order=2, scheme=SCHEME_SEMI_IMPLICIT,
+                      cfl=None):
+        """order 2: the two-stage IMEX step; 1: the first-order scheme.
+        scheme SCHEME_EXPLICIT: the explicit Heun step (flat bottom); cfl, if
+        given, replaces the workload's CFL number."""
+        params = [dict(g=wl.g[j], lam=wl.lam[j], dx=wl.dx[j],
+                       cfl=wl.cfl[j] if cfl is None else cfl, mcfl=wl.mcfl[j],
                        dt_fixed=wl.dt_fixed[j], t_end=wl.t_end[j], bc=wl.bc[j], has_b=wl.has_b[j],
-                       order=order)
+                       order=order, scheme=scheme)
                   for j in range(wl.n_inst)]
         b = None if wl.b is None else torch.from_numpy(wl.b).to(device)
         s = cls(wl.offsets, params, b, device=device)

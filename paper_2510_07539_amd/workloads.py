@@ -191,6 +191,25 @@ def batched_bar(n_inst=4096, seed=3, n_lo=512, n_hi=16384, dx=0.04, h0=0.4,
     return _pack("batched_bar", parts, nsteps, dict(seed=seed))
 
 
+def batched_flat(n_inst=4096, seed=3, n_lo=512, n_hi=16384, dx=0.04, h0=0.4,
+                 lams=(100.0, 1000.0, 10000.0), nsteps=100) -> Workload:
+    """Flat-bottom twin of the batched bar workload (the explicit scheme has
+    no bed): the same draws from default_rng(seed) in the same order (the bar
+    toe is drawn and unused), solitary waves on depth h0, transmissive."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.integers(n_lo, n_hi + 1, size=n_inst)
+    amps = rng.uniform(0.05, 0.4, size=n_inst) * h0
+    rng.uniform(0.35, 0.45, size=n_inst)
+    lam_j = rng.choice(np.asarray(lams, dtype=np.float64), size=n_inst)
+    parts = []
+    for j in range(n_inst):
+        N = int(Ns[j])
+        x = (np.arange(N) + 0.5) * dx
+        h, u, ux = soliton(x, h0, amps[j], 0.2 * N * dx)
+        parts.append(_part(N, dx, lam_j[j], BC_TRANSMISSIVE, h, u, ux))
+    return _pack("batched_flat", parts, nsteps, dict(seed=seed))
+
+
 def long_periodic(N=1 << 24, dx=0.01, lam=1e4, seed=4, K=16, nsteps=200) -> Workload:
     """C4: one long periodic mesh, h = 1 + sum_k a_k cos(2 pi k x / L + phi_k),
     a_k ~ U[0, 0.01], phi_k ~ U[0, 2 pi) drawn in that order from default_rng(seed)."""

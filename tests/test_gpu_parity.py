@@ -42,13 +42,16 @@ def field_err(a, ref):
     return d / scale if scale > 0 else d
 
 
-def check_instance(j, U, wl, nsteps, tol=TOL, seed=0, state_sens=False, order=2):
+def check_instance(j, U, wl, nsteps, tol=TOL, seed=0, state_sens=False, order=2, scheme=0,
+                   cfl=None):
     """Bars (1) and (2) for instance j; returns (state error, worst field ratio).
     state_sens: bar (1) becomes max(tol, 8 s) with s the oracle's own relative
     state sensitivity to a half-ulp perturbation (for runs that approach a
     loss of coercivity, where that sensitivity itself exceeds tol)."""
     n, prm, b, U0 = wl.instance(j)
-    p = O.make_params(**prm, order=order)
+    if cfl is not None:
+        prm = dict(prm, cfl=cfl)
+    p = O.make_params(**prm, order=order, scheme=scheme)
     orc, Uo, to = O.run(p, b, U0, 0.0, nsteps)
     assert orc == 0, ("oracle", j, orc)
     rng = np.random.default_rng(seed + j)
@@ -73,11 +76,11 @@ def check_instance(j, U, wl, nsteps, tol=TOL, seed=0, state_sens=False, order=2)
 
 
 def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", solver="auto",
-            order=2):
-    note("parity %s [%s, order %d]: %s, %d instances, %d cells, %d steps" % (
-        label, solver, order, wl.name, wl.n_inst, wl.n_cells, nsteps))
+            order=2, scheme=0, cfl=None):
+    note("parity %s [%s, order %d, scheme %d]: %s, %d instances, %d cells, %d steps" % (
+        label, solver, order, scheme, wl.name, wl.n_inst, wl.n_cells, nsteps))
     Solver = _solver()
-    s = Solver.from_workload(wl, solver=solver, order=order)
+    s = Solver.from_workload(wl, solver=solver, order=order, scheme=scheme, cfl=cfl)
     info = s.plan_info()
     note("  plan: %d windows, %d two-pass tiles, halo max %d" % (
         info["windows"], info["exact_tiles"], int(info["halo"].max())))
@@ -95,7 +98,7 @@ def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", 
     worst = 0.0
     worst_ratio = 0.0
     for j in insts:
-        e, r, to = check_instance(j, U, wl, nsteps, tol, order=order)
+        e, r, to = check_instance(j, U, wl, nsteps, tol, order=order, scheme=scheme, cfl=cfl)
         assert abs(tg[j] - to) <= 1e-12 * max(1.0, abs(to)), (j, tg[j], to)
         worst = max(worst, e)
         worst_ratio = max(worst_ratio, r)
@@ -329,6 +332,80 @@ def test_first_order_adjoint_is_rejected():
     with pytest.raises(HsgnError):
         s.adjoint(3, 2, torch.zeros((1, 1), dtype=torch.int32), torch.zeros((1, 3, 1)), z)
     s.close()
+
+
+# ---------------------------------------------------------------------------
+# Fully explicit hSGN scheme with Heun's method (Sec. 4.1, flat bottom,
+# CFL 0.4 on |u| + c as in the paper's comparisons)
+# ---------------------------------------------------------------------------
+EXS = 1  # scheme: explicit
+CFL_EX = 0.4
+
+
+def _flat_mix():
+    a = WL.solitary(N=800, lam=100.0, t_end=0.0)                # periodic, one tile
+    b = WL.solitary(N=3001, L=750.25, lam=1000.0, t_end=0.0)    # periodic, ragged tiles
+    c = WL.batched_flat(n_inst=6, seed=17, n_lo=513, n_hi=5000)  # transmissive, ragged
+    return WL.concat("explicit mix", [a, b, c])
+
+
+def test_explicit_parity_mix():
+    compare(_flat_mix(), 60, label="explicit Heun", scheme=EXS, cfl=CFL_EX)
+
+
+def test_explicit_edge_sizes():
+    parts = []
+    for n in (4, 5, 7, 1023, 1024, 1025, 2049):
+        for bc in (0, 1):
+            parts.append(WL.solitary(N=n, L=n * 0.25, lam=300.0, t_end=0.0, bc=bc))
+    compare(WL.concat("explicit edge sizes", parts), 25, label="explicit sizes", scheme=EXS,
+            cfl=CFL_EX)
+
+
+def test_explicit_graph_replay_equals_eager_and_t_end():
+    Solver = _solver()
+    wl = _flat_mix()
+    s1 = Solver.from_workload(wl, scheme=EXS, cfl=CFL_EX)
+    s1.step(40)
+    s2 = Solver.from_workload(wl, scheme=EXS, cfl=CFL_EX)
+    s2.run(40, block=20)
+    s2.step(1)
+    s2.run(19, block=20)
+    s1.step(20)
+    (a, ta), (b, tb) = s1.get_state(), s2.get_state()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    assert torch.equal(ta, tb)
+    s1.close()
+    s2.close()
+    # t_end: the last step is clamped and the instance then stays frozen
+    wl = WL.solitary(N=600, L=150.0, lam=100.0, t_end=0.05)
+    compare(wl, 40, label="explicit to t_end", scheme=EXS, cfl=CFL_EX)
+
+
+def test_explicit_rejects_bed_adjoint_and_autotune():
+    from paper_2510_07539_amd.hsgn import HsgnError
+    Solver = _solver()
+    with pytest.raises(HsgnError):
+        Solver.from_workload(WL.batched_bar(n_inst=2, seed=1, n_lo=600, n_hi=900), scheme=EXS)
+    wl = WL.solitary(N=200, L=50.0, t_end=0.0)
+    wl.dt_fixed[:] = 0.001
+    s = Solver.from_workload(wl, scheme=EXS)
+    with pytest.raises(HsgnError):
+        s.autotune()
+    z = torch.from_numpy(wl.h).cuda()
+    with pytest.raises(HsgnError):
+        s.adjoint(3, 2, torch.zeros((1, 1), dtype=torch.int32), torch.zeros((1, 3, 1)), z)
+    s.close()
+
+
+def test_explicit_batched_flat_full_size_sampled():
+    """The flat batched workload at its full size (4096 instances, 3.4e7
+    cells), 20 steps; 16 instances spread over the batch against the oracle."""
+    wl = WL.batched_flat()
+    insts = list(range(0, wl.n_inst, wl.n_inst // 16))
+    compare(wl, 20, use_run=True, block=10, insts=insts, label="batched flat full size",
+            scheme=EXS, cfl=CFL_EX)
 
 
 def test_dam_break_full_run():
