@@ -55,6 +55,8 @@ def bytes_per_cell(kind, bed):
             "win2": (8 + b + 4) * 8,
             "reduce1": (4 + b) * 8,         # reads U^n (+ b)
             "reduce2": (8 + b) * 8,         # reads U^n, U^(1) (+ b)
+            "ex1": (4 + 4) * 8,             # explicit Heun stage 1: reads U^n, writes U1
+            "ex2": (8 + 4) * 8,             # stage 2: reads U^n and U1, writes U^{n+1}
             }.get(kind, 0)
 
 
@@ -65,6 +67,10 @@ def make_workload(name):
                                   "dx=0.04 m, h0=0.4 m, soliton a_j~U[0.05,0.4]h0 over a "
                                   "trapezoidal bar (0.3 m, 1:20 / 2 m crest / 1:10), "
                                   "lambda_j in {100,1000,10000}, transmissive, CFL 0.9")
+    if name == "batched_flat":
+        return WL.batched_flat(), ("batched_flat: the batched_bar draws on a flat bottom (4096 "
+                                   "instances, N_j~U{512..16384}, seed 3, dx=0.04 m, h0=0.4 m, "
+                                   "lambda_j in {100,1000,10000}), transmissive")
     if name == "dam_break":
         return WL.dam_break(), "dam_break: N=20000 on [-300,300] m, lambda=1000, transmissive"
     if name == "long_periodic":
@@ -125,6 +131,55 @@ def cpu_baseline(wl, budget_s=15.0, n_sample=1024, max_steps=200, order=2):
     return {"value": rate, "unit": "cell-stage updates/s", "cores": cores, "kind": "oracle",
             "sample": "first %d instances (%d cells) of the same workload, %d IMEX steps, %.1f s"
                       % (sub.n_inst, sub.n_cells, steps, el)}
+
+
+def scheme_comparison(si_steps=20):
+    """The paper's cost comparison on MI355X: the semi-implicit step (CFL 0.9
+    on |u| + sqrt(g h)) against the explicit Heun step (CFL 0.4 on |u| + c),
+    both advancing the flat batch to the same physical time T, one lambda at
+    a time.  T = si_steps * 0.9 dx / max(|u| + sqrt(g h)) of the initial
+    state; each run stops once every instance has reached T (t_end clamp)."""
+    import numpy as np
+    import torch
+    from paper_2510_07539_amd import workloads as WL
+    from paper_2510_07539_amd.hsgn import SCHEME_EXPLICIT, SCHEME_SEMI_IMPLICIT, Solver
+    wl = WL.batched_flat()
+    out = []
+    for lam in (100.0, 1000.0, 10000.0):
+        sub = wl.subset([j for j in range(wl.n_inst) if wl.lam[j] == lam])
+        smax = float(np.max(np.abs(sub.q / sub.h) + np.sqrt(9.81 * sub.h)))
+        T = si_steps * 0.9 * float(sub.dx[0]) / smax
+        sub.t_end[:] = T
+        row = {"lambda": lam, "instances": sub.n_inst, "cells": sub.n_cells, "T_s": T}
+        for name, scheme, cfl in (("semi_implicit", SCHEME_SEMI_IMPLICIT, 0.9),
+                                  ("explicit", SCHEME_EXPLICIT, 0.4)):
+            s = Solver.from_workload(sub, solver="auto_small" if scheme == 0 else None,
+                                     scheme=scheme, cfl=cfl)
+            try:
+                def to_T():
+                    steps = 0
+                    while True:
+                        s.run(10, block=10)
+                        steps += 10
+                        _, t = s.get_state()
+                        if bool((t >= T * (1 - 1e-12)).all()):
+                            return steps
+                # one untimed pass (code loading, graph capture), then the same
+                # run again from the initial state with the cached graph
+                to_T()
+                s.set_state(*[torch.from_numpy(a).cuda() for a in sub.state()])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                steps = to_T()
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                rc, _ = s.status()
+            finally:
+                s.close()
+            row[name] = {"cfl": cfl, "steps": steps, "ms": round(1e3 * el, 2), "rc": rc}
+        row["explicit_over_semi_implicit"] = round(row["explicit"]["ms"] / row["semi_implicit"]["ms"], 3)
+        out.append(row)
+    return out
 
 
 def adjoint_cost(reps=2):
@@ -197,6 +252,10 @@ def main():
                     help="only the gradient workload (one timed adjoint), one JSON line")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: a plain copy of known size, then eager steps")
+    ap.add_argument("--scheme", default="si", choices=["si", "explicit"],
+                    help="explicit: the fully explicit Heun step (flat batch, CFL 0.4)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the semi-implicit vs explicit time-to-T comparison")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -213,12 +272,21 @@ def main():
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_cost(reps=1)}))
         return
+    explicit = args.scheme == "explicit"
+    if explicit and args.workload == "batched_bar":
+        args.workload = "batched_flat"  # the explicit scheme has no bed
     wl, desc = make_workload(args.workload)
     bed = wl.b is not None
-    s = Solver.from_workload(wl, solver=None if args.solver == "tune" else args.solver,
-                             order=args.order)
+    if explicit:
+        from paper_2510_07539_amd.hsgn import SCHEME_EXPLICIT
+        s = Solver.from_workload(wl, scheme=SCHEME_EXPLICIT, cfl=0.4)
+        desc += "; explicit Heun step, CFL 0.4 on |u| + c"
+        args.order = 2  # two Heun stages per step
+    else:
+        s = Solver.from_workload(wl, solver=None if args.solver == "tune" else args.solver,
+                                 order=args.order)
     tuned = None
-    if args.solver == "tune" and not args.probe:
+    if args.solver == "tune" and not args.probe and not explicit:
         chosen, tms = s.autotune(4)
         tuned = {"kept": chosen, "ms_per_step": {k: round(v, 4) for k, v in tms.items()}}
     plan = s.plan_info()
@@ -261,7 +329,8 @@ def main():
     dom = max(tot, key=lambda k: tot[k])
     ms_avg, launches = kt[dom][0] / max(kt[dom][1], 1), kt[dom][1]
     cells_launch = {"reduce1": ex_multi_cells, "reduce2": ex_multi_cells, "stage1": ex_cells,
-                    "stage2": ex_cells, "win1": win_cells, "win2": win_cells}.get(dom, 0)
+                    "stage2": ex_cells, "win1": win_cells, "win2": win_cells,
+                    "ex1": wl.n_cells, "ex2": wl.n_cells}.get(dom, 0)
     alg_bytes = bytes_per_cell(dom, bed) * cells_launch
     achieved = alg_bytes / (ms_avg * 1e-3) / 1e9 if ms_avg > 0 else 0.0
     h = src_hash()
@@ -271,12 +340,15 @@ def main():
         traffic = tr["bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-            "kernel": ("k_win<%s>" if dom.startswith("win") else "k_stage<%s>") % dom,
+            "kernel": ("k_win<%s>" if dom.startswith("win") else
+                       "k_ex<%s>" if dom.startswith("ex") else "k_stage<%s>") % dom,
             "avg_launch_ms": round(ms_avg, 4),
             "alg_bytes_per_launch": alg_bytes,
             "alg_bytes_per_cell": bytes_per_cell(dom, bed)}
     step_bytes = (bytes_per_cell("stage1", bed) if args.order == 1 else
                   (bytes_per_cell("stage1", bed) + bytes_per_cell("stage2", bed)) / 2.0)
+    if explicit:
+        step_bytes = (bytes_per_cell("ex1", False) + bytes_per_cell("ex2", False)) / 2.0
     out = {
         "metric": "cell-stage updates/s (FP64, batched vs per-instance) at 1e-11 oracle match",
         "value": value,
@@ -291,7 +363,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n_inst": wl.n_inst, "cells": wl.n_cells,
-                   "graph_block_steps": args.block, "order": args.order,
+                   "graph_block_steps": args.block, "order": args.order, "scheme": args.scheme,
                    "solver": tuned["kept"] if tuned else args.solver, "autotune": tuned,
                    "windows": plan["windows"], "window_rows": plan["window_rows"],
                    "two_pass_tiles": plan["exact_tiles"]},
@@ -299,7 +371,7 @@ def main():
         "step_hbm_frac": round(value * step_bytes / 1e9 / HBM_PEAK_GBPS, 4),
         "kernel_ms_per_step": {k: round(v[0] / args.timed_steps, 4) for k, v in kt.items() if v[1]},
     }
-    if not args.no_per_instance and wl.n_inst > 1:
+    if not args.no_per_instance and wl.n_inst > 1 and not explicit:
         r, pel, ns = per_instance_rate(wl, 32, 3, order=args.order)
         out["per_instance"] = {"value": r, "unit": "cell-stage updates/s",
                                "sample": "%d instances spread over the batch, one context each, "
@@ -308,7 +380,9 @@ def main():
     s.close()
     if not args.no_adjoint and args.workload == "batched_bar" and args.order == 2:
         out["adjoint"] = adjoint_cost()
-    if not args.no_cpu:
+    if not args.no_compare and args.workload == "batched_bar" and args.order == 2:
+        out["scheme_comparison"] = scheme_comparison()
+    if not args.no_cpu and not explicit:
         out["cpu_baseline"] = cpu_baseline(wl, order=args.order)
     print(json.dumps(out))
 

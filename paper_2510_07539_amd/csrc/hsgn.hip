@@ -89,6 +89,9 @@ struct hsgn_ctx {
   double *d_rlo = nullptr, *d_rdi = nullptr, *d_rup = nullptr, *d_rrhs = nullptr,
          *d_rx = nullptr, *d_scp = nullptr, *d_sy = nullptr, *d_sv = nullptr, *d_sw = nullptr;
   std::vector<GraphEntry> graphs;
+  // launch configuration the cached graphs were captured with: a re-plan
+  // that reproduces it (same counts, same descriptor buffers) keeps them
+  std::vector<uintptr_t> graph_sig;
   std::string err;
   // host copy of the full two-pass tiling (all instances)
   std::vector<TileDesc> h_tiles_all;
@@ -490,8 +493,15 @@ int make_plan(hsgn_ctx* c) {
   c->nwin = (int)win.size();
   // uploads read host vectors that die here
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
-  c->graphs.clear();
+  const std::vector<uintptr_t> sig = {
+      (uintptr_t)c->win_nt, (uintptr_t)c->n_ex_tiles, (uintptr_t)c->n_ex_tiles_multi,
+      (uintptr_t)c->n_ex_multi, (uintptr_t)c->nwin, (uintptr_t)c->d_ex_tiles,
+      (uintptr_t)c->d_ex_tiles_multi, (uintptr_t)c->d_ex_multi, (uintptr_t)c->d_win};
+  if (sig != c->graph_sig) {
+    for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    c->graph_sig = sig;
+  }
   return HSGN_OK;
 }
 

@@ -19,15 +19,17 @@
 // One workgroup owns a tile of NT * KX cells of one instance.  The four
 // fields of the stage operand are staged through LDS with coalesced loads
 // (tile plus two ghost cells per side: periodic wrap or zero-order copy);
-// each thread computes its KX cells from the KX + 1 faces around them.
+// the face fluxes are computed once per face into LDS, then every cell is
+// updated from its two faces.  Threads take faces and cells at stride NT,
+// so every global load and store is coalesced.
 #pragma once
 
 #include "hsgn_kernels.hpp"
 
 namespace hsgn {
 
-constexpr int kExNT = 256;               // threads per tile
-constexpr int kExK = 4;                  // cells per thread
+constexpr int kExNT = 512;               // threads per tile
+constexpr int kExK = 2;                  // cells per thread
 constexpr int kExTile = kExNT * kExK;    // cells per tile
 
 struct ExArgs {
@@ -51,120 +53,104 @@ struct ExArgs {
   int32_t* __restrict__ status;
 };
 
-// Staged index i of a thread's window: one pad double after every four, so
-// that threads reading KX + 4 consecutive values (stride KX) spread over
-// the banks.
-__device__ __forceinline__ int xpad(int i) { return i + (i >> 2); }
-
 template <int NT, int KX, int STAGE>
 __global__ __launch_bounds__(NT) void k_ex(ExArgs A) {
-  constexpr int TL = NT * KX;          // tile cells
-  constexpr int SL = TL + 4;           // staged cells (two ghosts per side)
-  constexpr int SP = SL + (SL >> 2) + 1;
-  __shared__ double X[4][SP];
+  constexpr int TL = NT * KX;  // tile cells
+  constexpr int SL = TL + 4;   // staged cells (two ghosts per side)
+  __shared__ double X[4][SL];       // stage operand; staged index s <-> cell s - 2
+  __shared__ double F[4][TL + 1];   // face fluxes (h, q u, m u, W u); face e: cells e-1 | e
   const TileDesc td = A.tiles[blockIdx.x];
   const InstDesc I = A.inst[td.inst];
   const double dt = A.dt[td.inst];
   const int t = threadIdx.x;
-  const int n = I.n, bc = I.bc;
-  const int64_t base = I.off;
+  const int n = I.n, bc = I.bc, len = td.len;
+  const int64_t base = I.off + td.start;  // first cell of the tile
   const double* in[4] = {A.in_h, A.in_q, A.in_m, A.in_W};
   const double* un[4] = {A.un_h, A.un_q, A.un_m, A.un_W};
   double* out[4] = {A.o_h, A.o_q, A.o_m, A.o_W};
-  const int p0 = t * KX;  // first tile cell of this thread
-  const int own = td.len - p0 < KX ? (td.len - p0 > 0 ? td.len - p0 : 0) : KX;
 
   if (!(dt > 0.0)) {  // frozen instance: the state stays
-    for (int i = t; i < td.len; i += NT) {
-      const int64_t gi = base + td.start + i;
+    for (int i = t; i < len; i += NT) {
 #pragma unroll
-      for (int f = 0; f < 4; ++f) out[f][gi] = un[f][gi];
+      for (int f = 0; f < 4; ++f) out[f][base + i] = un[f][base + i];
     }
     return;
   }
-  // ---- staging: staged index i <-> instance cell start - 2 + i
-  const int SLn = td.len + 4;
+  // ---- staging (instance-relative cell start - 2 + s, wrapped or clamped)
 #pragma unroll
   for (int r = 0; r < (SL + NT - 1) / NT; ++r) {
-    const int i = t + r * NT;
-    if (i < SLn) {
-      int c = td.start - 2 + i;
+    const int si = t + r * NT;
+    if (si < len + 4) {
+      int c = td.start - 2 + si;
       if (bc == 0) c = c < 0 ? c + n : (c >= n ? c - n : c);
       else c = c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
 #pragma unroll
-      for (int f = 0; f < 4; ++f) X[f][xpad(i)] = in[f][base + c];
+      for (int f = 0; f < 4; ++f) X[f][si] = in[f][I.off + c];
     }
   }
   __syncthreads();
-
   const double g = I.g, lam = I.lam, idx = 1.0 / I.dx, i2dx = 0.5 / I.dx;
-  // window of this thread: v[f][k] = staged p0 + k (cells p0 - 2 .. p0 + KX + 1)
-  // (threads past the tile's end keep zeros and only join the reductions)
-  double v[4][KX + 4];
-#pragma unroll
-  for (int f = 0; f < 4; ++f)
-#pragma unroll
-    for (int k = 0; k < KX + 4; ++k) v[f][k] = own > 0 ? X[f][xpad(p0 + k)] : 0.0;
-  // Rusanov fluxes at faces e = 0..KX: face e lies between cells p0 + e - 1
-  // and p0 + e; its stencil is v[.][e .. e + 3]
-  double Fh[KX + 1], Fq[KX + 1], Fm[KX + 1], FW[KX + 1];
   bool bad = false;
+  // ---- Rusanov fluxes of faces 0..len (stencil: staged e .. e + 3)
 #pragma unroll
-  for (int e = 0; e <= KX; ++e) {
-    double L[4], R[4];
+  for (int r = 0; r <= KX; ++r) {
+    const int e = t + r * NT;
+    if (e <= len) {
+      double L[4], R[4];
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      L[f] = v[f][e + 1] + 0.25 * (v[f][e + 2] - v[f][e]);
-      R[f] = v[f][e + 2] - 0.25 * (v[f][e + 3] - v[f][e + 1]);
+      for (int f = 0; f < 4; ++f) {
+        L[f] = X[f][e + 1] + 0.25 * (X[f][e + 2] - X[f][e]);
+        R[f] = X[f][e + 2] - 0.25 * (X[f][e + 3] - X[f][e + 1]);
+      }
+      bad |= !(L[0] > 0.0) || !(R[0] > 0.0);
+      const double iL = 1.0 / L[0], iR = 1.0 / R[0];
+      const double uL = L[1] * iL, uR = R[1] * iR;
+      const double eL = L[2] * iL * iL, eR = R[2] * iR * iR;
+      const double sL = fabs(uL) + sqrt(g * L[0] + (lam / 3.0) * eL * eL);
+      const double sR = fabs(uR) + sqrt(g * R[0] + (lam / 3.0) * eR * eR);
+      const double al = fmax(sL, sR);
+      F[0][e] = 0.5 * (L[1] + R[1] - al * (R[0] - L[0]));
+      F[1][e] = 0.5 * (L[1] * uL + R[1] * uR - al * (R[1] - L[1]));
+      F[2][e] = 0.5 * (L[2] * uL + R[2] * uR - al * (R[2] - L[2]));
+      F[3][e] = 0.5 * (L[3] * uL + R[3] * uR - al * (R[3] - L[3]));
     }
-    // faces beyond a short tile's last cell read stale staging: no flag
-    if (own > 0 && e <= own) bad |= !(L[0] > 0.0) || !(R[0] > 0.0);
-    const double iL = 1.0 / L[0], iR = 1.0 / R[0];
-    const double uL = L[1] * iL, uR = R[1] * iR;
-    const double eL = L[2] * iL * iL, eR = R[2] * iR * iR;
-    const double sL = fabs(uL) + sqrt(g * L[0] + (lam / 3.0) * eL * eL);
-    const double sR = fabs(uR) + sqrt(g * R[0] + (lam / 3.0) * eR * eR);
-    const double al = fmax(sL, sR);
-    Fh[e] = 0.5 * (L[1] + R[1] - al * (R[0] - L[0]));
-    Fq[e] = 0.5 * (L[1] * uL + R[1] * uR - al * (R[1] - L[1]));
-    Fm[e] = 0.5 * (L[2] * uL + R[2] * uR - al * (R[2] - L[2]));
-    FW[e] = 0.5 * (L[3] * uL + R[3] * uR - al * (R[3] - L[3]));
   }
+  __syncthreads();
+  // ---- cells: explicit update (stage 1) or Heun average (stage 2)
   double smx = 0.0, umx = 0.0;
 #pragma unroll
-  for (int j = 0; j < KX; ++j) {
-    if (j < own) {
-      const int k = j + 2;  // window index of cell p0 + j
-      const double h = v[0][k], m = v[2][k], W = v[3][k];
+  for (int r = 0; r < KX; ++r) {
+    const int i = t + r * NT;
+    if (i < len) {
+      const int k = i + 2;  // staged index of the cell
+      const double h = X[0][k], m = X[2][k], W = X[3][k];
       bad |= !(h > 0.0);
       const double ih = 1.0 / h;
       const double eh = m * ih * ih;
       const double a2 = g * h + lam * eh * eh - (lam / 3.0) * eh;
       const double alpha = -(2.0 * eh - 1.0) * ih * (1.0 / 3.0);
-      const double dh = (v[0][k + 1] - v[0][k - 1]) * i2dx;
-      const double dm = (v[2][k + 1] - v[2][k - 1]) * i2dx;
+      const double dh = (X[0][k + 1] - X[0][k - 1]) * i2dx;
+      const double dm = (X[2][k + 1] - X[2][k - 1]) * i2dx;
       double Lv[4];
-      Lv[0] = -(Fh[j + 1] - Fh[j]) * idx;
-      Lv[1] = -(Fq[j + 1] - Fq[j]) * idx - a2 * dh - lam * alpha * dm;
-      Lv[2] = -(Fm[j + 1] - Fm[j]) * idx + W;
-      Lv[3] = -(FW[j + 1] - FW[j]) * idx - lam * (eh - 1.0);
-      const int64_t gi = base + td.start + p0 + j;
+      Lv[0] = -(F[0][i + 1] - F[0][i]) * idx;
+      Lv[1] = -(F[1][i + 1] - F[1][i]) * idx - a2 * dh - lam * alpha * dm;
+      Lv[2] = -(F[2][i + 1] - F[2][i]) * idx + W;
+      Lv[3] = -(F[3][i + 1] - F[3][i]) * idx - lam * (eh - 1.0);
       double o[4];
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
-        const double u1 = v[f][k] + dt * Lv[f];
-        o[f] = STAGE == 1 ? u1 : 0.5 * (un[f][gi] + u1);
+        const double u1 = X[f][k] + dt * Lv[f];
+        o[f] = STAGE == 1 ? u1 : 0.5 * (un[f][base + i] + u1);
         bad |= !isfinite(o[f]);
-        out[f][gi] = o[f];
+        out[f][base + i] = o[f];
       }
       if (STAGE == 2) {
-        const double hn = o[0];
-        const double ihn = 1.0 / hn;
-        const double un_ = fabs(o[1] * ihn);
+        const double ihn = 1.0 / o[0];
+        const double uu = fabs(o[1] * ihn);
         const double en = o[2] * ihn * ihn;
-        bad |= !(hn > 0.0);
-        smx = fmax(smx, un_ + sqrt(g * hn + (lam / 3.0) * en * en));
-        umx = fmax(umx, un_);
+        bad |= !(o[0] > 0.0);
+        smx = fmax(smx, uu + sqrt(g * o[0] + (lam / 3.0) * en * en));
+        umx = fmax(umx, uu);
       }
     }
   }
