@@ -75,6 +75,8 @@ def lib():
         L.or_stage.argtypes = [C.c_int, C.POINTER(Params), C.c_double, dp] + [dp] * 12 + [C.POINTER(StageDbg)]
         L.or_dt.restype = C.c_double
         L.or_dt.argtypes = [C.c_int, C.POINTER(Params), dp, dp, C.c_double]
+        L.or_sgn_phi.restype = C.c_int
+        L.or_sgn_phi.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp]
         L.or_dt_ex.restype = C.c_double
         L.or_dt_ex.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, C.c_double]
         L.or_step.restype = C.c_int
@@ -108,7 +110,7 @@ def _p(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-SCHEME_SI, SCHEME_EXPLICIT = 0, 1
+SCHEME_SI, SCHEME_EXPLICIT, SCHEME_SGN = 0, 1, 2
 
 
 def make_params(g=9.81, lam=100.0, dx=1.0, cfl=0.9, mcfl=0.5, dt_fixed=0.0,
@@ -166,6 +168,14 @@ def dt(p: Params, h, q, t=0.0) -> float:
 def dt_ex(p: Params, h, q, m, t=0.0) -> float:
     h, q, m = _f(h), _f(q), _f(m)
     return lib().or_dt_ex(len(h), C.byref(p), _p(h), _p(q), _p(m), float(t))
+
+
+def sgn_phi(p: Params, h, q):
+    """phi of the standard SGN elliptic problem; returns (rc, phi)."""
+    h, q = _f(h), _f(q)
+    phi = np.empty(len(h))
+    rc = lib().or_sgn_phi(len(h), C.byref(p), _p(h), _p(q), _p(phi))
+    return rc, phi
 
 
 def step(p: Params, b, U, t=0.0):

@@ -40,6 +40,15 @@
  * eigenvalues of the system it treats explicitly (the print has |u|).  As
  * printed, one step at rest grows by a factor 1.011 (lambda = 100) to 1.029
  * (lambda = 1000) at CFL 0.4; the pressure terms stay central as printed.
+ *
+ * The standard SGN equations in the elliptic-hyperbolic form of Sec. 4.3
+ * (eq. SGN_standard; scheme = 2, flat bottom, lambda unused) are here as the
+ * explicit scheme of Sec. 4.4 with Heun's method.  Readings: the g-term of
+ * the right-hand side h* carries h^3 (as its derivation from eq. SGN_standard
+ * and the units require; the print has h); h^3 at a face is the mean of the
+ * two cell values; the Rusanov speed of the shallow-water fluxes is
+ * max(|u| + sqrt(g h)); at a transmissive boundary phi has zero gradient
+ * (the ghost copies the boundary cell, as for the state).
  */
 #include "hsgn_oracle.h"
 
@@ -507,6 +516,117 @@ static int FN(or_ex_step)(int n, const or_params* p, real_t* h, real_t* q, real_
 }
 
 /* ---------------------------------------------------------------------- */
+/* Standard SGN (Sec. 4.3-4.4), flat bottom, state (h, q = h u):            */
+/*   h_t + q_x = 0,  q_t + (q u + g h^2/2)_x = h phi,                       */
+/*   h phi - (h^3/3 phi_x)_x = -(h^3/3 g h_xx + 2 h^3/3 u_x^2)_x            */
+/* discretised as                                                           */
+/*   h_i phi_i - (H_{i+1/2}(phi_{i+1} - phi_i) - H_{i-1/2}(phi_i - phi_{i-1})) */
+/*        / (3 dx^2) = h*_i,   H_{i+1/2} = (h_i^3 + h_{i+1}^3) / 2,          */
+/*   h*_i = -(G_{i+1} - G_{i-1}) / (6 dx^3),                                */
+/*   G_j = g h_j^3 (h_{j+1} - 2 h_j + h_{j-1}) + (h_j^3 / 2)(u_{j+1} - u_{j-1})^2, */
+/* and L_h = -Dhat_x(q), L_q = -Dhat_x(q u + g h^2/2) + h phi with Rusanov  */
+/* fluxes on the unlimited linear reconstruction of (h, q).                 */
+/* ---------------------------------------------------------------------- */
+static int FN(or_sgn_rhs)(int n, const or_params* p, const real_t* h, const real_t* q,
+                          real_t* Lh, real_t* Lq, real_t* phi_out) {
+  const double g = p->g, dx = p->dx;
+  const int bc = p->bc;
+  size_t nc = (size_t)n, nf = (size_t)n + 1;
+  real_t* Fh = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* Fq = (real_t*)malloc(nf * sizeof(real_t));
+  real_t* G = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* lo = (real_t*)calloc(nc, sizeof(real_t));
+  real_t* di = (real_t*)calloc(nc, sizeof(real_t));
+  real_t* up = (real_t*)calloc(nc, sizeof(real_t));
+  real_t* rhs = (real_t*)calloc(nc, sizeof(real_t));
+  real_t* phi = (real_t*)calloc(nc, sizeof(real_t));
+  int rc = OR_OK;
+  if (!Fh || !Fq || !G || !lo || !di || !up || !rhs || !phi) { rc = OR_EINVAL; goto done; }
+  for (int i = 0; i < n; ++i)
+    if (!(RE(h[i]) > 0.0)) { rc = OR_ENONPHYS; goto done; }
+  /* shallow-water Rusanov fluxes, face k between cells k-1 and k */
+  for (int k = 0; k <= n; ++k) {
+    int a = gidx(k - 2, n, bc), b0 = gidx(k - 1, n, bc), b1 = gidx(k, n, bc), c = gidx(k + 1, n, bc);
+    real_t hL = h[b0] + 0.25 * (h[b1] - h[a]), hR = h[b1] - 0.25 * (h[c] - h[b0]);
+    real_t qL = q[b0] + 0.25 * (q[b1] - q[a]), qR = q[b1] - 0.25 * (q[c] - q[b0]);
+    if (!(RE(hL) > 0.0) || !(RE(hR) > 0.0)) { rc = OR_ENONPHYS; goto done; }
+    real_t uL = qL / hL, uR = qR / hR;
+    real_t sL = RABS(uL) + RSQRT(g * hL), sR = RABS(uR) + RSQRT(g * hR);
+    real_t al = RMAX(sL, sR);
+    Fh[k] = 0.5 * (qL + qR - al * (hR - hL));
+    Fq[k] = 0.5 * (qL * uL + 0.5 * g * hL * hL + qR * uR + 0.5 * g * hR * hR - al * (qR - qL));
+  }
+  /* G_j at every cell */
+  for (int j = 0; j < n; ++j) {
+    int jm = gidx(j - 1, n, bc), jp = gidx(j + 1, n, bc);
+    real_t h3 = h[j] * h[j] * h[j];
+    real_t du = q[jp] / h[jp] - q[jm] / h[jm];
+    G[j] = g * h3 * (h[jp] - 2.0 * h[j] + h[jm]) + 0.5 * h3 * du * du;
+  }
+  /* rows of the phi system */
+  for (int i = 0; i < n; ++i) {
+    int im = gidx(i - 1, n, bc), ip = gidx(i + 1, n, bc);
+    real_t Hm = 0.5 * (h[im] * h[im] * h[im] + h[i] * h[i] * h[i]);
+    real_t Hp = 0.5 * (h[i] * h[i] * h[i] + h[ip] * h[ip] * h[ip]);
+    real_t c3 = 1.0 / (3.0 * dx * dx);
+    lo[i] = -c3 * Hm;
+    up[i] = -c3 * Hp;
+    di[i] = h[i] + c3 * (Hm + Hp);
+    rhs[i] = -(G[ip] - G[im]) / (6.0 * dx * dx * dx);
+    if (bc != 0) { /* zero-gradient phi at a transmissive end */
+      if (i == 0) { di[i] += lo[i]; lo[i] = 0.0; }
+      if (i == n - 1) { di[i] += up[i]; up[i] = 0.0; }
+    }
+  }
+  rc = FN(or_tridiag)(n, bc == 0, lo, di, up, rhs, phi);
+  if (rc != OR_OK) goto done;
+  for (int i = 0; i < n; ++i) {
+    Lh[i] = -(Fh[i + 1] - Fh[i]) / dx;
+    Lq[i] = -(Fq[i + 1] - Fq[i]) / dx + h[i] * phi[i];
+    if (phi_out) phi_out[i] = phi[i];
+  }
+done:
+  free(Fh); free(Fq); free(G); free(lo); free(di); free(up); free(rhs); free(phi);
+  return rc;
+}
+
+/* One SGN step with Heun's method (Sec. 4.4), m and W untouched. */
+static int FN(or_sgn_step)(int n, const or_params* p, real_t* h, real_t* q, double dt) {
+  size_t nc = (size_t)n;
+  real_t* buf = (real_t*)malloc(4 * nc * sizeof(real_t));
+  if (!buf) return OR_EINVAL;
+  real_t *Lh = buf, *Lq = buf + nc, *h1 = buf + 2 * nc, *q1 = buf + 3 * nc;
+  int rc = FN(or_sgn_rhs)(n, p, h, q, Lh, Lq, NULL);
+  if (rc == OR_OK) {
+    for (size_t i = 0; i < nc; ++i) {
+      h1[i] = h[i] + dt * Lh[i];
+      q1[i] = q[i] + dt * Lq[i];
+    }
+    rc = FN(or_sgn_rhs)(n, p, h1, q1, Lh, Lq, NULL);
+  }
+  if (rc == OR_OK) {
+    for (size_t i = 0; i < nc; ++i) {
+      h[i] = 0.5 * (h[i] + (h1[i] + dt * Lh[i]));
+      q[i] = 0.5 * (q[i] + (q1[i] + dt * Lq[i]));
+    }
+  }
+  free(buf);
+  return rc;
+}
+
+#ifndef OR_COMPLEX
+/* phi of the SGN elliptic problem for a state (for the pins). */
+int or_sgn_phi(int n, const or_params* p, const double* h, const double* q, double* phi) {
+  size_t nc = (size_t)n;
+  double* tmp = (double*)malloc(2 * nc * sizeof(double));
+  if (!tmp) return OR_EINVAL;
+  int rc = or_sgn_rhs(n, p, h, q, tmp, tmp + nc, phi);
+  free(tmp);
+  return rc;
+}
+#endif
+
+/* ---------------------------------------------------------------------- */
 /* Time step (Sec. 5: dt = CFL dx / max speed, then the material CFL cap).  */
 /* The speed is |u| + sqrt(g h): the lambda-independent rule of the remark  */
 /* after the coercivity proposition (Sec. 3.1).                             */
@@ -538,6 +658,15 @@ double FN(or_dt)(int n, const or_params* p, const real_t* h, const real_t* q, do
 /* ---------------------------------------------------------------------- */
 int FN(or_step)(int n, const or_params* p, const real_t* b,
             real_t* h, real_t* q, real_t* m, real_t* W, double* t, double* dt_out) {
+  if (p->scheme == 2) {
+    if (p->has_b) return OR_EINVAL; /* flat bottom only */
+    double dts = FN(or_dt)(n, p, h, q, *t); /* same rule as the semi-implicit step */
+    if (dt_out) *dt_out = dts;
+    if (!(dts > 0.0)) return OR_OK;
+    int rcs = FN(or_sgn_step)(n, p, h, q, dts);
+    *t += dts;
+    return rcs;
+  }
   if (p->scheme == 1) {
     if (p->has_b) return OR_EINVAL; /* the explicit scheme is for a flat bottom */
     double dte = FN(or_dt_ex)(n, p, h, q, m, *t);

@@ -31,7 +31,9 @@ typedef struct {
   int order;       /* 1: first-order scheme (one stage, tau = dt, no
                       reconstruction); otherwise the two-stage IMEX step */
   int scheme;      /* 0: semi-implicit (above); 1: fully explicit hSGN with
-                      Heun's method (flat bottom; cfl applies to |u| + c) */
+                      Heun's method (flat bottom; cfl applies to |u| + c);
+                      2: standard SGN, elliptic-hyperbolic form, Heun's
+                      method (flat bottom; lambda unused; m, W untouched) */
 } or_params;
 
 /* Optional per-stage intermediates (any pointer may be NULL). Cell arrays
@@ -68,7 +70,8 @@ double or_dt_ex(int n, const or_params* p, const double* h, const double* q, con
                 double t);
 
 /* One full step, in place: the two-stage IMEX step, the first-order
- * semi-implicit step (order 1), or the explicit Heun step (scheme 1).
+ * semi-implicit step (order 1), the explicit Heun step (scheme 1), or the
+ * standard SGN Heun step (scheme 2).
  * *t advances by the step used; *dt_out (may be NULL) receives it.  A zero
  * step leaves the state frozen. */
 int or_step(int n, const or_params* p, const double* b,
@@ -101,6 +104,9 @@ int or_run_gauges(int n, const or_params* p, const double* b, double* h, double*
 int or_run_batch(int n_inst, const long long* offsets, const or_params* p,
                  const double* b, double* h, double* q, double* m, double* W,
                  double* t, int nsteps, int nthreads, int* status);
+
+/* phi of the standard SGN elliptic problem (scheme 2) for the state (h, q). */
+int or_sgn_phi(int n, const or_params* p, const double* h, const double* q, double* phi);
 
 /* Tridiagonal solve: row i reads lo[i] x[i-1] + di[i] x[i] + up[i] x[i+1].
  * cyclic != 0: lo[0] couples x[n-1] and up[n-1] couples x[0]. */

@@ -647,3 +647,108 @@ def test_explicit_rejects_a_bed():
     p = O.make_params(lam=100.0, dx=0.1, has_b=1, scheme=EX)
     rc, _, _, _ = O.step(p, np.zeros(n), (h, np.zeros(n), h * h, np.zeros(n)))
     assert rc == O.EINVAL
+
+
+# ---------------------------------------------------------------------------
+# Standard SGN equations, elliptic-hyperbolic form (Sec. 4.3-4.4, scheme 2,
+# flat bottom, Heun's method).
+# ---------------------------------------------------------------------------
+SGN = O.SCHEME_SGN
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_sgn_rest_and_uniform_flow_are_steady(bc):
+    n = 48
+    for u0 in (0.0, 0.3):
+        h = np.full(n, 0.6)
+        U = (h, u0 * h, h * h, np.zeros(n))
+        p = O.make_params(dx=0.05, bc=bc, scheme=SGN)
+        rc, Un, t = O.run(p, None, U, 0.0, 100)
+        assert rc == 0 and t > 0
+        for a, b in zip(U, Un):
+            assert np.array_equal(a, b)
+
+
+def test_sgn_conserves_mass_and_momentum_periodic():
+    """Periodic: the Rusanov fluxes telescope, and sum_i h_i phi_i equals the
+    sum of the right-hand side h*, itself a telescoping difference."""
+    (h, q, m, W), _ = rand_state(200, 31, amp=0.1)
+    p = O.make_params(dx=0.05, bc=0, scheme=SGN)
+    rc, Un, t = O.run(p, None, (h, q, m, W), 0.0, 100)
+    assert rc == 0
+    assert abs(Un[0].sum() - h.sum()) / h.sum() < 1e-14
+    assert abs(Un[1].sum() - q.sum()) / np.abs(q).sum() < 1e-13
+    assert np.array_equal(Un[2], m) and np.array_equal(Un[3], W)
+
+
+def _sgn_phi_spectral(h, u, L, g=9.81):
+    """The continuous elliptic problem of eq. SGN_standard,
+    h phi - (h^3/3 phi_x)_x = -(h^3/3 g h_xx + 2 h^3/3 u_x^2)_x, periodic,
+    by Fourier collocation (a dense solve): spectrally accurate."""
+    N = len(h)
+    k = 2 * np.pi * np.fft.fftfreq(N, d=L / N)
+    I = np.eye(N)
+    D = np.real(np.fft.ifft(1j * k[:, None] * np.fft.fft(I, axis=0), axis=0))
+    hx, hxx, ux = D @ h, D @ (D @ h), D @ u
+    rhs = -D @ (h ** 3 / 3 * g * hxx + 2 * h ** 3 / 3 * ux ** 2)
+    A = np.diag(h) - D @ np.diag(h ** 3 / 3) @ D
+    return np.linalg.solve(A, rhs)
+
+
+def test_sgn_phi_converges_to_the_continuous_elliptic_problem():
+    L = 10.0
+    errs = []
+    for N in (64, 128, 256):
+        x = (np.arange(N) + 0.5) * (L / N)
+        h = 1.0 + 0.2 * np.sin(2 * np.pi * x / L) + 0.05 * np.cos(4 * np.pi * x / L)
+        u = 0.3 * np.cos(2 * np.pi * x / L)
+        rc, phi = O.sgn_phi(O.make_params(dx=L / N, bc=0, scheme=SGN), h, h * u)
+        assert rc == 0
+        ref = _sgn_phi_spectral(h, u, L)
+        errs.append(np.max(np.abs(phi - ref)) / np.max(np.abs(ref)))
+    assert errs[0] / errs[1] > 3.6 and errs[1] / errs[2] > 3.6, errs
+    assert errs[2] < 2e-3
+
+
+def test_sgn_solitary_wave_second_order():
+    """The SGN solitary wave is an exact travelling solution (Sec. 6.3):
+    the error at t = 2 s falls like dx^2."""
+    L, errs = 100.0, []
+    for N in (200, 400, 800):
+        wl = WL.solitary(N=N, L=L, h0=1.0, a=0.2, lam=100.0, t_end=2.0)
+        n, prm, b, U = wl.instance(0)
+        rc, Un, t = O.run(O.make_params(**prm, scheme=SGN), None, U, 0.0, 100000)
+        assert rc == 0 and t == 2.0
+        x = (np.arange(N) + 0.5) * (L / N)
+        he, _, _ = WL.soliton(x, 1.0, 0.2, 0.5 * L, t=t)
+        errs.append(np.sum(np.abs(Un[0] - he)) * L / N)
+    r1, r2 = math.log2(errs[0] / errs[1]), math.log2(errs[1] / errs[2])
+    assert 1.8 < r1 < 2.3 and 1.8 < r2 < 2.3, errs
+
+
+def test_sgn_linear_dispersion_relation():
+    """A small sinusoid moves with the SGN phase speed,
+    w^2 = g h k^2 / (1 + k^2 h^2 / 3); the phase error after one period falls
+    at second order and extrapolates far below the gap to shallow water."""
+    h0, Lw, g = 1.0, 10.0, 9.81
+    k = 2 * math.pi / Lw
+    w = math.sqrt(g * h0 * k * k / (1 + k * k * h0 * h0 / 3))
+    eps = 1e-6
+    Tp = 2 * math.pi / w
+    phase_err = []
+    for N in (32, 64, 128):
+        dx = Lw / N
+        x = (np.arange(N) + 0.5) * dx
+        th = k * x
+        hp = eps * np.cos(th)
+        U = (h0 + hp, (w / k) * hp, np.ones(N), np.zeros(N))
+        nsteps = 4 * N
+        p = O.make_params(dx=dx, bc=0, dt_fixed=Tp / nsteps, scheme=SGN)
+        rc, Un, t = O.run(p, None, U, 0.0, nsteps)
+        assert rc == 0
+        d = Un[0] - h0
+        phase_err.append(math.atan2((d * np.sin(th)).sum(), (d * np.cos(th)).sum()))
+    assert abs(phase_err[0] / phase_err[1]) > 3.5 and abs(phase_err[1] / phase_err[2]) > 3.5, phase_err
+    gap = abs(math.sqrt(g * h0) * k - w) / w * 2 * math.pi
+    ext = (4 * phase_err[2] - phase_err[1]) / 3
+    assert abs(ext) < 0.01 * gap, (ext, gap)
