@@ -534,7 +534,7 @@ static int FN(or_sgn_rhs)(int n, const or_params* p, const real_t* h, const real
   size_t nc = (size_t)n, nf = (size_t)n + 1;
   real_t* Fh = (real_t*)malloc(nf * sizeof(real_t));
   real_t* Fq = (real_t*)malloc(nf * sizeof(real_t));
-  real_t* G = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* G = (real_t*)malloc((nc + 2) * sizeof(real_t)); /* G[j + 1], j = -1 .. n */
   real_t* lo = (real_t*)calloc(nc, sizeof(real_t));
   real_t* di = (real_t*)calloc(nc, sizeof(real_t));
   real_t* up = (real_t*)calloc(nc, sizeof(real_t));
@@ -556,12 +556,13 @@ static int FN(or_sgn_rhs)(int n, const or_params* p, const real_t* h, const real
     Fh[k] = 0.5 * (qL + qR - al * (hR - hL));
     Fq[k] = 0.5 * (qL * uL + 0.5 * g * hL * hL + qR * uR + 0.5 * g * hR * hR - al * (qR - qL));
   }
-  /* G_j at every cell */
-  for (int j = 0; j < n; ++j) {
-    int jm = gidx(j - 1, n, bc), jp = gidx(j + 1, n, bc);
-    real_t h3 = h[j] * h[j] * h[j];
+  /* G_j at every cell and at the first ghost on each side (ghost states are
+   * the copies or wrapped cells that every stencil reads) */
+  for (int j = -1; j <= n; ++j) {
+    int jc = gidx(j, n, bc), jm = gidx(j - 1, n, bc), jp = gidx(j + 1, n, bc);
+    real_t h3 = h[jc] * h[jc] * h[jc];
     real_t du = q[jp] / h[jp] - q[jm] / h[jm];
-    G[j] = g * h3 * (h[jp] - 2.0 * h[j] + h[jm]) + 0.5 * h3 * du * du;
+    G[j + 1] = g * h3 * (h[jp] - 2.0 * h[jc] + h[jm]) + 0.5 * h3 * du * du;
   }
   /* rows of the phi system */
   for (int i = 0; i < n; ++i) {
@@ -572,7 +573,7 @@ static int FN(or_sgn_rhs)(int n, const or_params* p, const real_t* h, const real
     lo[i] = -c3 * Hm;
     up[i] = -c3 * Hp;
     di[i] = h[i] + c3 * (Hm + Hp);
-    rhs[i] = -(G[ip] - G[im]) / (6.0 * dx * dx * dx);
+    rhs[i] = -(G[i + 2] - G[i]) / (6.0 * dx * dx * dx); /* G_{i+1} - G_{i-1} */
     if (bc != 0) { /* zero-gradient phi at a transmissive end */
       if (i == 0) { di[i] += lo[i]; lo[i] = 0.0; }
       if (i == n - 1) { di[i] += up[i]; up[i] = 0.0; }
