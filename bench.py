@@ -57,6 +57,9 @@ def bytes_per_cell(kind, bed):
             "reduce2": (8 + b) * 8,         # reads U^n, U^(1) (+ b)
             "ex1": (4 + 4) * 8,             # explicit Heun stage 1: reads U^n, writes U1
             "ex2": (8 + 4) * 8,             # stage 2: reads U^n and U1, writes U^{n+1}
+            "sgn_rows": (2 + 4) * 8,        # SGN: reads h, q; writes the 4 bands
+            "sgn_solve": (4 + 1) * 8,       # reads the bands, writes phi
+            "sgn_update": (2 + 1 + 2) * 8,  # reads h, q, phi; writes h, q (stage 1)
             }.get(kind, 0)
 
 
@@ -135,14 +138,15 @@ def cpu_baseline(wl, budget_s=15.0, n_sample=1024, max_steps=200, order=2):
 
 def scheme_comparison(si_steps=20):
     """The paper's cost comparison on MI355X: the semi-implicit step (CFL 0.9
-    on |u| + sqrt(g h)) against the explicit Heun step (CFL 0.4 on |u| + c),
-    both advancing the flat batch to the same physical time T, one lambda at
-    a time.  T = si_steps * 0.9 dx / max(|u| + sqrt(g h)) of the initial
+    on |u| + sqrt(g h)) against the explicit Heun step (CFL 0.4 on |u| + c)
+    and the standard SGN solver (Heun, CFL 0.9), all advancing the flat
+    batch to the same physical time T, one lambda at a time (the SGN run
+    does not depend on lambda).  T = si_steps * 0.9 dx / max(|u| + sqrt(g h)) of the initial
     state; each run stops once every instance has reached T (t_end clamp)."""
     import numpy as np
     import torch
     from paper_2510_07539_amd import workloads as WL
-    from paper_2510_07539_amd.hsgn import SCHEME_EXPLICIT, SCHEME_SEMI_IMPLICIT, Solver
+    from paper_2510_07539_amd.hsgn import SCHEME_EXPLICIT, SCHEME_SEMI_IMPLICIT, SCHEME_SGN, Solver
     wl = WL.batched_flat()
     out = []
     for lam in (100.0, 1000.0, 10000.0):
@@ -152,7 +156,8 @@ def scheme_comparison(si_steps=20):
         sub.t_end[:] = T
         row = {"lambda": lam, "instances": sub.n_inst, "cells": sub.n_cells, "T_s": T}
         for name, scheme, cfl in (("semi_implicit", SCHEME_SEMI_IMPLICIT, 0.9),
-                                  ("explicit", SCHEME_EXPLICIT, 0.4)):
+                                  ("explicit", SCHEME_EXPLICIT, 0.4),
+                                  ("sgn", SCHEME_SGN, 0.9)):
             s = Solver.from_workload(sub, solver="auto_small" if scheme == 0 else None,
                                      scheme=scheme, cfl=cfl)
             try:
@@ -178,6 +183,7 @@ def scheme_comparison(si_steps=20):
                 s.close()
             row[name] = {"cfl": cfl, "steps": steps, "ms": round(1e3 * el, 2), "rc": rc}
         row["explicit_over_semi_implicit"] = round(row["explicit"]["ms"] / row["semi_implicit"]["ms"], 3)
+        row["sgn_over_semi_implicit"] = round(row["sgn"]["ms"] / row["semi_implicit"]["ms"], 3)
         out.append(row)
     return out
 
@@ -252,8 +258,9 @@ def main():
                     help="only the gradient workload (one timed adjoint), one JSON line")
     ap.add_argument("--probe", action="store_true",
                     help="counter probe: a plain copy of known size, then eager steps")
-    ap.add_argument("--scheme", default="si", choices=["si", "explicit"],
-                    help="explicit: the fully explicit Heun step (flat batch, CFL 0.4)")
+    ap.add_argument("--scheme", default="si", choices=["si", "explicit", "sgn"],
+                    help="explicit: the fully explicit Heun step (flat batch, CFL 0.4); "
+                         "sgn: the standard SGN solver (flat batch, CFL 0.9)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the semi-implicit vs explicit time-to-T comparison")
     args = ap.parse_args()
@@ -272,15 +279,19 @@ def main():
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_cost(reps=1)}))
         return
-    explicit = args.scheme == "explicit"
+    explicit = args.scheme != "si"  # the explicit hSGN or the SGN Heun step
     if explicit and args.workload == "batched_bar":
-        args.workload = "batched_flat"  # the explicit scheme has no bed
+        args.workload = "batched_flat"  # these schemes have no bed
     wl, desc = make_workload(args.workload)
     bed = wl.b is not None
     if explicit:
-        from paper_2510_07539_amd.hsgn import SCHEME_EXPLICIT
-        s = Solver.from_workload(wl, scheme=SCHEME_EXPLICIT, cfl=0.4)
-        desc += "; explicit Heun step, CFL 0.4 on |u| + c"
+        from paper_2510_07539_amd.hsgn import SCHEME_EXPLICIT, SCHEME_SGN
+        if args.scheme == "explicit":
+            s = Solver.from_workload(wl, scheme=SCHEME_EXPLICIT, cfl=0.4)
+            desc += "; explicit Heun step, CFL 0.4 on |u| + c"
+        else:
+            s = Solver.from_workload(wl, scheme=SCHEME_SGN)
+            desc += "; standard SGN, Heun step, CFL 0.9 on |u| + sqrt(g h)"
         args.order = 2  # two Heun stages per step
     else:
         s = Solver.from_workload(wl, solver=None if args.solver == "tune" else args.solver,
@@ -330,7 +341,8 @@ def main():
     ms_avg, launches = kt[dom][0] / max(kt[dom][1], 1), kt[dom][1]
     cells_launch = {"reduce1": ex_multi_cells, "reduce2": ex_multi_cells, "stage1": ex_cells,
                     "stage2": ex_cells, "win1": win_cells, "win2": win_cells,
-                    "ex1": wl.n_cells, "ex2": wl.n_cells}.get(dom, 0)
+                    "ex1": wl.n_cells, "ex2": wl.n_cells, "sgn_rows": wl.n_cells,
+                    "sgn_solve": wl.n_cells, "sgn_update": wl.n_cells}.get(dom, 0)
     alg_bytes = bytes_per_cell(dom, bed) * cells_launch
     achieved = alg_bytes / (ms_avg * 1e-3) / 1e9 if ms_avg > 0 else 0.0
     h = src_hash()
@@ -341,14 +353,17 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
             "kernel": ("k_win<%s>" if dom.startswith("win") else
-                       "k_ex<%s>" if dom.startswith("ex") else "k_stage<%s>") % dom,
+                       "k_ex<%s>" if dom.startswith("ex") else
+                       "k_%s" if dom.startswith("sgn") else "k_stage<%s>") % dom,
             "avg_launch_ms": round(ms_avg, 4),
             "alg_bytes_per_launch": alg_bytes,
             "alg_bytes_per_cell": bytes_per_cell(dom, bed)}
     step_bytes = (bytes_per_cell("stage1", bed) if args.order == 1 else
                   (bytes_per_cell("stage1", bed) + bytes_per_cell("stage2", bed)) / 2.0)
-    if explicit:
+    if args.scheme == "explicit":
         step_bytes = (bytes_per_cell("ex1", False) + bytes_per_cell("ex2", False)) / 2.0
+    elif args.scheme == "sgn":  # the minimum of a Heun stage: read 2 (stage 2: 4), write 2
+        step_bytes = (4 + 6) / 2.0 * 8
     out = {
         "metric": "cell-stage updates/s (FP64, batched vs per-instance) at 1e-11 oracle match",
         "value": value,

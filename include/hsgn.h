@@ -27,6 +27,14 @@
  * reconstruction for h, q u, m u, W u; central differences for the pressure
  * terms a^2 h_x + lambda alpha (h eta)_x; sources h w and
  * -lambda (eta/h - 1).  Its dt is CFL dx / max(|u| + c) (eq. CFL_ex).
+ * With scheme = HSGN_SCHEME_SGN a step is the explicit scheme of Sec. 4.4
+ * for the standard SGN equations (eq. SGN_standard) with Heun's method:
+ * per stage, phi from the tridiagonal (cyclic when periodic) system
+ *   h_i phi_i - (H_{i+1/2}(phi_{i+1} - phi_i) - H_{i-1/2}(phi_i - phi_{i-1}))
+ *     / (3 dx^2) = -(G_{i+1} - G_{i-1}) / (6 dx^3),
+ * H = face mean of h^3, G_j = g h_j^3 (h_{j+1} - 2 h_j + h_{j-1})
+ * + (h_j^3 / 2)(u_{j+1} - u_{j-1})^2, then shallow-water Rusanov fluxes
+ * with the source h phi.  Its dt follows the semi-implicit rule.
  *
  * State per cell (all FP64, structure of arrays): h (depth), q = h u,
  * m = h eta, W = h w.  Independent instances ("batch") are concatenated:
@@ -90,11 +98,16 @@ typedef struct {
                             bottom only (has_bathymetry = 0), order 0 or 2;
                             cfl then applies to |u| + c with the hSGN
                             celerity c^2 = g h + (lambda/3)(eta/h)^2
-                            (eq. hSGN_c).  Same for every instance.        */
+                            (eq. hSGN_c).  HSGN_SCHEME_SGN (2): the
+                            standard SGN equations in elliptic-hyperbolic
+                            form (Sec. 4.3-4.4) with Heun's method, flat
+                            bottom, order 0 or 2, lambda unused, m and W
+                            carried unchanged.  Same for every instance.   */
 } hsgn_params;
 
 #define HSGN_SCHEME_SEMI_IMPLICIT 0
 #define HSGN_SCHEME_EXPLICIT 1
+#define HSGN_SCHEME_SGN 2
 
 typedef struct hsgn_ctx hsgn_ctx;
 
@@ -160,8 +173,8 @@ int hsgn_set_solver(hsgn_ctx* ctx, int32_t mode);
  * as it was.  h_ms (host, 3 doubles or NULL): milliseconds per step of each
  * mode, indexed by the mode's value; h_mode (host or NULL): the mode kept.
  * The modes agree with each other to rounding.  Allocates a copy of the
- * state for its duration; synchronises the stream.  The explicit scheme has
- * no solver: HSGN_EINVAL. */
+ * state for its duration; synchronises the stream.  Only the semi-implicit
+ * step has solver modes (else HSGN_EINVAL). */
 int hsgn_autotune(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_mode);
 
 /* Plan of the loaded state (host arrays, any may be NULL): h_mode[j] = 0
@@ -182,7 +195,10 @@ int hsgn_plan_info(hsgn_ctx* ctx, int32_t* h_mode, int32_t* h_halo, int32_t* h_c
 #define HSGN_K_WIN2 8         /* stage 2, windowed single pass               */
 #define HSGN_K_EX1 9          /* explicit scheme, first Heun stage           */
 #define HSGN_K_EX2 10         /* explicit scheme, second Heun stage          */
-#define HSGN_NKERNEL 11
+#define HSGN_K_SGN_ROWS 11    /* SGN: rows of the phi system (both stages)   */
+#define HSGN_K_SGN_SOLVE 12   /* SGN: batched tridiagonal solve for phi      */
+#define HSGN_K_SGN_UPDATE 13  /* SGN: flux update with the source h phi      */
+#define HSGN_NKERNEL 14
 
 /* Measurement variant of hsgn_step: the same launches, each bracketed by HIP
  * events on the library's stream; synchronises at the end.  h_ms[k]

@@ -79,8 +79,9 @@ struct hsgn_ctx {
   bool io_stage1_only = false;  // the step stops after stage 1 (U^(1) only)
   int order = 2;                // 2: two-stage IMEX step; 1: one first-order stage
   int scheme = HSGN_SCHEME_SEMI_IMPLICIT;  // or the explicit Heun step
-  TileDesc* d_xtiles = nullptr;  // tiles of the explicit kernel (kExTile cells)
+  TileDesc* d_xtiles = nullptr;  // tiles of the explicit and SGN kernels (kExTile cells)
   int nxtiles = 0;
+  double* d_sgn = nullptr;       // SGN: rows lo, di, up, rhs of the phi system, and phi
   double* d_dt = nullptr;
   double* d_t = nullptr;
   unsigned long long* d_smax = nullptr;
@@ -164,7 +165,7 @@ void free_all(hsgn_ctx* c) {
                   c->d_dt, c->d_t, c->d_smax, c->d_umax, c->d_status, c->d_rlo, c->d_rdi,
                   c->d_rup, c->d_rrhs, c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw,
                   c->d_ex_tiles, c->d_ex_tiles_multi, c->d_ex_multi, c->d_win, c->d_hmax,
-                  c->d_xtiles};
+                  c->d_xtiles, c->d_sgn};
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (int i = 0; i < 3; ++i)
@@ -267,6 +268,70 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
   hipLaunchKernelGGL(hsgn::k_dt, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_inst, c->d_dt,
                      c->d_t, c->d_smax, c->d_umax, c->d_status);
   mark(HSGN_K_DT, false);
+  if (c->scheme == HSGN_SCHEME_SGN) {
+    // Heun on the SGN operator: rows of the phi system, batched tridiagonal
+    // solve (one workgroup per instance), flux update with the source h phi
+    double* const* un = c->buf[c->cur];
+    double* const* u1 = c->buf[c->s1];
+    double* const* out = c->buf[c->nxt];
+    const size_t nc = (size_t)c->ncell;
+    hsgn::SgnArgs x;
+    std::memset(&x, 0, sizeof x);
+    x.un_h = un[0]; x.un_q = un[1]; x.un_m = un[2]; x.un_W = un[3];
+    x.lo = c->d_sgn; x.di = c->d_sgn + nc; x.up = c->d_sgn + 2 * nc; x.rhs = c->d_sgn + 3 * nc;
+    x.phi = c->d_sgn + 4 * nc;
+    x.inst = c->d_inst;
+    x.tiles = c->d_xtiles;
+    x.dt = c->d_dt;
+    x.smax = c->d_smax;
+    x.umax = c->d_umax;
+    x.status = c->d_status;
+    // exact tiled solve of phi on the two-pass tiling (tiles of kTileMax rows)
+    hsgn::TriArgs ta;
+    ta.inst = c->d_inst;
+    ta.dt = c->d_dt;
+    ta.lo = x.lo; ta.di = x.di; ta.up = x.up; ta.rhs = x.rhs;
+    ta.x = c->d_sgn + 4 * nc;
+    ta.rlo = c->d_rlo; ta.rdi = c->d_rdi; ta.rup = c->d_rup; ta.rrhs = c->d_rrhs;
+    ta.rx = c->d_rx;
+    for (int stage = 1; stage <= 2; ++stage) {
+      double* const* in = stage == 1 ? un : u1;
+      double* const* o = stage == 1 ? u1 : out;
+      x.in_h = in[0]; x.in_q = in[1];
+      x.o_h = o[0]; x.o_q = o[1]; x.o_m = o[2]; x.o_W = o[3];
+      mark(HSGN_K_SGN_ROWS, true);
+      hipLaunchKernelGGL((hsgn::k_sgn_rows<hsgn::kExNT, hsgn::kExK>), dim3(c->nxtiles),
+                         dim3(hsgn::kExNT), 0, c->stream, x);
+      mark(HSGN_K_SGN_ROWS, false);
+      mark(HSGN_K_SGN_SOLVE, true);
+      if (c->n_multi_inst > 0) {
+        ta.tiles = c->d_tiles_multi;
+        hipLaunchKernelGGL((hsgn::k_tri_tiles<kTileMax / 8, 8, true>), dim3(c->ntiles_multi),
+                           dim3(kTileMax / 8), 0, c->stream, ta);
+        hipLaunchKernelGGL(hsgn::k_rsolve<kNTR>, dim3(c->n_multi_inst), dim3(kNTR), 0, c->stream,
+                           c->d_inst, c->d_multi, c->d_dt, c->d_rlo, c->d_rdi, c->d_rup,
+                           c->d_rrhs, c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw);
+      }
+      ta.tiles = c->d_tiles_all;
+      hipLaunchKernelGGL((hsgn::k_tri_tiles<kTileMax / 8, 8, false>), dim3(c->ntiles_all),
+                         dim3(kTileMax / 8), 0, c->stream, ta);
+      mark(HSGN_K_SGN_SOLVE, false);
+      mark(HSGN_K_SGN_UPDATE, true);
+      if (stage == 1)
+        hipLaunchKernelGGL((hsgn::k_sgn_update<hsgn::kExNT, hsgn::kExK, 1>), dim3(c->nxtiles),
+                           dim3(hsgn::kExNT), 0, c->stream, x);
+      else
+        hipLaunchKernelGGL((hsgn::k_sgn_update<hsgn::kExNT, hsgn::kExK, 2>), dim3(c->nxtiles),
+                           dim3(hsgn::kExNT), 0, c->stream, x);
+      mark(HSGN_K_SGN_UPDATE, false);
+    }
+    HIPCHK(c, hipGetLastError());
+    if (!marks_ok) return fail(c, HSGN_EHIP, "hsgn_step_timed: timing events failed");
+    const int old = c->cur;
+    c->cur = c->nxt;
+    c->nxt = old;
+    return HSGN_OK;
+  }
   if (c->scheme == HSGN_SCHEME_EXPLICIT) {
     // Heun: U1 = U^n + dt L(U^n), U^{n+1} = (U^n + U1 + dt L(U1)) / 2
     double* const* un = c->buf[c->cur];
@@ -551,16 +616,17 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
       break;
     }
     c->order = ord;
-    if ((p.scheme != HSGN_SCHEME_SEMI_IMPLICIT && p.scheme != HSGN_SCHEME_EXPLICIT) ||
+    if ((p.scheme != HSGN_SCHEME_SEMI_IMPLICIT && p.scheme != HSGN_SCHEME_EXPLICIT &&
+         p.scheme != HSGN_SCHEME_SGN) ||
         (j > 0 && p.scheme != c->scheme)) {
-      rc = fail(c, HSGN_EINVAL, "instance %d: scheme must be 0 or 1 and the same for every "
+      rc = fail(c, HSGN_EINVAL, "instance %d: scheme must be 0, 1 or 2 and the same for every "
                 "instance", j);
       break;
     }
     c->scheme = p.scheme;
-    if (p.scheme == HSGN_SCHEME_EXPLICIT && (p.has_bathymetry || ord != 2)) {
-      rc = fail(c, HSGN_EINVAL, "instance %d: the explicit scheme needs a flat bottom and "
-                "order 0 or 2", j);
+    if (p.scheme != HSGN_SCHEME_SEMI_IMPLICIT && (p.has_bathymetry || ord != 2)) {
+      rc = fail(c, HSGN_EINVAL, "instance %d: the explicit and SGN schemes need a flat bottom "
+                "and order 0 or 2", j);
       break;
     }
     InstDesc& d = inst[j];
@@ -588,7 +654,7 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
       multi.push_back(j);
       red += 2 * nt;
     }
-    if (p.scheme == HSGN_SCHEME_EXPLICIT) {  // tiles of the explicit kernel
+    if (p.scheme != HSGN_SCHEME_SEMI_IMPLICIT) {  // tiles of the explicit and SGN kernels
       const int nx = (int)((n + hsgn::kExTile - 1) / hsgn::kExTile);
       for (int k = 0; k < nx; ++k) {
         TileDesc t;
@@ -629,6 +695,7 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_tiles_all, tall.size());
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_tiles_multi, tmulti.size());
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_xtiles, xt.size());
+  if (rc == HSGN_OK && c->scheme == HSGN_SCHEME_SGN) rc = dmalloc(c, &c->d_sgn, 5 * nc);
   c->nxtiles = (int)xt.size();
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_multi, multi.size());
   for (int i = 0; i < 3 && rc == HSGN_OK; ++i)
@@ -892,8 +959,8 @@ int hsgn_step_timed(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_count)
 int hsgn_autotune(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_mode) {
   if (!c) return HSGN_EINVAL;
   if (nsteps < 1) return fail(c, HSGN_EINVAL, "hsgn_autotune: nsteps < 1");
-  if (c->scheme == HSGN_SCHEME_EXPLICIT)
-    return fail(c, HSGN_EINVAL, "hsgn_autotune: the explicit scheme has no solver to tune");
+  if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
+    return fail(c, HSGN_EINVAL, "hsgn_autotune: only the semi-implicit step has solver modes");
   int rc = enter(c);
   if (rc) return rc;
   const size_t nc = (size_t)c->ncell, ni = (size_t)c->n_inst;

@@ -722,30 +722,64 @@ __device__ void wg_tri_solve(Lds<NT>& S, const double* __restrict__ lo, const do
   const int k = ch.k;
   const int f = ch.first;
   const bool act = t < ch.active;
+  // The chunk's rows are read (and its scratch rows written back) in blocks
+  // of B rows whose loads are issued together: one memory latency per block
+  // instead of one per row of the recurrence.
+  constexpr int B = 8;
   if (act) {
     double cprev = 0.0, yprev = 0.0, vprev = 1.0, wprev = 0.0;
-    for (int i = 1; i <= k - 2; ++i) {
-      const double l = lo[f + i], d = di[f + i], u = up[f + i], r = rhs[f + i];
-      const double inv = 1.0 / (d - l * cprev);
-      const bool lastint = (i == k - 2);
-      cprev = lastint ? 0.0 : u * inv;
-      yprev = (r - l * yprev) * inv;
-      vprev = (-l * vprev) * inv;
-      wprev = (-l * wprev) * inv - (lastint ? u * inv : 0.0);
-      scp[f + i] = cprev;
-      sy[f + i] = yprev;
-      sv[f + i] = vprev;
-      sw[f + i] = wprev;
+    for (int i0 = 1; i0 <= k - 2; i0 += B) {
+      double L[B], D[B], U[B], R[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int i = i0 + b <= k - 2 ? i0 + b : k - 2;
+        L[b] = lo[f + i];
+        D[b] = di[f + i];
+        U[b] = up[f + i];
+        R[b] = rhs[f + i];
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int i = i0 + b;
+        if (i <= k - 2) {
+          const double l = L[b], d = D[b], u = U[b], r = R[b];
+          const double inv = 1.0 / (d - l * cprev);
+          const bool lastint = (i == k - 2);
+          cprev = lastint ? 0.0 : u * inv;
+          yprev = (r - l * yprev) * inv;
+          vprev = (-l * vprev) * inv;
+          wprev = (-l * wprev) * inv - (lastint ? u * inv : 0.0);
+          scp[f + i] = cprev;
+          sy[f + i] = yprev;
+          sv[f + i] = vprev;
+          sw[f + i] = wprev;
+        }
+      }
     }
     double yn = 0.0, vn = 0.0, wn = 0.0;
-    for (int i = k - 2; i >= 1; --i) {
-      const double c = scp[f + i];
-      yn = sy[f + i] - c * yn;
-      vn = sv[f + i] - c * vn;
-      wn = sw[f + i] - c * wn;
-      sy[f + i] = yn;
-      sv[f + i] = vn;
-      sw[f + i] = wn;
+    for (int i1 = k - 2; i1 >= 1; i1 -= B) {
+      double Cc[B], Y[B], V[B], W[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int i = i1 - b >= 1 ? i1 - b : 1;
+        Cc[b] = scp[f + i];
+        Y[b] = sy[f + i];
+        V[b] = sv[f + i];
+        W[b] = sw[f + i];
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int i = i1 - b;
+        if (i >= 1) {
+          const double c = Cc[b];
+          yn = Y[b] - c * yn;
+          vn = V[b] - c * vn;
+          wn = W[b] - c * wn;
+          sy[f + i] = yn;
+          sv[f + i] = vn;
+          sw[f + i] = wn;
+        }
+      }
     }
     const int l = f + k - 1;
     double R0[4] = {lo[f], di[f], up[f], rhs[f]};
@@ -787,7 +821,19 @@ __device__ void wg_tri_solve(Lds<NT>& S, const double* __restrict__ lo, const do
     const double zb = (j1 == n1 - 1) ? zl : S.d0[j1] + S.d1[j1] * z0 + S.d2[j1] * zl;
     x[f] = zf;
     x[f + k - 1] = zb;
-    for (int i = 1; i <= k - 2; ++i) x[f + i] = sy[f + i] + sv[f + i] * zf + sw[f + i] * zb;
+    for (int i0 = 1; i0 <= k - 2; i0 += B) {
+      double Y[B], V[B], W[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int i = i0 + b <= k - 2 ? i0 + b : k - 2;
+        Y[b] = sy[f + i];
+        V[b] = sv[f + i];
+        W[b] = sw[f + i];
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        if (i0 + b <= k - 2) x[f + i0 + b] = Y[b] + V[b] * zf + W[b] * zb;
+    }
   }
   __syncthreads();
 }
@@ -806,35 +852,22 @@ struct AdjSolveArgs {
   double* sw;
 };
 
-// Register-resident solve of one instance of n <= NT * K rows: each thread
-// eliminates its chunk (consecutive rows, read straight from global memory)
-// into two rows of the level-1 system, which PCR solves in LDS (stopping
-// once every coupling is below 2^-66 of its diagonal); the chunk interiors
-// follow from the spikes.  Longer instances use the global-scratch solve.
+// Register-resident chunk elimination of n <= NT * K rows (a whole system or
+// one tile of it): each thread eliminates its chunk (consecutive rows, read
+// straight from global memory) into two rows of the level-1 system in LDS,
+// keeping the chunk's interior spikes (y, v, w) in registers.  All threads
+// call it; the caller synchronises before the level-1 solve.
 template <int NT, int K>
-__global__ __launch_bounds__(NT) void k_adj_r2(AdjSolveArgs P) {
-  __shared__ Lds<NT> S;
-  const InstDesc D = P.inst[blockIdx.x];
-  if (!(P.dt[blockIdx.x] > 0.0)) return;  // frozen: lam is not used
-  const int64_t o = D.off;
-  const int n = D.n;
-  const bool cyclic = D.bc == 0;
-  if (n > NT * K) {
-    wg_tri_solve<NT>(S, P.lot + o, P.dit + o, P.upt + o, P.hba + o, P.lam + o, n, cyclic,
-                     P.scp + o, P.sy + o, P.sv + o, P.sw + o);
-    return;
-  }
+__device__ __forceinline__ Chunk reg_chunk_elim(Lds<NT>& S, const double* __restrict__ lo,
+                                                const double* __restrict__ di,
+                                                const double* __restrict__ up,
+                                                const double* __restrict__ rhs, int n,
+                                                double (&y)[K], double (&v)[K], double (&w)[K]) {
   const int t = threadIdx.x;
   const Chunk ch = chunk_of(n, NT, t);
   const int k = ch.k;  // 2 <= k <= K for active threads
   const int f = ch.first;
-  const bool act = t < ch.active;
-  const double* lo = P.lot + o;
-  const double* di = P.dit + o;
-  const double* up = P.upt + o;
-  const double* rhs = P.hba + o;
-  double y[K], v[K], w[K];
-  if (act) {
+  if (t < ch.active) {
     // every row of the chunk is loaded before the elimination starts (the
     // K loads of one lane share cache lines; issued together they are
     // served by one fetch)
@@ -898,12 +931,55 @@ __global__ __launch_bounds__(NT) void k_adj_r2(AdjSolveArgs P) {
     S.a[2 * t + 1] = R1[0]; S.b[2 * t + 1] = R1[1]; S.c[2 * t + 1] = R1[2];
     S.d0[2 * t + 1] = R1[3]; S.d1[2 * t + 1] = 0.0; S.d2[2 * t + 1] = 0.0;
   }
-  __syncthreads();
+  return ch;
+}
+
+// Unknowns of a thread's chunk from the system's end values z0, zl (after
+// the level-1 solve): chunk ends from the level-1 spikes, interiors from
+// the chunk spikes.
+template <int NT, int K>
+__device__ __forceinline__ void reg_chunk_write(const Lds<NT>& S, const Chunk& ch,
+                                                double* __restrict__ x, double z0, double zl,
+                                                const double (&y)[K], const double (&v)[K],
+                                                const double (&w)[K]) {
+  const int t = threadIdx.x;
+  if (t >= ch.active) return;
+  const int k = ch.k, f = ch.first;
   const int n1 = 2 * ch.active;
-  level1_interior_fast<NT>(S, n1);
-  if (t == 0) {
+  const int j0 = 2 * t, j1 = 2 * t + 1;
+  const double zf = (j0 == 0) ? z0 : S.d0[j0] + S.d1[j0] * z0 + S.d2[j0] * zl;
+  const double zb = (j1 == n1 - 1) ? zl : S.d0[j1] + S.d1[j1] * z0 + S.d2[j1] * zl;
+  x[f] = zf;
+  x[f + k - 1] = zb;
+#pragma unroll
+  for (int i = 1; i < K - 1; ++i)
+    if (i <= k - 2) x[f + i] = y[i] + v[i] * zf + w[i] * zb;
+}
+
+// Register-resident solve of one instance of n <= NT * K rows (chunks in
+// registers, level-1 PCR in LDS stopping once every coupling is below 2^-66
+// of its diagonal, 2x2 end solve, cyclic when periodic).  Longer instances
+// use the global-scratch solve.
+template <int NT, int K>
+__global__ __launch_bounds__(NT) void k_adj_r2(AdjSolveArgs P) {
+  __shared__ Lds<NT> S;
+  const InstDesc D = P.inst[blockIdx.x];
+  if (!(P.dt[blockIdx.x] > 0.0)) return;  // frozen: lam is not used
+  const int64_t o = D.off;
+  const int n = D.n;
+  const bool cyclic = D.bc == 0;
+  if (n > NT * K) {
+    wg_tri_solve<NT>(S, P.lot + o, P.dit + o, P.upt + o, P.hba + o, P.lam + o, n, cyclic,
+                     P.scp + o, P.sy + o, P.sv + o, P.sw + o);
+    return;
+  }
+  double y[K], v[K], w[K];
+  const Chunk ch = reg_chunk_elim<NT, K>(S, P.lot + o, P.dit + o, P.upt + o, P.hba + o, n, y, v, w);
+  __syncthreads();
+  level1_interior_fast<NT>(S, 2 * ch.active);
+  if (threadIdx.x == 0) {
     double R0[4], R1[4], z0, zl;
-    tile_rows<NT>(S, n1, R0, R1);
+    tile_rows<NT>(S, 2 * ch.active, R0, R1);
     if (!cyclic) {
       R0[0] = 0.0;
       R1[2] = 0.0;
@@ -913,18 +989,72 @@ __global__ __launch_bounds__(NT) void k_adj_r2(AdjSolveArgs P) {
     S.s[1] = zl;
   }
   __syncthreads();
-  if (act) {
-    const double z0 = S.s[0], zl = S.s[1];
-    const int j0 = 2 * t, j1 = 2 * t + 1;
-    const double zf = (j0 == 0) ? z0 : S.d0[j0] + S.d1[j0] * z0 + S.d2[j0] * zl;
-    const double zb = (j1 == n1 - 1) ? zl : S.d0[j1] + S.d1[j1] * z0 + S.d2[j1] * zl;
-    double* x = P.lam + o;
-    x[f] = zf;
-    x[f + k - 1] = zb;
-#pragma unroll
-    for (int i = 1; i < K - 1; ++i)
-      if (i <= k - 2) x[f + i] = y[i] + v[i] * zf + w[i] * zb;
+  reg_chunk_write<NT, K>(S, ch, P.lam + o, S.s[0], S.s[1], y, v, w);
+}
+
+// ---------------------------------------------------------------------------
+// Exact tiled solve of a batch of tridiagonal systems held in global rows
+// (lo[i] x[i-1] + di[i] x[i] + up[i] x[i+1] = rhs[i]; cyclic when periodic,
+// end couplings already zero when not): each tile of at most NT * K rows is
+// eliminated in registers.  REDUCE: the tile writes its two reduced rows
+// (first and last unknown, coupled to the neighbouring tiles) for the
+// per-instance reduced solve.  Otherwise the tile takes its end unknowns
+// from that solve (or solves them itself when it is the whole system) and
+// writes its solution.
+// ---------------------------------------------------------------------------
+struct TriArgs {
+  const InstDesc* __restrict__ inst;
+  const TileDesc* __restrict__ tiles;
+  const double* __restrict__ dt;
+  const double* __restrict__ lo;
+  const double* __restrict__ di;
+  const double* __restrict__ up;
+  const double* __restrict__ rhs;
+  double* __restrict__ x;
+  double* __restrict__ rlo;  // reduced rows (2 per tile at red_off + 2 tidx)
+  double* __restrict__ rdi;
+  double* __restrict__ rup;
+  double* __restrict__ rrhs;
+  const double* __restrict__ rx;  // reduced solution
+};
+
+template <int NT, int K, bool REDUCE>
+__global__ __launch_bounds__(NT) void k_tri_tiles(TriArgs P) {
+  __shared__ Lds<NT> S;
+  const TileDesc td = P.tiles[blockIdx.x];
+  const InstDesc I = P.inst[td.inst];
+  if (!(P.dt[td.inst] > 0.0)) return;  // frozen: x is not used
+  const int64_t o = I.off + td.start;
+  double y[K], v[K], w[K];
+  const Chunk ch = reg_chunk_elim<NT, K>(S, P.lo + o, P.di + o, P.up + o, P.rhs + o, td.len, y,
+                                         v, w);
+  __syncthreads();
+  level1_interior_fast<NT>(S, 2 * ch.active);
+  if (threadIdx.x == 0) {
+    double R0[4], R1[4];
+    tile_rows<NT>(S, 2 * ch.active, R0, R1);
+    if (REDUCE) {
+      const int r = I.red_off + 2 * td.tidx;
+      P.rlo[r] = R0[0]; P.rdi[r] = R0[1]; P.rup[r] = R0[2]; P.rrhs[r] = R0[3];
+      P.rlo[r + 1] = R1[0]; P.rdi[r + 1] = R1[1]; P.rup[r + 1] = R1[2]; P.rrhs[r + 1] = R1[3];
+    } else if (I.ntiles == 1) {
+      const bool cyclic = I.bc == 0;
+      if (!cyclic) {
+        R0[0] = 0.0;
+        R1[2] = 0.0;
+      }
+      double z0, zl;
+      solve_ends(R0, R1, cyclic, z0, zl);
+      S.s[0] = z0;
+      S.s[1] = zl;
+    } else {
+      S.s[0] = P.rx[I.red_off + 2 * td.tidx];
+      S.s[1] = P.rx[I.red_off + 2 * td.tidx + 1];
+    }
   }
+  if (REDUCE) return;
+  __syncthreads();
+  reg_chunk_write<NT, K>(S, ch, P.x + o, S.s[0], S.s[1], y, v, w);
 }
 
 }  // namespace hsgn

@@ -204,4 +204,194 @@ __global__ __launch_bounds__(NT) void k_speed_ex(const InstDesc* __restrict__ in
   }
 }
 
+// ---------------------------------------------------------------------------
+// Standard SGN equations, elliptic-hyperbolic form (Sec. 4.3-4.4), flat
+// bottom, Heun's method.  Per stage: k_sgn_rows assembles the tridiagonal
+// system of phi,
+//   h_i phi_i - (H_{i+1/2}(phi_{i+1} - phi_i) - H_{i-1/2}(phi_i - phi_{i-1})) / (3 dx^2)
+//     = h*_i = -(G_{i+1} - G_{i-1}) / (6 dx^3),
+//   H_{i+1/2} = (h_i^3 + h_{i+1}^3) / 2,
+//   G_j = g h_j^3 (h_{j+1} - 2 h_j + h_{j-1}) + (h_j^3 / 2)(u_{j+1} - u_{j-1})^2,
+// (zero-gradient phi at transmissive ends; cyclic when periodic); the
+// batched tridiagonal solve gives phi; k_sgn_update applies
+//   L_h = -Dhat_x(q),  L_q = -Dhat_x(q u + g h^2 / 2) + h phi
+// with Rusanov fluxes (speed max(|u| + sqrt(g h))) on the linear
+// reconstruction of (h, q).  m and W are carried unchanged.
+// ---------------------------------------------------------------------------
+struct SgnArgs {
+  const double* __restrict__ un_h;  // U^n (stage 2; also the m, W carried along)
+  const double* __restrict__ un_q;
+  const double* __restrict__ un_m;
+  const double* __restrict__ un_W;
+  const double* __restrict__ in_h;  // stage operand
+  const double* __restrict__ in_q;
+  double* __restrict__ o_h;         // stage output
+  double* __restrict__ o_q;
+  double* __restrict__ o_m;
+  double* __restrict__ o_W;
+  double* __restrict__ lo;          // rows of the phi system (k_sgn_rows)
+  double* __restrict__ di;
+  double* __restrict__ up;
+  double* __restrict__ rhs;
+  const double* __restrict__ phi;   // solution (k_sgn_update)
+  const InstDesc* __restrict__ inst;
+  const TileDesc* __restrict__ tiles;
+  const double* __restrict__ dt;
+  unsigned long long* __restrict__ smax;
+  unsigned long long* __restrict__ umax;
+  int32_t* __restrict__ status;
+};
+
+// Stage h and q of tile cells -2 .. len + 1 (wrapped or copied ghosts).
+template <int NT, int SL>
+__device__ __forceinline__ void sgn_stage(double (*X)[SL], const double* __restrict__ h,
+                                          const double* __restrict__ q, const InstDesc& I,
+                                          const TileDesc& td) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < (SL + NT - 1) / NT; ++r) {
+    const int si = t + r * NT;
+    if (si < td.len + 4) {
+      int c = td.start - 2 + si;
+      if (I.bc == 0) c = c < 0 ? c + I.n : (c >= I.n ? c - I.n : c);
+      else c = c < 0 ? 0 : (c > I.n - 1 ? I.n - 1 : c);
+      X[0][si] = h[I.off + c];
+      X[1][si] = q[I.off + c];
+    }
+  }
+}
+
+template <int NT, int KX>
+__global__ __launch_bounds__(NT) void k_sgn_rows(SgnArgs A) {
+  constexpr int TL = NT * KX;
+  constexpr int SL = TL + 4;
+  __shared__ double X[2][SL];   // h, q; staged index s <-> tile cell s - 2
+  __shared__ double GH[2][SL];  // G_j and h_j^3 at staged cells 1 .. len + 2
+  const TileDesc td = A.tiles[blockIdx.x];
+  const InstDesc I = A.inst[td.inst];
+  if (!(A.dt[td.inst] > 0.0)) return;  // frozen: the solve skips the instance
+  const int t = threadIdx.x, len = td.len;
+  sgn_stage<NT, SL>(X, A.in_h, A.in_q, I, td);
+  __syncthreads();
+  const double g = I.g;
+  bool bad = false;
+#pragma unroll
+  for (int r = 0; r < (SL + NT - 1) / NT; ++r) {
+    const int j = t + r * NT;
+    if (j >= 1 && j <= len + 2) {
+      const double hj = X[0][j];
+      const double h3 = hj * hj * hj;
+      const double du = X[1][j + 1] / X[0][j + 1] - X[1][j - 1] / X[0][j - 1];
+      GH[0][j] = g * h3 * (X[0][j + 1] - 2.0 * hj + X[0][j - 1]) + 0.5 * h3 * du * du;
+      GH[1][j] = h3;
+      bad |= !(hj > 0.0);
+    }
+  }
+  __syncthreads();
+  const double c3 = 1.0 / (3.0 * I.dx * I.dx);
+  const double c6 = 1.0 / (6.0 * I.dx * I.dx * I.dx);
+  const int64_t base = I.off + td.start;
+#pragma unroll
+  for (int r = 0; r < KX; ++r) {
+    const int i = t + r * NT;
+    if (i < len) {
+      const int k = i + 2;
+      const double Hm = 0.5 * (GH[1][k - 1] + GH[1][k]);
+      const double Hp = 0.5 * (GH[1][k] + GH[1][k + 1]);
+      double l = -c3 * Hm, u = -c3 * Hp, d = X[0][k] + c3 * (Hm + Hp);
+      const double rh = -(GH[0][k + 1] - GH[0][k - 1]) * c6;
+      if (I.bc != 0) {  // zero-gradient phi at a transmissive end
+        const int c = td.start + i;
+        if (c == 0) { d += l; l = 0.0; }
+        if (c == I.n - 1) { d += u; u = 0.0; }
+      }
+      A.lo[base + i] = l;
+      A.di[base + i] = d;
+      A.up[base + i] = u;
+      A.rhs[base + i] = rh;
+    }
+  }
+  if (bad) atomicOr(&A.status[td.inst], kFlagNonPhys);
+}
+
+template <int NT, int KX, int STAGE>
+__global__ __launch_bounds__(NT) void k_sgn_update(SgnArgs A) {
+  constexpr int TL = NT * KX;
+  constexpr int SL = TL + 4;
+  __shared__ double X[2][SL];
+  __shared__ double F[2][TL + 1];  // face fluxes of h and q
+  const TileDesc td = A.tiles[blockIdx.x];
+  const InstDesc I = A.inst[td.inst];
+  const double dt = A.dt[td.inst];
+  const int t = threadIdx.x, len = td.len;
+  const int64_t base = I.off + td.start;
+  if (!(dt > 0.0)) {  // frozen instance: the state stays
+    for (int i = t; i < len; i += NT) {
+      A.o_h[base + i] = A.un_h[base + i];
+      A.o_q[base + i] = A.un_q[base + i];
+      if (STAGE == 2) {
+        A.o_m[base + i] = A.un_m[base + i];
+        A.o_W[base + i] = A.un_W[base + i];
+      }
+    }
+    return;
+  }
+  sgn_stage<NT, SL>(X, A.in_h, A.in_q, I, td);
+  __syncthreads();
+  const double g = I.g, idx = 1.0 / I.dx;
+  bool bad = false;
+#pragma unroll
+  for (int r = 0; r <= KX; ++r) {
+    const int e = t + r * NT;
+    if (e <= len) {
+      const double hL = X[0][e + 1] + 0.25 * (X[0][e + 2] - X[0][e]);
+      const double hR = X[0][e + 2] - 0.25 * (X[0][e + 3] - X[0][e + 1]);
+      const double qL = X[1][e + 1] + 0.25 * (X[1][e + 2] - X[1][e]);
+      const double qR = X[1][e + 2] - 0.25 * (X[1][e + 3] - X[1][e + 1]);
+      bad |= !(hL > 0.0) || !(hR > 0.0);
+      const double uL = qL / hL, uR = qR / hR;
+      const double al = fmax(fabs(uL) + sqrt(g * hL), fabs(uR) + sqrt(g * hR));
+      F[0][e] = 0.5 * (qL + qR - al * (hR - hL));
+      F[1][e] = 0.5 * (qL * uL + 0.5 * g * hL * hL + qR * uR + 0.5 * g * hR * hR - al * (qR - qL));
+    }
+  }
+  __syncthreads();
+  double smx = 0.0, umx = 0.0;
+#pragma unroll
+  for (int r = 0; r < KX; ++r) {
+    const int i = t + r * NT;
+    if (i < len) {
+      const int k = i + 2;
+      const double h = X[0][k];
+      const double Lh = -(F[0][i + 1] - F[0][i]) * idx;
+      const double Lq = -(F[1][i + 1] - F[1][i]) * idx + h * A.phi[base + i];
+      double hn = h + dt * Lh, qn = X[1][k] + dt * Lq;
+      if (STAGE == 2) {
+        hn = 0.5 * (A.un_h[base + i] + hn);
+        qn = 0.5 * (A.un_q[base + i] + qn);
+        A.o_m[base + i] = A.un_m[base + i];
+        A.o_W[base + i] = A.un_W[base + i];
+        const double un = fabs(qn / hn);
+        smx = fmax(smx, un + sqrt(g * hn));
+        umx = fmax(umx, un);
+      }
+      bad |= !(hn > 0.0) || !isfinite(hn) || !isfinite(qn);
+      A.o_h[base + i] = hn;
+      A.o_q[base + i] = qn;
+    }
+  }
+  if (STAGE == 2) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      smx = fmax(smx, __shfl_xor(smx, off));
+      umx = fmax(umx, __shfl_xor(umx, off));
+    }
+    if ((t & 63) == 0 && smx > 0.0) {
+      atomicMax(&A.smax[td.inst], (unsigned long long)__double_as_longlong(smx));
+      atomicMax(&A.umax[td.inst], (unsigned long long)__double_as_longlong(umx));
+    }
+  }
+  if (bad) atomicOr(&A.status[td.inst], kFlagNonPhys);
+}
+
 }  // namespace hsgn

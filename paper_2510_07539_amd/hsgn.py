@@ -18,11 +18,11 @@ LIB_PATH = os.path.join(HERE, "libhsgn.so")
 HSGN_OK, HSGN_EINVAL, HSGN_EHIP, HSGN_ENONPHYS, HSGN_ENONCOERCIVE, HSGN_ENOMEM = 0, -1, -2, -3, -4, -5
 FLAG_NONPHYS, FLAG_NONCOERCIVE = 1, 2
 KERNEL_KINDS = ("dt", "reduce1", "rsolve1", "stage1", "reduce2", "rsolve2", "stage2", "win1", "win2",
-                "ex1", "ex2")
+                "ex1", "ex2", "sgn_rows", "sgn_solve", "sgn_update")
 SOLVER_AUTO, SOLVER_EXACT, SOLVER_AUTO_SMALL = 0, 1, 2
 SOLVERS = {"auto": SOLVER_AUTO, "exact": SOLVER_EXACT, "auto_small": SOLVER_AUTO_SMALL}
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
-SCHEME_SEMI_IMPLICIT, SCHEME_EXPLICIT = 0, 1
+SCHEME_SEMI_IMPLICIT, SCHEME_EXPLICIT, SCHEME_SGN = 0, 1, 2
 
 
 class HsgnParams(C.Structure):

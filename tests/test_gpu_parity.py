@@ -158,6 +158,28 @@ def test_graph_run_matches_step_bitwise():
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_graph_cached_across_set_state(scheme):
+    """Loading a state whose plan has the same launch configuration keeps the
+    captured graph; its replays match a fresh context's eager steps."""
+    Solver = _solver()
+    wl = WL.concat("mix", [WL.solitary(N=3000, L=750.0, t_end=0.0),
+                           WL.solitary(N=700, L=175.0, lam=1000.0, t_end=0.0)])
+    kw = dict(scheme=scheme, cfl=0.4 if scheme else None)
+    s1 = Solver.from_workload(wl, **kw)
+    s1.run(20, block=10)
+    s1.set_state(*[torch.from_numpy(a).cuda() for a in wl.state()])
+    s1.run(30, block=10)
+    s2 = Solver.from_workload(wl, **kw)
+    s2.step(30)
+    (a, ta), (b, tb) = s1.get_state(), s2.get_state()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    assert torch.equal(ta, tb)
+    s1.close()
+    s2.close()
+
+
 @pytest.mark.parametrize("solver", SOLVERS)
 def test_edge_sizes_and_frozen_instances(solver):
     parts = []
@@ -406,6 +428,71 @@ def test_explicit_batched_flat_full_size_sampled():
     insts = list(range(0, wl.n_inst, wl.n_inst // 16))
     compare(wl, 20, use_run=True, block=10, insts=insts, label="batched flat full size",
             scheme=EXS, cfl=CFL_EX)
+
+
+# ---------------------------------------------------------------------------
+# Standard SGN equations, elliptic-hyperbolic form (Sec. 4.3-4.4), flat
+# bottom, Heun's method, CFL 0.9 on |u| + sqrt(g h)
+# ---------------------------------------------------------------------------
+SGNS = 2  # scheme: standard SGN
+
+
+def _sgn_mix():
+    a = WL.solitary(N=800, t_end=0.0)                               # periodic, register solve
+    b = WL.solitary(N=5001, L=1250.25, t_end=0.0)                   # periodic, > 4096 rows
+    c = WL.batched_flat(n_inst=6, seed=19, n_lo=513, n_hi=9000)      # transmissive, mixed
+    return WL.concat("sgn mix", [a, b, c])
+
+
+def test_sgn_parity_mix():
+    compare(_sgn_mix(), 40, label="SGN Heun", scheme=SGNS)
+
+
+def test_sgn_edge_sizes():
+    parts = []
+    for n in (4, 5, 7, 1023, 1024, 1025, 4096, 4097):
+        for bc in (0, 1):
+            parts.append(WL.solitary(N=n, L=n * 0.25, t_end=0.0, bc=bc))
+    compare(WL.concat("sgn edge sizes", parts), 20, label="SGN sizes", scheme=SGNS)
+
+
+def test_sgn_graph_replay_equals_eager_and_t_end():
+    Solver = _solver()
+    wl = _sgn_mix()
+    s1 = Solver.from_workload(wl, scheme=SGNS)
+    s1.step(40)
+    s2 = Solver.from_workload(wl, scheme=SGNS)
+    s2.run(40, block=20)
+    (a, ta), (b, tb) = s1.get_state(), s2.get_state()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    assert torch.equal(ta, tb)
+    s1.close()
+    s2.close()
+    compare(WL.solitary(N=600, L=150.0, t_end=0.3), 40, label="SGN to t_end", scheme=SGNS)
+
+
+def test_sgn_rejects_bed_adjoint_and_autotune():
+    from paper_2510_07539_amd.hsgn import HsgnError
+    Solver = _solver()
+    with pytest.raises(HsgnError):
+        Solver.from_workload(WL.batched_bar(n_inst=2, seed=1, n_lo=600, n_hi=900), scheme=SGNS)
+    wl = WL.solitary(N=200, L=50.0, t_end=0.0)
+    wl.dt_fixed[:] = 0.01
+    s = Solver.from_workload(wl, scheme=SGNS)
+    with pytest.raises(HsgnError):
+        s.autotune()
+    z = torch.from_numpy(wl.h).cuda()
+    with pytest.raises(HsgnError):
+        s.adjoint(3, 2, torch.zeros((1, 1), dtype=torch.int32), torch.zeros((1, 3, 1)), z)
+    s.close()
+
+
+def test_sgn_batched_flat_full_size_sampled():
+    wl = WL.batched_flat()
+    insts = list(range(0, wl.n_inst, wl.n_inst // 16))
+    compare(wl, 20, use_run=True, block=10, insts=insts, label="SGN batched flat full size",
+            scheme=SGNS)
 
 
 def test_dam_break_full_run():
