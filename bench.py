@@ -27,15 +27,16 @@ CSRC = [os.path.join(ROOT, "paper_2510_07539_amd", "csrc", f)
         for f in ("hsgn_kernels.hpp", "hsgn_window.hpp")]
 
 # HBM traffic of the dominant kernel measured with rocprofv3 --pmc (FETCH_SIZE
-# and WRITE_SIZE in separate runs, `bench.py --probe`), scaled by the same
-# counters on a plain 512 MiB copy (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0).
+# and WRITE_SIZE in separate runs, `bench.py --probe --solver auto_small`),
+# scaled by the same counters on a plain 512 MiB copy (FETCH_SIZE x 1.9998,
+# WRITE_SIZE x 1.0).
 # Keyed by the hash of the kernel's sources; reported as null once they change.
 TRAFFIC = {
-    "cf6a4e07ace53dc2": {"kernel": "win2", "workload": "batched_bar",
-                         "fetch_bytes": 4594529921, "write_bytes": 3170134763,
-                         "bytes_per_launch": 7764664683},
+    "c32ef263ae984a9e": {"kernel": "win2", "workload": "batched_bar",
+                         "solver": "auto_small",
+                         "fetch_bytes": 2947989177, "write_bytes": 1617624064,
+                         "bytes_per_launch": 4565613241},
 }
-
 
 def src_hash():
     h = hashlib.sha256()
@@ -348,7 +349,9 @@ def main():
     h = src_hash()
     tr = TRAFFIC.get(h)
     traffic = None
-    if tr and tr.get("kernel") == dom and tr.get("workload") == args.workload:
+    solver_used = tuned["kept"] if tuned else args.solver
+    if (tr and tr.get("kernel") == dom and tr.get("workload") == args.workload and
+            tr.get("solver") == solver_used):
         traffic = tr["bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
