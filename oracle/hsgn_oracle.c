@@ -37,9 +37,10 @@
  * a Rusanov flux like the other three (the print differences q centrally),
  * and the Rusanov speed is max(|u| + c) over the two face states with the
  * hSGN celerity c^2 = g h + (lambda/3) (eta/h)^2 (eq. hSGN_c), the
- * eigenvalues of the system it treats explicitly (the print has |u|).  As
- * printed, one step at rest grows by a factor 1.011 (lambda = 100) to 1.029
- * (lambda = 1000) at CFL 0.4; the pressure terms stay central as printed.
+ * eigenvalues of the system it treats explicitly (the print has |u|).  At
+ * rest and CFL 0.4 one step as printed grows by a factor 1.0014 (lambda =
+ * 100) and 1.0012 (lambda = 1000); with speed |u| + c but the central mass
+ * flux by 1.011 and 1.029.  The pressure terms stay central as printed.
  *
  * The standard SGN equations in the elliptic-hyperbolic form of Sec. 4.3
  * (eq. SGN_standard; scheme = 2, flat bottom, lambda unused) are here as the
