@@ -230,8 +230,10 @@ int hsgn_step_timed(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_coun
  * hsgn_set_state); the reverse stages solve the transposed depth system
  * exactly (no truncation).
  * On return the state is the state after nsteps steps and t is reset to 0.
- * The adjoint workspace (22 + 8 K doubles per cell, plus 4 (nsteps/K + 1)
- * doubles per cell of checkpoints) is kept until hsgn_destroy.
+ * The recompute of a segment runs on a second stream of the library while
+ * the previous segment is swept in reverse (two tape buffers).  The adjoint
+ * workspace (22 + 16 K doubles per cell, plus 4 (nsteps/K + 1) doubles per
+ * cell of checkpoints) is kept until hsgn_destroy.
  * Synchronises the stream once, after the initial state. */
 int hsgn_adjoint(hsgn_ctx* ctx, int32_t nsteps, int32_t K, int32_t n_gauge,
                  const int32_t* d_gauge, const double* d_target, const double* d_zeta0,

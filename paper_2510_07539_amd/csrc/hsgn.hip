@@ -77,6 +77,7 @@ struct hsgn_ctx {
   double* const* io_u1 = nullptr;
   double* const* io_out = nullptr;
   bool io_stage1_only = false;  // the step stops after stage 1 (U^(1) only)
+  bool io_skip_dt = false;      // the step reuses the current dt (fixed-step recompute)
   int order = 2;                // 2: two-stage IMEX step; 1: one first-order stage
   int scheme = HSGN_SCHEME_SEMI_IMPLICIT;  // or the explicit Heun step
   TileDesc* d_xtiles = nullptr;  // tiles of the explicit and SGN kernels (kExTile cells)
@@ -115,12 +116,16 @@ struct hsgn_ctx {
     int K = 0, nseg = 0;
     int64_t nres = 0;
     double* sys = nullptr;     // 9 x ncell: transposed rows, rhs, lam, solver scratch
-    double* tape = nullptr;    // K x 8 x ncell  (U^n, U^(1) per step)
+    double* tape = nullptr;    // 2 x K x 8 x ncell (U^n, U^(1) per step; two segments)
     double* ckpt = nullptr;    // (nseg + 1) x 4 x ncell
     double* res = nullptr;     // n_inst x nsteps x n_gauge residuals
     double* st = nullptr;      // 12 x ncell adjoint states + 1 x ncell bed adjoint
     hsgn::adj::TileA* tiles = nullptr;
     int ntiles = 0;
+    // the recompute of segment s - 1 runs on its own stream while the
+    // reverse sweep of segment s runs on the library's stream
+    hipStream_t rstream = nullptr;
+    hipEvent_t ev_fwd = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
   } adj;
 };
 
@@ -175,6 +180,11 @@ void free_all(hsgn_ctx* c) {
   for (double* p : ap)
     if (p) hipFree(p);
   if (c->adj.tiles) hipFree(c->adj.tiles);
+  if (c->adj.rstream) hipStreamDestroy(c->adj.rstream);
+  hipEvent_t aev[5] = {c->adj.ev_fwd, c->adj.ev_rec[0], c->adj.ev_rec[1], c->adj.ev_rev[0],
+                       c->adj.ev_rev[1]};
+  for (hipEvent_t e : aev)
+    if (e) hipEventDestroy(e);
   if (c->ev_in) hipEventDestroy(c->ev_in);
   if (c->ev_out) hipEventDestroy(c->ev_out);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
@@ -264,10 +274,12 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
     }
   };
   const int nb = (c->n_inst + 255) / 256;
-  mark(HSGN_K_DT, true);
-  hipLaunchKernelGGL(hsgn::k_dt, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_inst, c->d_dt,
-                     c->d_t, c->d_smax, c->d_umax, c->d_status);
-  mark(HSGN_K_DT, false);
+  if (!c->io_skip_dt) {
+    mark(HSGN_K_DT, true);
+    hipLaunchKernelGGL(hsgn::k_dt, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_inst, c->d_dt,
+                       c->d_t, c->d_smax, c->d_umax, c->d_status);
+    mark(HSGN_K_DT, false);
+  }
   if (c->scheme == HSGN_SCHEME_SGN) {
     // Heun on the SGN operator: rows of the phi system, batched tridiagonal
     // solve (one workgroup per instance), flux update with the source h phi
@@ -1182,9 +1194,17 @@ int adj_alloc(hsgn_ctx* c, int K, int nseg, int64_t nres, bool grad) {
     if (a.tape) hipFree(a.tape);
     a.tape = nullptr;
     a.K = 0;
-    int rc = dmalloc(c, &a.tape, (size_t)K * 8 * nc);
+    int rc = dmalloc(c, &a.tape, (size_t)2 * K * 8 * nc);
     if (rc) return rc;
     a.K = K;
+  }
+  if (!a.rstream) {
+    HIPCHK(c, hipStreamCreateWithFlags(&a.rstream, hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&a.ev_fwd, hipEventDisableTiming));
+    for (int i = 0; i < 2; ++i) {
+      HIPCHK(c, hipEventCreateWithFlags(&a.ev_rec[i], hipEventDisableTiming));
+      HIPCHK(c, hipEventCreateWithFlags(&a.ev_rev[i], hipEventDisableTiming));
+    }
   }
   if (nseg > a.nseg) {
     if (a.ckpt) hipFree(a.ckpt);
@@ -1249,7 +1269,10 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   const unsigned nbi = (unsigned)((c->n_inst + 255) / 256);
   double** U = nullptr;
   auto ckpt = [&](int k, int f) { return a.ckpt + ((size_t)k * 4 + f) * nc; };
-  auto tape = [&](int k, int f) { return a.tape + ((size_t)k * 8 + f) * nc; };
+  // two tape buffers: segment s uses buffer s % 2
+  auto tape = [&](int s, int k, int f) {
+    return a.tape + (((size_t)(s % 2) * a.K + k) * 8 + f) * nc;
+  };
   double* AS[4];
   double* A1[4];
   double* ANP[4];
@@ -1282,9 +1305,9 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
       const int k = s - s_last, ksl = nsteps - s_last;
       double *un[4], *u1[4], *out[4];
       for (int f = 0; f < 4; ++f) {
-        un[f] = k == 0 ? ckpt(nseg - 1, f) : tape(k, f);
-        u1[f] = tape(k, 4 + f);
-        out[f] = (k + 1 < ksl) ? tape(k + 1, f) : ckpt(nseg, f);
+        un[f] = k == 0 ? ckpt(nseg - 1, f) : tape(nseg - 1, k, f);
+        u1[f] = tape(nseg - 1, k, 4 + f);
+        out[f] = (k + 1 < ksl) ? tape(nseg - 1, k + 1, f) : ckpt(nseg, f);
       }
       rc = enqueue_step_io(c, un, u1, out);
       hnew = out[0];
@@ -1333,35 +1356,55 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   Q.sv = sysa(7);
   Q.sw = sysa(8);
   const dim3 gt(a.ntiles), bt(kAdjNT);
+  // Recompute of a segment from its checkpoint on the recompute stream,
+  // keeping U^n and U^(1) of every step on the segment's tape (the steps
+  // write there directly; dt is fixed, so the steps reuse it).  The last
+  // step needs only U^(1): its U^{n+1} is the next checkpoint.
+  auto recompute = [&](int seg) -> int {
+    const int s0 = seg * K, ks = std::min(K, nsteps - s0);
+    hipStream_t main_stream = c->stream;
+    c->stream = a.rstream;
+    c->io_skip_dt = true;
+    int r = HSGN_OK;
+    for (int k = 0; k < ks && r == HSGN_OK; ++k) {
+      double *un[4], *u1[4], *nx[4];
+      for (int f = 0; f < 4; ++f) {
+        un[f] = k == 0 ? ckpt(seg, f) : tape(seg, k, f);
+        u1[f] = tape(seg, k, 4 + f);
+        nx[f] = k + 1 < ks ? tape(seg, k + 1, f) : nullptr;
+      }
+      r = enqueue_step_io(c, un, u1, k + 1 < ks ? nx : nullptr);
+    }
+    c->io_skip_dt = false;
+    c->stream = main_stream;
+    return r;
+  };
+  // the recompute stream starts once the forward pass (checkpoints, dt) is done
+  HIPCHK(c, hipEventRecord(a.ev_fwd, c->stream));
+  HIPCHK(c, hipStreamWaitEvent(a.rstream, a.ev_fwd, 0));
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int s0 = seg * K;
     const int ks = std::min(K, nsteps - s0);
-    // recompute the segment from its checkpoint, keeping U^n and U^(1) of
-    // every step on the tape (the steps write there directly)
-    double* cks[4] = {ckpt(seg, 0), ckpt(seg, 1), ckpt(seg, 2), ckpt(seg, 3)};
-    auto un_of = [&](int k, int f) { return k == 0 ? cks[f] : tape(k, f); };
-    for (int k = 0; k < ks && seg != nseg - 1; ++k) {
-      double* un[4] = {un_of(k, 0), un_of(k, 1), un_of(k, 2), un_of(k, 3)};
-      double* u1[4] = {tape(k, 4), tape(k, 5), tape(k, 6), tape(k, 7)};
-      // the last step needs only U^(1): its U^{n+1} is the next checkpoint
-      double* nx[4];
-      double* const* out = nullptr;
-      if (k + 1 < ks) {
-        for (int f = 0; f < 4; ++f) nx[f] = tape(k + 1, f);
-        out = nx;
-      }
-      rc = enqueue_step_io(c, un, u1, out);
+    // the previous segment is recomputed while this one is swept in reverse;
+    // its tape buffer was last read by the reverse sweep of segment seg + 1
+    if (seg >= 1) {
+      if (seg + 1 <= nseg - 1) HIPCHK(c, hipStreamWaitEvent(a.rstream, a.ev_rev[(seg + 1) % 2], 0));
+      rc = recompute(seg - 1);
       if (rc) return rc;
+      HIPCHK(c, hipEventRecord(a.ev_rec[(seg - 1) % 2], a.rstream));
     }
+    if (seg < nseg - 1) HIPCHK(c, hipStreamWaitEvent(c->stream, a.ev_rec[seg % 2], 0));
+    double* cks[4] = {ckpt(seg, 0), ckpt(seg, 1), ckpt(seg, 2), ckpt(seg, 3)};
+    auto un_of = [&](int k, int f) { return k == 0 ? cks[f] : tape(seg, k, f); };
     for (int k = ks - 1; k >= 0; --k) {
       hipLaunchKernelGGL(k_gauge_adj, dim3(nbi), dim3(256), 0, c->stream, c->n_inst, c->d_inst,
                          ng, d_gauge, nsteps, s0 + k, a.res, AS[0]);
       for (int f = 0; f < 4; ++f) {
         P.un[f] = un_of(k, f);
-        P.u1[f] = tape(k, 4 + f);
+        P.u1[f] = tape(seg, k, 4 + f);
       }
       // stage 2: hbar is the depth of U^{n+1}
-      P.hbar = (k + 1 < ks) ? tape(k + 1, 0) : ckpt(seg + 1, 0);
+      P.hbar = (k + 1 < ks) ? tape(seg, k + 1, 0) : ckpt(seg + 1, 0);
       for (int f = 0; f < 4; ++f) {
         P.abar[f] = AS[f];
         P.out1[f] = A1[f];
@@ -1371,13 +1414,14 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
       hipLaunchKernelGGL((hsgn::k_adj_r2<512, 8>), dim3(c->n_inst), dim3(512), 0, c->stream, Q);
       hipLaunchKernelGGL((hsgn::k_adj_r3<kAdjNT, 2>), gt, bt, 0, c->stream, P);
       // stage 1: hbar is the depth of U^(1)
-      P.hbar = tape(k, 4);
+      P.hbar = tape(seg, k, 4);
       for (int f = 0; f < 4; ++f) P.abar[f] = A1[f];
       hipLaunchKernelGGL((hsgn::k_adj_r1<kAdjNT, 1>), gt, bt, 0, c->stream, P);
       hipLaunchKernelGGL((hsgn::k_adj_r2<512, 8>), dim3(c->n_inst), dim3(512), 0, c->stream, Q);
       hipLaunchKernelGGL((hsgn::k_adj_r3<kAdjNT, 1>), gt, bt, 0, c->stream, P);
       for (int f = 0; f < 4; ++f) std::swap(AS[f], ANP[f]);
     }
+    HIPCHK(c, hipEventRecord(a.ev_rev[seg % 2], c->stream));
   }
   // ---- gradients of the initial-state map; restore the final state
   hipLaunchKernelGGL(k_adj_surface, dim3(c->n_inst), dim3(256), 0, c->stream, c->d_inst, d_zeta0,
