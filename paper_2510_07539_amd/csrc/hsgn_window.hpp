@@ -247,6 +247,10 @@ struct WinLds {
     } nb;
   } u;
   double misc[16];
+  // inputs of the outer rows of truncated edges (window rows -1 and wl):
+  // U_E of five staged cells, the row's old state, the bed (side 0 left,
+  // side 1 right)
+  double side[2][4][5], sideo[2][4], sideb[2][5];
 };
 
 template <int NT, int K, bool BED, int STAGE>
@@ -393,6 +397,25 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   auto bed_row = [&](int i) -> double {
     return (BED && useb) ? L.u.st.b[spad(p0 + 2 + i)] : 0.0;
   };
+  // while field f is staged, the edge threads copy what the outer row of a
+  // truncated edge needs (staged cells i0 .. i0 + 4, i0 = 0 on the left and
+  // wl + 1 on the right) aside
+  auto save_side = [&](int f) {
+#pragma unroll
+    for (int sd = 0; sd < 2; ++sd) {
+      const bool need = sd == 0 ? (t == 0 && truncL) : (t == na - 1 && truncR);
+      if (!need) continue;
+      const int i0 = sd == 0 ? 0 : wd.wl + 1;
+#pragma unroll
+      for (int d = 0; d < 5; ++d) L.side[sd][f][d] = L.u.st.e[spad(i0 + d)];
+      const double* od = f == 0 ? L.u.st.ho : L.u.st.o;
+      L.sideo[sd][f] = STAGE == 1 ? L.u.st.e[spad(i0 + 2)] : od[spad(i0 + 2)];
+      if (f == 0) {
+#pragma unroll
+        for (int d = 0; d < 5; ++d) L.sideb[sd][d] = (BED && useb) ? L.u.st.b[spad(i0 + d)] : 0.0;
+      }
+    }
+  };
 
   load_round(0);
   put_round(0);
@@ -403,6 +426,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   double hL[K + 1], hR[K + 1], dmh[K + 1], hf[K + 2];
   unsigned badf = 0;  // bit f: a face depth of face f is not positive
   if (act) {
+    save_side(0);
     double xh[K + 4], xb[K + 4];
     read_x(xh, L.u.st.e);
     if (BED && useb && !kLean) {
@@ -438,6 +462,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   // round q: face velocities and Rusanov speeds, q-dagger
   double uL[K + 1], uR[K + 1], ap[K + 1], qd[K], eq[K];
   if (act) {
+    save_side(1);
     double xq[K + 4], Fq[K + 1];
     read_x(xq, L.u.st.e);
 #pragma unroll
@@ -466,6 +491,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   // here in the lean form
   double mdp[K], em[K];
   if (act) {
+    save_side(2);
     double xm[K + 4], xb[K + 4], Fm[K + 1];
     read_x(xm, L.u.st.e);
     if (BED && useb && kLean) {
@@ -511,6 +537,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   Rec rec[K];
   Rec recL, recR;
   if (act) {
+    save_side(3);
     double xw[K + 4], Fw[K + 1];
     read_x(xw, L.u.st.e);
 #pragma unroll
@@ -536,33 +563,28 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
     }
   }
   // outer neighbours (row -1 and row wl) of truncated edges: record of the
-  // row at staged index i0 + 2 from cells i0 .. i0 + 4, read from global
-  // memory with the staging's arithmetic
-  auto outer_record = [&](int i0, double& hrow) -> Rec {
+  // row from its five cells and its old state, as copied aside (side 0 left,
+  // side 1 right)
+  auto outer_record = [&](int sd, double& hrow) -> Rec {
     Cell c[5];
     double bb[5];
 #pragma unroll
     for (int d = 0; d < 5; ++d) {
-      const int64_t gi = base + cell_of(i0 + d);
-      if (STAGE == 1) {
-        c[d].h = A.un_h[gi];
-        c[d].q = A.un_q[gi];
-        c[d].m = A.un_m[gi];
-        c[d].W = A.un_W[gi];
-      } else {
-        c[d].h = kE0 * A.un_h[gi] + kE1 * A.u1_h[gi];
-        c[d].q = kE0 * A.un_q[gi] + kE1 * A.u1_q[gi];
-        c[d].m = kE0 * A.un_m[gi] + kE1 * A.u1_m[gi];
-        c[d].W = kE0 * A.un_W[gi] + kE1 * A.u1_W[gi];
-      }
-      bb[d] = (BED && useb) ? A.b[gi] : 0.0;
+      c[d].h = L.side[sd][0][d];
+      c[d].q = L.side[sd][1][d];
+      c[d].m = L.side[sd][2][d];
+      c[d].W = L.side[sd][3][d];
+      bb[d] = L.sideb[sd][d];
     }
     const Flux Fa = face_flux_fast<BED>(c[0], c[1], c[2], c[3], bb[0], bb[1], bb[2], bb[3], P.g,
                                         P.sl, bad);
     const Flux Fb = face_flux_fast<BED>(c[1], c[2], c[3], c[4], bb[1], bb[2], bb[3], bb[4], P.g,
                                         P.sl, bad);
-    const int64_t go = base + wrap_any(wd.ws + i0 - 1, n, bc);
-    const Cell o = STAGE == 1 ? load_old<1>(A, go) : load_old<2>(A, go);
+    Cell o;
+    o.h = L.sideo[sd][0];
+    o.q = L.sideo[sd][1];
+    o.m = L.sideo[sd][2];
+    o.W = L.sideo[sd][3];
     hrow = c[2].h;
     return cell_record_fast<BED>(c[2], o, Fa, Fb, bb[1], bb[2], bb[3], P, i2dx, bad, noncoer);
   };
@@ -585,7 +607,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       recR = last;
     } else {
       double hg;
-      recR = outer_record(wd.wl + 1, hg);
+      recR = outer_record(1, hg);
       L.misc[1] = hg;  // depth guess beyond the right edge
     }
   }
