@@ -19,17 +19,16 @@
 // One workgroup owns a tile of NT * KX cells of one instance.  The four
 // fields of the stage operand are staged through LDS with coalesced loads
 // (tile plus two ghost cells per side: periodic wrap or zero-order copy);
-// the face fluxes are computed once per face into LDS, then every cell is
-// updated from its two faces.  Threads take faces and cells at stride NT,
-// so every global load and store is coalesced.
+// every cell is updated from its two faces.  Threads take cells at stride
+// NT, so every global load and store is coalesced.
 #pragma once
 
 #include "hsgn_kernels.hpp"
 
 namespace hsgn {
 
-constexpr int kExNT = 512;               // threads per tile
-constexpr int kExK = 2;                  // cells per thread
+constexpr int kExNT = 256;               // threads per tile
+constexpr int kExK = 4;                  // cells per thread
 constexpr int kExTile = kExNT * kExK;    // cells per tile
 
 struct ExArgs {
@@ -53,12 +52,35 @@ struct ExArgs {
   int32_t* __restrict__ status;
 };
 
+// Rusanov fluxes (h, q u, m u, W u) of face e (between tile cells e - 1 and
+// e; stencil: staged cells e .. e + 3) at speed max(|u| + c).
+template <int SL>
+__device__ __forceinline__ void ex_face(const double (*X)[SL], int e, double g, double lam,
+                                        double F[4], bool& bad) {
+  double L[4], R[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    L[f] = X[f][e + 1] + 0.25 * (X[f][e + 2] - X[f][e]);
+    R[f] = X[f][e + 2] - 0.25 * (X[f][e + 3] - X[f][e + 1]);
+  }
+  bad |= !(L[0] > 0.0) || !(R[0] > 0.0);
+  const double iL = 1.0 / L[0], iR = 1.0 / R[0];
+  const double uL = L[1] * iL, uR = R[1] * iR;
+  const double eL = L[2] * iL * iL, eR = R[2] * iR * iR;
+  const double sL = fabs(uL) + sqrt(g * L[0] + (lam / 3.0) * eL * eL);
+  const double sR = fabs(uR) + sqrt(g * R[0] + (lam / 3.0) * eR * eR);
+  const double al = fmax(sL, sR);
+  F[0] = 0.5 * (L[1] + R[1] - al * (R[0] - L[0]));
+  F[1] = 0.5 * (L[1] * uL + R[1] * uR - al * (R[1] - L[1]));
+  F[2] = 0.5 * (L[2] * uL + R[2] * uR - al * (R[2] - L[2]));
+  F[3] = 0.5 * (L[3] * uL + R[3] * uR - al * (R[3] - L[3]));
+}
+
 template <int NT, int KX, int STAGE>
 __global__ __launch_bounds__(NT) void k_ex(ExArgs A) {
   constexpr int TL = NT * KX;  // tile cells
   constexpr int SL = TL + 4;   // staged cells (two ghosts per side)
-  __shared__ double X[4][SL];       // stage operand; staged index s <-> cell s - 2
-  __shared__ double F[4][TL + 1];   // face fluxes (h, q u, m u, W u); face e: cells e-1 | e
+  __shared__ double X[4][SL];  // stage operand; staged index s <-> cell s - 2
   const TileDesc td = A.tiles[blockIdx.x];
   const InstDesc I = A.inst[td.inst];
   const double dt = A.dt[td.inst];
@@ -91,37 +113,17 @@ __global__ __launch_bounds__(NT) void k_ex(ExArgs A) {
   __syncthreads();
   const double g = I.g, lam = I.lam, idx = 1.0 / I.dx, i2dx = 0.5 / I.dx;
   bool bad = false;
-  // ---- Rusanov fluxes of faces 0..len (stencil: staged e .. e + 3)
-#pragma unroll
-  for (int r = 0; r <= KX; ++r) {
-    const int e = t + r * NT;
-    if (e <= len) {
-      double L[4], R[4];
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        L[f] = X[f][e + 1] + 0.25 * (X[f][e + 2] - X[f][e]);
-        R[f] = X[f][e + 2] - 0.25 * (X[f][e + 3] - X[f][e + 1]);
-      }
-      bad |= !(L[0] > 0.0) || !(R[0] > 0.0);
-      const double iL = 1.0 / L[0], iR = 1.0 / R[0];
-      const double uL = L[1] * iL, uR = R[1] * iR;
-      const double eL = L[2] * iL * iL, eR = R[2] * iR * iR;
-      const double sL = fabs(uL) + sqrt(g * L[0] + (lam / 3.0) * eL * eL);
-      const double sR = fabs(uR) + sqrt(g * R[0] + (lam / 3.0) * eR * eR);
-      const double al = fmax(sL, sR);
-      F[0][e] = 0.5 * (L[1] + R[1] - al * (R[0] - L[0]));
-      F[1][e] = 0.5 * (L[1] * uL + R[1] * uR - al * (R[1] - L[1]));
-      F[2][e] = 0.5 * (L[2] * uL + R[2] * uR - al * (R[2] - L[2]));
-      F[3][e] = 0.5 * (L[3] * uL + R[3] * uR - al * (R[3] - L[3]));
-    }
-  }
-  __syncthreads();
-  // ---- cells: explicit update (stage 1) or Heun average (stage 2)
+  // ---- cells: explicit update (stage 1) or Heun average (stage 2); each
+  // thread forms both faces of its cell (a face is formed twice, which
+  // keeps the LDS of a tile to the staged operand)
   double smx = 0.0, umx = 0.0;
 #pragma unroll
   for (int r = 0; r < KX; ++r) {
     const int i = t + r * NT;
     if (i < len) {
+      double Fl[4], Fr[4];
+      ex_face<SL>(X, i, g, lam, Fl, bad);
+      ex_face<SL>(X, i + 1, g, lam, Fr, bad);
       const int k = i + 2;  // staged index of the cell
       const double h = X[0][k], m = X[2][k], W = X[3][k];
       bad |= !(h > 0.0);
@@ -132,10 +134,10 @@ __global__ __launch_bounds__(NT) void k_ex(ExArgs A) {
       const double dh = (X[0][k + 1] - X[0][k - 1]) * i2dx;
       const double dm = (X[2][k + 1] - X[2][k - 1]) * i2dx;
       double Lv[4];
-      Lv[0] = -(F[0][i + 1] - F[0][i]) * idx;
-      Lv[1] = -(F[1][i + 1] - F[1][i]) * idx - a2 * dh - lam * alpha * dm;
-      Lv[2] = -(F[2][i + 1] - F[2][i]) * idx + W;
-      Lv[3] = -(F[3][i + 1] - F[3][i]) * idx - lam * (eh - 1.0);
+      Lv[0] = -(Fr[0] - Fl[0]) * idx;
+      Lv[1] = -(Fr[1] - Fl[1]) * idx - a2 * dh - lam * alpha * dm;
+      Lv[2] = -(Fr[2] - Fl[2]) * idx + W;
+      Lv[3] = -(Fr[3] - Fl[3]) * idx - lam * (eh - 1.0);
       double o[4];
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
