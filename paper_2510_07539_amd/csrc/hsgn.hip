@@ -312,8 +312,8 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
       x.in_h = in[0]; x.in_q = in[1];
       x.o_h = o[0]; x.o_q = o[1]; x.o_m = o[2]; x.o_W = o[3];
       mark(HSGN_K_SGN_ROWS, true);
-      hipLaunchKernelGGL((hsgn::k_sgn_rows<hsgn::kExNT, hsgn::kExK>), dim3(c->nxtiles),
-                         dim3(hsgn::kExNT), 0, c->stream, x);
+      hipLaunchKernelGGL((hsgn::k_sgn_rows<hsgn::kSgnNT, hsgn::kSgnK>), dim3(c->nxtiles),
+                         dim3(hsgn::kSgnNT), 0, c->stream, x);
       mark(HSGN_K_SGN_ROWS, false);
       mark(HSGN_K_SGN_SOLVE, true);
       if (c->n_multi_inst > 0) {
@@ -330,11 +330,11 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
       mark(HSGN_K_SGN_SOLVE, false);
       mark(HSGN_K_SGN_UPDATE, true);
       if (stage == 1)
-        hipLaunchKernelGGL((hsgn::k_sgn_update<hsgn::kExNT, hsgn::kExK, 1>), dim3(c->nxtiles),
-                           dim3(hsgn::kExNT), 0, c->stream, x);
+        hipLaunchKernelGGL((hsgn::k_sgn_update<hsgn::kSgnNT, hsgn::kSgnK, 1>), dim3(c->nxtiles),
+                           dim3(hsgn::kSgnNT), 0, c->stream, x);
       else
-        hipLaunchKernelGGL((hsgn::k_sgn_update<hsgn::kExNT, hsgn::kExK, 2>), dim3(c->nxtiles),
-                           dim3(hsgn::kExNT), 0, c->stream, x);
+        hipLaunchKernelGGL((hsgn::k_sgn_update<hsgn::kSgnNT, hsgn::kSgnK, 2>), dim3(c->nxtiles),
+                           dim3(hsgn::kSgnNT), 0, c->stream, x);
       mark(HSGN_K_SGN_UPDATE, false);
     }
     HIPCHK(c, hipGetLastError());

@@ -30,6 +30,11 @@ namespace hsgn {
 constexpr int kExNT = 256;               // threads per tile
 constexpr int kExK = 4;                  // cells per thread
 constexpr int kExTile = kExNT * kExK;    // cells per tile
+// The SGN kernels walk the same 1024-cell tiles with 512 threads of two
+// cells each: measured faster for them than 256 x 4, unlike k_ex.
+constexpr int kSgnNT = 512;
+constexpr int kSgnK = 2;
+static_assert(kSgnNT * kSgnK == kExTile, "SGN and explicit kernels share one tile list");
 
 struct ExArgs {
   const double* __restrict__ un_h;  // U^n
