@@ -502,6 +502,8 @@ int make_plan(hsgn_ctx* c) {
       const int L = halo_width(p, c->h_smax[j], c->h_hmax[j], c->order == 1 ? 1.0 : hsgn::kGamma);
       auto add = [&](int ws, int wl, int cs, int cl, int flags) {
         WinDesc d;
+        std::memset(&d, 0, sizeof d);
+        d.off = c->offsets[j]; d.n = n; d.bc = p.bc; d.has_b = p.has_bathymetry ? 1 : 0;
         d.inst = j; d.ws = ws; d.wl = wl; d.cs = cs; d.cl = cl; d.flags = flags;
         wj.push_back(d);
       };

@@ -25,12 +25,17 @@ namespace hsgn {
 constexpr int32_t kFlagWindow = 4;
 
 struct WinDesc {
+  int64_t off;    // the instance's first cell, its length, boundary and bed flag
+  int32_t n;      // (copies of its descriptor, so that the first loads of a
+  int32_t bc;     // window wait for this descriptor only)
+  int32_t has_b;
   int32_t inst;
   int32_t ws;     // window start, relative to the instance (may be < 0 if periodic)
   int32_t wl;     // real rows of the window (<= NT*K)
   int32_t cs;     // core start (relative to the instance, in [0, n))
   int32_t cl;     // core length
   int32_t flags;  // bit 0: left edge truncated; bit 1: right edge truncated
+  int32_t pad;
 };
 
 struct WinArgs {
@@ -274,41 +279,16 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   }
   if (bid >= W.nwin) return;
   const WinDesc wd = W.win[bid];
-  const InstDesc I = A.inst[wd.inst];
-  const double dt = A.dt[wd.inst];
   const int t = threadIdx.x;
-  const int n = I.n, bc = I.bc;
-  const int64_t base = I.off;
+  const int n = wd.n, bc = wd.bc;
+  const int64_t base = wd.off;
   constexpr int WN = NT * K;
   const int na = (wd.wl + K - 1) / K;  // threads with real rows
   const bool act = t < na;
   const int p0 = t * K;                 // first window row of this thread
   const bool truncL = (wd.flags & 1) != 0, truncR = (wd.flags & 2) != 0;
+  const bool useb = BED && wd.has_b;
   const bool physL = !truncL, physR = !truncR;
-
-  if (!(dt > 0.0)) {  // frozen: copy the core
-    for (int i = t; i < wd.cl; i += NT) {
-      const int64_t gi = base + wd.cs + i;
-      A.o_h[gi] = A.un_h[gi];
-      A.o_q[gi] = A.un_q[gi];
-      A.o_m[gi] = A.un_m[gi];
-      A.o_W[gi] = A.un_W[gi];
-    }
-    return;
-  }
-  PhysC P;
-  P.g = I.g;
-  P.lam = I.lam;
-  P.dx = I.dx;
-  P.tau = A.tau_factor * dt;
-  P.sl = A.slope;
-  P.tdx = P.tau / P.dx;
-  P.lt2 = P.lam * P.tau * P.tau;
-  P.rr = P.tdx * P.tdx;
-  P.tdx2 = 0.5 * P.tdx;
-  const double i2dx = 0.5 / P.dx;
-  const bool useb = BED && I.has_b;
-  bool bad = false, noncoer = false;
 
   // ---- staging and explicit sweep, one field per round: h (with the bed),
   // q, m, W.  A round stages the explicit state E (stage 2: kE0 U^n + kE1 U(1))
@@ -347,7 +327,8 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
     const int i = t + r * NT;
     cidx[r] = (kLean && i < SLn) ? cell_of(i) : 0;
   }
-  auto load_round = [&](int f) {
+  // loads of round f into (xa, xb, xc): U^n, U(1) and the bed
+  auto load_into = [&](int f, double* xa, double* xb, double* xc) {
     const double* un = fld(f, false);
     const double* u1 = fld(f, true);
 #pragma unroll
@@ -355,35 +336,37 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       const int i = t + r * NT;
       if (i < SLn) {
         if constexpr (kLean) {
-          va[r] = (un + base)[cidx[r]];
-          if (STAGE == 2) vb[r] = (u1 + base)[cidx[r]];
-          if (BED && f == 0 && useb) vc[r] = (A.b + base)[cidx[r]];
+          xa[r] = (un + base)[cidx[r]];
+          if (STAGE == 2) xb[r] = (u1 + base)[cidx[r]];
+          if (BED && f == 0 && useb) xc[r] = (A.b + base)[cidx[r]];
         } else {
           const int64_t gi = base + cell_of(i);
-          va[r] = un[gi];
-          if (STAGE == 2) vb[r] = u1[gi];
-          if (BED && f == 0 && useb) vc[r] = A.b[gi];
+          xa[r] = un[gi];
+          if (STAGE == 2) xb[r] = u1[gi];
+          if (BED && f == 0 && useb) xc[r] = A.b[gi];
         }
       }
     }
   };
-  auto put_round = [&](int f) {
+  auto put_from = [&](int f, const double* xa, const double* xb, const double* xc) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int i = t + r * NT;
       if (i < SLn) {
         double* od = f == 0 ? L.u.st.ho : L.u.st.o;  // the old depth stays until the rows
         if (STAGE == 1) {
-          L.u.st.e[spad(i)] = va[r];
-          if (f == 0) od[spad(i)] = va[r];
+          L.u.st.e[spad(i)] = xa[r];
+          if (f == 0) od[spad(i)] = xa[r];
         } else {
-          L.u.st.e[spad(i)] = kE0 * va[r] + kE1 * vb[r];
-          od[spad(i)] = kT0 * va[r] + kT1 * vb[r];
+          L.u.st.e[spad(i)] = kE0 * xa[r] + kE1 * xb[r];
+          od[spad(i)] = kT0 * xa[r] + kT1 * xb[r];
         }
-        if (BED && f == 0 && useb) L.u.st.b[spad(i)] = vc[r];
+        if (BED && f == 0 && useb) L.u.st.b[spad(i)] = xc[r];
       }
     }
   };
+  auto load_round = [&](int f) { load_into(f, va, vb, vc); };
+  auto put_round = [&](int f) { put_from(f, va, vb, vc); };
   // face f (0..K) lies between rows p0 + f - 1 and p0 + f; its stencil is
   // x[f .. f + 3] with x[i] the staged value of row p0 + i - 2
   auto read_x = [&](double* x, const double* src) {
@@ -417,9 +400,39 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
     }
   };
 
+  // rounds 0 and 1 are in flight together (the second set of registers
+  // lives only until round 1 is staged, where few other values are live)
+  double wa[NR], wb[NR];
   load_round(0);
+  load_into(1, wa, wb, vc);
+  // the instance's parameters and step arrive while the first rounds load;
+  // a frozen instance (no step) copies its core and leaves
+  const InstDesc I = A.inst[wd.inst];
+  const double dt = A.dt[wd.inst];
+  if (!(dt > 0.0)) {  // frozen: copy the core
+    for (int i = t; i < wd.cl; i += NT) {
+      const int64_t gi = base + wd.cs + i;
+      A.o_h[gi] = A.un_h[gi];
+      A.o_q[gi] = A.un_q[gi];
+      A.o_m[gi] = A.un_m[gi];
+      A.o_W[gi] = A.un_W[gi];
+    }
+    return;
+  }
+  PhysC P;
+  P.g = I.g;
+  P.lam = I.lam;
+  P.dx = I.dx;
+  P.tau = A.tau_factor * dt;
+  P.sl = A.slope;
+  P.tdx = P.tau / P.dx;
+  P.lt2 = P.lam * P.tau * P.tau;
+  P.rr = P.tdx * P.tdx;
+  P.tdx2 = 0.5 * P.tdx;
+  const double i2dx = 0.5 / P.dx;
+  bool bad = false, noncoer = false;
+
   put_round(0);
-  load_round(1);
   __syncthreads();
   // round h (+ bed): face depths, the bed's rest-moment jump (plain form),
   // depths of rows p0 - 1 .. p0 + K
@@ -456,7 +469,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
     for (int i = 0; i < K + 2; ++i) hf[i] = xh[i + 1];
   }
   __syncthreads();
-  put_round(1);
+  put_from(1, wa, wb, vc);
   load_round(2);
   __syncthreads();
   // round q: face velocities and Rusanov speeds, q-dagger
