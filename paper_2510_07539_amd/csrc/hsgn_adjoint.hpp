@@ -52,6 +52,7 @@ struct TileA {
 struct TC {
   int n, bc, has_b, lo0;  // lo0: virtual cell of slot 0
   double g, lam, dx, tau, tdx, lt2, rr, tdx2, i2dx;
+  double lam3, lam23;  // lambda / 3 and 2 lambda / 3
 };
 
 // virtual cell -> the position holding its values: periodic positions are
@@ -71,20 +72,20 @@ struct Coef {
 };
 __device__ __forceinline__ Coef coefs(const TC& I, double h, double m, double md) {
   Coef c;
-  c.ih = 1.0 / h;
+  c.ih = frcp(h);
   c.eh = m * c.ih * c.ih;
   c.alpha = -(2.0 * c.eh - 1.0) * c.ih * (1.0 / 3.0);
-  c.a2 = I.g * h + I.lam * c.eh * c.eh - (I.lam / 3.0) * c.eh;
+  c.a2 = I.g * h + I.lam * c.eh * c.eh - I.lam3 * c.eh;
   c.b1 = 1.0 + I.lt2 * c.ih * c.ih;
-  c.ib1 = 1.0 / c.b1;
+  c.ib1 = frcp(c.b1);
   c.b2 = 2.0 * I.lt2 * c.ib1 * c.ib1 * c.ih * c.ih * c.ih;
   c.beta = c.a2 + I.lam * c.alpha * c.b2 * md;
   c.eta0 = md * c.ib1 * c.ih;
-  c.pt0 = (I.lam / 3.0) * (1.0 - c.eta0 * c.ih);
+  c.pt0 = I.lam3 * (1.0 - c.eta0 * c.ih);
   c.P0 = 0.5 * I.g * h * h + c.eta0 * c.pt0;
   c.S = c.P0 - c.beta * h;
   if (I.has_b) {
-    c.phi = (2.0 * I.lam / 3.0) * md * c.ih * c.ih * c.ih * c.ib1 * c.ib1;
+    c.phi = I.lam23 * md * c.ih * c.ih * c.ih * c.ib1 * c.ib1;
     c.T = c.pt0 - c.phi * h;
   } else {
     c.phi = 0.0;
@@ -170,7 +171,7 @@ __device__ __forceinline__ void face_flux(const TC& I, const LT& L, int f, doubl
   const double qL = q0 + 0.25 * (q1 - qm), qR = q1 - 0.25 * (q2 - q0);
   const double mL = m0 + 0.25 * (m1 - mm), mR = m1 - 0.25 * (m2 - m0);
   const double WL = w0 + 0.25 * (w1 - wm), WR = w1 - 0.25 * (w2 - w0);
-  const double uL = qL / hL, uR = qR / hR;
+  const double uL = qL * frcp(hL), uR = qR * frcp(hR);
   const double sL = fabs(uL) + sqrt(I.g * hL), sR = fabs(uR) + sqrt(I.g * hR);
   const double a = sL >= sR ? sL : sR;
   double jm = mR - mL;
@@ -214,8 +215,8 @@ template <class LT>
 __device__ __forceinline__ void rev_back(const TC& I, LT& L, int i, const double aU[4],
                                          Own& w) {
   const int t = i - I.lo0;
-  const double h = L.hb[t], ih = 1.0 / h, ih2 = ih * ih, md = w.md;
-  const double rden = 1.0 / (1.0 + I.lt2 * ih2);
+  const double h = L.hb[t], ih = frcp(h), ih2 = ih * ih, md = w.md;
+  const double rden = frcp(1.0 + I.lt2 * ih2);
   const double mn = md * rden;
   const double aW = aU[3], aM = aU[2], aQ = aU[1];
   double hA = aU[0];
@@ -323,6 +324,8 @@ __device__ __forceinline__ TC make_tc(const InstDesc& D, int lo0, double dt) {
   T.rr = T.tdx * T.tdx;
   T.tdx2 = 0.5 * T.tdx;
   T.i2dx = 1.0 / (2.0 * T.dx);
+  T.lam3 = T.lam / 3.0;
+  T.lam23 = 2.0 * T.lam / 3.0;
   return T;
 }
 
@@ -514,10 +517,10 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
     hA += I.g * h * P0A;
     double eta0A = c.pt0 * P0A;
     pt0A += c.eta0 * P0A;
-    eta0A += -(lam / 3.0) * c.ih * pt0A;
-    ihA += -(lam / 3.0) * c.eta0 * pt0A;
+    eta0A += -I.lam3 * c.ih * pt0A;
+    ihA += -I.lam3 * c.eta0 * pt0A;
     if (I.has_b) {
-      const double k = 2.0 * lam / 3.0;
+      const double k = I.lam23;
       mdA += k * c.ih * c.ih * c.ih * c.ib1 * c.ib1 * phiA;
       ihA += 3.0 * k * md * c.ih * c.ih * c.ib1 * c.ib1 * phiA;
       ib1A += 2.0 * k * md * c.ih * c.ih * c.ih * c.ib1 * phiA;
@@ -534,7 +537,7 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
     const double b1A = -c.ib1 * c.ib1 * ib1A;
     ihA += 2.0 * I.lt2 * c.ih * b1A;
     hA += I.g * a2A;
-    double ehA = (2.0 * lam * c.eh - lam / 3.0) * a2A;
+    double ehA = (2.0 * lam * c.eh - I.lam3) * a2A;
     ehA += -(2.0 / 3.0) * c.ih * alphaA;
     ihA += -(2.0 * c.eh - 1.0) * (1.0 / 3.0) * alphaA;
     mA += c.ih * c.ih * ehA;
@@ -603,7 +606,8 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
     const double qL = q[1] + 0.25 * (q[2] - q[0]), qR = q[2] - 0.25 * (q[3] - q[1]);
     const double mL = m[1] + 0.25 * (m[2] - m[0]), mR = m[2] - 0.25 * (m[3] - m[1]);
     const double WL = wv[1] + 0.25 * (wv[2] - wv[0]), WR = wv[2] - 0.25 * (wv[3] - wv[1]);
-    const double uL = qL / hL, uR = qR / hR;
+    const double ihL = frcp(hL), ihR = frcp(hR);
+    const double uL = qL * ihL, uR = qR * ihR;
     const double gsL = sqrt(I.g * hL), gsR = sqrt(I.g * hR);
     const double sL = fabs(uL) + gsL, sR = fabs(uR) + gsR;
     const bool leftmax = sL >= sR;
@@ -630,11 +634,11 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
     const double sLA = leftmax ? aA : 0.0, sRA = leftmax ? 0.0 : aA;
     uLA += (uL < 0.0 ? -1.0 : 1.0) * sLA;
     uRA += (uR < 0.0 ? -1.0 : 1.0) * sRA;
-    double hLA = I.g / (2.0 * gsL) * sLA, hRA = I.g / (2.0 * gsR) * sRA;
-    qLA += uLA / hL;
-    hLA += -uL / hL * uLA;
-    qRA += uRA / hR;
-    hRA += -uR / hR * uRA;
+    double hLA = 0.5 * I.g * frcp(gsL) * sLA, hRA = 0.5 * I.g * frcp(gsR) * sRA;
+    qLA += uLA * ihL;
+    hLA += -uL * ihL * uLA;
+    qRA += uRA * ihR;
+    hRA += -uR * ihR * uRA;
     const double vLA[4] = {hLA, qLA, mLA, WLA}, vRA[4] = {hRA, qRA, mRA, WRA};
 #pragma unroll
     for (int fl = 0; fl < 4; ++fl) {
@@ -743,7 +747,7 @@ __device__ void wg_tri_solve(Lds<NT>& S, const double* __restrict__ lo, const do
         const int i = i0 + b;
         if (i <= k - 2) {
           const double l = L[b], d = D[b], u = U[b], r = R[b];
-          const double inv = 1.0 / (d - l * cprev);
+          const double inv = frcp(d - l * cprev);
           const bool lastint = (i == k - 2);
           cprev = lastint ? 0.0 : u * inv;
           yprev = (r - l * yprev) * inv;
@@ -886,7 +890,7 @@ __device__ __forceinline__ Chunk reg_chunk_elim(Lds<NT>& S, const double* __rest
     for (int i = 1; i < K - 1; ++i) {
       if (i <= k - 2) {
         const double l = Lo[i], d = Di[i], u = Up[i], r = Rh[i];
-        const double inv = 1.0 / (d - l * cprev);
+        const double inv = frcp(d - l * cprev);
         const bool lastint = (i == k - 2);
         cprev = lastint ? 0.0 : u * inv;
         yprev = (r - l * yprev) * inv;
