@@ -279,6 +279,20 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   }
   if (bid >= W.nwin) return;
   const WinDesc wd = W.win[bid];
+  // Warm this XCD's L2 with the descriptor of the window that starts about
+  // one block lifetime later (64 blocks run at once per XCD): a vector load
+  // by one thread (its index made opaque, so the load is not scalarised and
+  // does not hold up the waits for LDS) whose value only feeds an empty asm
+  // statement after the last staging round.
+  int ahead = 0;
+  {
+    int zero = threadIdx.x;
+    asm volatile("" : "+v"(zero));
+    zero >>= 31;
+    const int wa_ = bid + 64;
+    const int lim = W.xcd_stride > 0 ? min(W.nwin, (bid / W.xcd_stride + 1) * W.xcd_stride) : W.nwin;
+    if (threadIdx.x == 0 && wa_ < lim) ahead = W.win[wa_ + zero].inst;
+  }
   const int t = threadIdx.x;
   const int n = wd.n, bc = wd.bc;
   const int64_t base = wd.off;
@@ -348,6 +362,10 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       }
     }
   };
+  // staging buffer of round f: stage 1 (which stages no old state) alternates
+  // between two, so a round's writes need no barrier after the previous
+  // round's reads
+  auto ebuf = [&](int f) -> double* { return (STAGE == 1 && (f & 1)) ? L.u.st.o : L.u.st.e; };
   auto put_from = [&](int f, const double* xa, const double* xb, const double* xc) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -355,7 +373,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       if (i < SLn) {
         double* od = f == 0 ? L.u.st.ho : L.u.st.o;  // the old depth stays until the rows
         if (STAGE == 1) {
-          L.u.st.e[spad(i)] = xa[r];
+          ebuf(f)[spad(i)] = xa[r];
           if (f == 0) od[spad(i)] = xa[r];
         } else {
           L.u.st.e[spad(i)] = kE0 * xa[r] + kE1 * xb[r];
@@ -390,9 +408,9 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       if (!need) continue;
       const int i0 = sd == 0 ? 0 : wd.wl + 1;
 #pragma unroll
-      for (int d = 0; d < 5; ++d) L.side[sd][f][d] = L.u.st.e[spad(i0 + d)];
+      for (int d = 0; d < 5; ++d) L.side[sd][f][d] = ebuf(f)[spad(i0 + d)];
       const double* od = f == 0 ? L.u.st.ho : L.u.st.o;
-      L.sideo[sd][f] = STAGE == 1 ? L.u.st.e[spad(i0 + 2)] : od[spad(i0 + 2)];
+      L.sideo[sd][f] = STAGE == 1 ? ebuf(f)[spad(i0 + 2)] : od[spad(i0 + 2)];
       if (f == 0) {
 #pragma unroll
         for (int d = 0; d < 5; ++d) L.sideb[sd][d] = (BED && useb) ? L.u.st.b[spad(i0 + d)] : 0.0;
@@ -441,7 +459,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   if (act) {
     save_side(0);
     double xh[K + 4], xb[K + 4];
-    read_x(xh, L.u.st.e);
+    read_x(xh, ebuf(0));
     if (BED && useb && !kLean) {
       read_x(xb, L.u.st.b);
     } else {
@@ -468,7 +486,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
 #pragma unroll
     for (int i = 0; i < K + 2; ++i) hf[i] = xh[i + 1];
   }
-  __syncthreads();
+  if (STAGE == 2) __syncthreads();
   put_from(1, wa, wb, vc);
   load_round(2);
   __syncthreads();
@@ -477,7 +495,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   if (act) {
     save_side(1);
     double xq[K + 4], Fq[K + 1];
-    read_x(xq, L.u.st.e);
+    read_x(xq, ebuf(1));
 #pragma unroll
     for (int f = 0; f <= K; ++f) {
       const double qL = xq[f + 1] + P.sl * (xq[f + 2] - xq[f]);
@@ -495,7 +513,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       eq[j] = xq[j + 2];
     }
   }
-  __syncthreads();
+  if (STAGE == 2) __syncthreads();
   put_round(2);
   load_round(3);
   __syncthreads();
@@ -506,7 +524,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   if (act) {
     save_side(2);
     double xm[K + 4], xb[K + 4], Fm[K + 1];
-    read_x(xm, L.u.st.e);
+    read_x(xm, ebuf(2));
     if (BED && useb && kLean) {
       read_x(xb, L.u.st.b);
     } else {
@@ -543,8 +561,9 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       em[j] = xm[j + 2];
     }
   }
-  __syncthreads();
+  if (STAGE == 2) __syncthreads();
   put_round(3);
+  asm volatile("" ::"v"(ahead));
   __syncthreads();
   // round W: W-dagger, m-dagger, and the rows' frozen coefficients
   Rec rec[K];
@@ -552,7 +571,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   if (act) {
     save_side(3);
     double xw[K + 4], Fw[K + 1];
-    read_x(xw, L.u.st.e);
+    read_x(xw, ebuf(3));
 #pragma unroll
     for (int f = 0; f <= K; ++f) {
       const double WL = xw[f + 1] + P.sl * (xw[f + 2] - xw[f]);
