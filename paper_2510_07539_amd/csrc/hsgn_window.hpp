@@ -868,19 +868,24 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       }
     }
   }
-  // ---- coalesced stores of the core, one field at a time through LDS
+  // ---- coalesced stores of the core through LDS: two fields per round in
+  // the staging buffers e and o, or (with a bed) all four in one round, the bed
+  // and old-depth buffers being free by now
   __syncthreads();  // level-1 values (a) are no longer read
   double* out[4] = {A.o_h, A.o_q, A.o_m, A.o_W};
   constexpr int NS = (WN + NT - 1) / NT;
+  constexpr bool kOneRound = BED;
+  constexpr int kPer = kOneRound ? 4 : 2;
+  double* const sb[4] = {L.u.st.e, L.u.st.o, kOneRound ? L.u.st.b : L.u.st.e, L.u.st.ho};
 #pragma unroll
-  for (int f = 0; f < 4; f += 2) {  // two fields per round (buffers e and o)
+  for (int f = 0; f < 4; f += kPer) {
     if (has_core) {
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         const int p = p0 + j;
         if (p >= c0 && p < c1) {
-          L.u.st.e[spad(p)] = on[f][j];
-          L.u.st.o[spad(p)] = on[f + 1][j];
+#pragma unroll
+          for (int e = 0; e < kPer; ++e) sb[e][spad(p)] = on[f + e][j];
         }
       }
     }
@@ -891,8 +896,8 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       if (i < wd.cl) {
         int c = wd.cs + i;
         if (c >= n) c -= n;
-        out[f][base + c] = L.u.st.e[spad(c0 + i)];
-        out[f + 1][base + c] = L.u.st.o[spad(c0 + i)];
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) out[f + e][base + c] = sb[e][spad(c0 + i)];
       }
     }
     __syncthreads();
