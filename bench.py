@@ -64,6 +64,26 @@ def bytes_per_cell(kind, bed):
             }.get(kind, 0)
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Bandwidth of a plain device-to-device copy of nbytes (read + write
+    counted), timed with events on torch's stream: the measured ceiling the
+    roofline is also reported against."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def make_workload(name):
     from paper_2510_07539_amd import workloads as WL
     if name == "batched_bar":
@@ -361,6 +381,9 @@ def main():
             "avg_launch_ms": round(ms_avg, 4),
             "alg_bytes_per_launch": alg_bytes,
             "alg_bytes_per_cell": bytes_per_cell(dom, bed)}
+    copy_gbps = copy_bandwidth()
+    roof["copy_gbps"] = round(copy_gbps, 1)
+    roof["frac_of_copy"] = round(achieved / copy_gbps, 4)
     step_bytes = (bytes_per_cell("stage1", bed) if args.order == 1 else
                   (bytes_per_cell("stage1", bed) + bytes_per_cell("stage2", bed)) / 2.0)
     if args.scheme == "explicit":
