@@ -22,26 +22,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
-# sources of the windowed stage kernel (the dominant kernel of the benchmark)
-CSRC = [os.path.join(ROOT, "paper_2510_07539_amd", "csrc", f)
-        for f in ("hsgn_kernels.hpp", "hsgn_window.hpp")]
+# HBM traffic of the dominant kernels measured with rocprofv3 --pmc (FETCH_SIZE
+# and WRITE_SIZE in separate runs, `bench.py --probe [--solver auto_small |
+# --scheme explicit | --scheme sgn]`), scaled by the same counters on a plain
+# 512 MiB copy (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0), in bytes per launch
+# (the SGN solve: per stage, its three kernels).  Each entry is keyed by the
+# hash of the sources of its kernels and reported as null once they change.
+TRAFFIC = [
+    {"kernel": "win2", "workload": "batched_bar", "solver": "auto_small",
+     "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp"], "hash": "0f45e66be4d9d410",
+     "fetch_bytes": 2812629309, "write_bytes": 1544248213, "bytes_per_launch": 4356877522},
+    {"kernel": "ex2", "workload": "batched_flat", "scheme": "explicit",
+     "sources": ["hsgn_kernels.hpp", "hsgn_explicit.hpp"], "hash": "aa640bfae82747bf",
+     "fetch_bytes": 2232930559, "write_bytes": 1118178346, "bytes_per_launch": 3351108905},
+    {"kernel": "sgn_solve", "workload": "batched_flat", "scheme": "sgn",
+     "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp",
+                 "hsgn_explicit.hpp"], "hash": "2c7c57d314257748",
+     "fetch_bytes": 2227124592, "write_bytes": 280497749, "bytes_per_launch": 2507622342},
+]
 
-# HBM traffic of the dominant kernel measured with rocprofv3 --pmc (FETCH_SIZE
-# and WRITE_SIZE in separate runs, `bench.py --probe --solver auto_small`),
-# scaled by the same counters on a plain 512 MiB copy (FETCH_SIZE x 1.9998,
-# WRITE_SIZE x 1.0).
-# Keyed by the hash of the kernel's sources; reported as null once they change.
-TRAFFIC = {
-    "0f45e66be4d9d410": {"kernel": "win2", "workload": "batched_bar",
-                         "solver": "auto_small",
-                         "fetch_bytes": 2812629309, "write_bytes": 1544248213,
-                         "bytes_per_launch": 4356877522},
-}
-
-def src_hash():
+def src_hash(sources):
     h = hashlib.sha256()
-    for f in CSRC:
-        with open(f, "rb") as fh:
+    for f in sources:
+        with open(os.path.join(ROOT, "paper_2510_07539_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -366,13 +369,14 @@ def main():
                     "sgn_solve": wl.n_cells, "sgn_update": wl.n_cells}.get(dom, 0)
     alg_bytes = bytes_per_cell(dom, bed) * cells_launch
     achieved = alg_bytes / (ms_avg * 1e-3) / 1e9 if ms_avg > 0 else 0.0
-    h = src_hash()
-    tr = TRAFFIC.get(h)
     traffic = None
     solver_used = tuned["kept"] if tuned else args.solver
-    if (tr and tr.get("kernel") == dom and tr.get("workload") == args.workload and
-            tr.get("solver") == solver_used):
-        traffic = tr["bytes_per_launch"]
+    for tr in TRAFFIC:
+        if (tr["kernel"] == dom and tr["workload"] == args.workload and
+                tr.get("solver", solver_used) == solver_used and
+                tr.get("scheme", args.scheme) == args.scheme and
+                src_hash(tr["sources"]) == tr["hash"]):
+            traffic = tr["bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
             "kernel": ("k_win<%s>" if dom.startswith("win") else
