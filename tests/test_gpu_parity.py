@@ -120,6 +120,26 @@ def test_solitary_to_t_end():
     compare(wl, 200, label="C1 to t_end")
 
 
+def test_supercritical_flow_material_cfl_cap():
+    """Froude-6 flow over h = 0.1 m (|u| = 6 m/s): the material CFL cap
+    max|u| dt / dx <= 0.5 binds instead of the CFL rule on |u| + sqrt(g h)
+    (checked on the oracle first); periodic and transmissive, 2 tiles."""
+    parts = []
+    for bc in (0, 1):
+        n, dx = 3000, 0.04
+        x = (np.arange(n) + 0.5) * dx
+        h = 0.1 * (1.0 + 0.05 * np.sin(2 * np.pi * x / (n * dx)))
+        u = np.full(n, 6.0)
+        parts.append(WL._part(n, dx, 100.0, bc, h, u, np.zeros(n)))
+    wl = WL._pack("supercritical", parts, 30)
+    for j in range(wl.n_inst):
+        n, prm, b, U0 = wl.instance(j)
+        p = O.make_params(**prm)
+        umax = float(np.max(np.abs(U0[1] / U0[0])))
+        assert O.dt(p, U0[0], U0[1]) == pytest.approx(prm["mcfl"] * prm["dx"] / umax, rel=1e-15)
+    compare(wl, 30, label="supercritical (material CFL cap)")
+
+
 @pytest.mark.parametrize("solver", SOLVERS)
 def test_multi_tile_periodic(solver):
     compare(WL.solitary(N=5000, L=1250.0, lam=1000.0, t_end=0.0), 100, label="periodic 3 tiles",

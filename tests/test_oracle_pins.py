@@ -546,6 +546,35 @@ def test_explicit_heun_on_uniform_state():
     assert np.max(np.abs(Un[2] - m2)) < 1e-15 and np.max(np.abs(Un[3] - W2)) < 1e-13
 
 
+def test_semi_implicit_dt_rule():
+    """dt = CFL dx / max(|u| + sqrt(g h)), capped so that max|u| dt / dx <=
+    MCFL (Sec. 5), replaced by a fixed step when one is given, and clamped
+    to t_end (0 once t_end is reached): each branch made to bind."""
+    g, dx, cfl, mcfl = 9.81, 0.1, 0.9, 0.5
+    # subcritical: the CFL rule binds
+    h = np.array([1.0, 0.5, 2.0])
+    q = np.array([0.2, -0.4, 0.1])
+    p = O.make_params(dx=dx, cfl=cfl, mcfl=mcfl)
+    s = max(abs(q[i] / h[i]) + math.sqrt(g * h[i]) for i in range(3))
+    assert abs(O.dt(p, h, q) - cfl * dx / s) < 1e-17
+    # supercritical: the material cap binds (max|u| = 6, c ~ 1)
+    h = np.array([0.1, 0.1, 0.1])
+    q = np.array([0.5, -0.6, 0.1])
+    s = max(abs(q[i] / h[i]) + math.sqrt(g * h[i]) for i in range(3))
+    assert 6.0 * (cfl * dx / s) / dx > mcfl
+    assert abs(O.dt(p, h, q) - mcfl * dx / 6.0) < 1e-17
+    # no cap when mcfl <= 0
+    p0 = O.make_params(dx=dx, cfl=cfl, mcfl=0.0)
+    assert abs(O.dt(p0, h, q) - cfl * dx / s) < 1e-17
+    # a fixed step is taken as given
+    pf = O.make_params(dx=dx, cfl=cfl, mcfl=mcfl, dt_fixed=0.0123)
+    assert O.dt(pf, h, q) == 0.0123
+    # t_end: the last step is shortened, then the state is frozen
+    pt = O.make_params(dx=dx, cfl=cfl, mcfl=mcfl, dt_fixed=0.0123, t_end=0.05)
+    assert O.dt(pt, h, q, t=0.045) == pytest.approx(0.005, abs=1e-16)
+    assert O.dt(pt, h, q, t=0.05) == 0.0
+
+
 def test_explicit_dt_rule():
     """dt = CFL dx / max(|u| + c), c^2 = g h + (lambda/3)(eta/h)^2 (Sec. 5,
     eq. CFL_ex), clamped to t_end."""
