@@ -76,7 +76,7 @@ def check_instance(j, U, wl, nsteps, tol=TOL, seed=0, state_sens=False, order=2,
 
 
 def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", solver="auto",
-            order=2, scheme=0, cfl=None):
+            order=2, scheme=0, cfl=None, state_sens=False):
     note("parity %s [%s, order %d, scheme %d]: %s, %d instances, %d cells, %d steps" % (
         label, solver, order, scheme, wl.name, wl.n_inst, wl.n_cells, nsteps))
     Solver = _solver()
@@ -98,7 +98,8 @@ def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", 
     worst = 0.0
     worst_ratio = 0.0
     for j in insts:
-        e, r, to = check_instance(j, U, wl, nsteps, tol, order=order, scheme=scheme, cfl=cfl)
+        e, r, to = check_instance(j, U, wl, nsteps, tol, order=order, scheme=scheme, cfl=cfl,
+                                  state_sens=state_sens)
         assert abs(tg[j] - to) <= 1e-12 * max(1.0, abs(to)), (j, tg[j], to)
         worst = max(worst, e)
         worst_ratio = max(worst_ratio, r)
@@ -268,15 +269,27 @@ def test_batched_full_size_sampled():
     compare(wl, 100, use_run=True, block=100, insts=sorted(set(pick)), label="C3 full, sampled")
 
 
-def test_window_plan_covers_every_cell_once():
-    """Host plan: the windows' cores tile every windowed instance exactly."""
+@pytest.mark.parametrize("solver", ["auto", "auto_small"])
+def test_mixed_plan_windows_and_two_pass_tiles(solver):
+    """One context whose plan mixes both solvers: bar instances go to
+    windows, while a solitary wave at lambda = 3e5 on dx = 0.01 (halo
+    estimate ~1660 rows, beyond a quarter of either window width) falls
+    back to the exact two-pass tiles; every instance matches the oracle.
+    At lambda = 3e5 the oracle's own result moves by 5e-10 (relative) under
+    a half-ulp perturbation of its input, so the state bar is max(1e-11,
+    8x that sensitivity), as for every field bar."""
     Solver = _solver()
-    wl = WL.concat("plan", [WL.batched_bar(n_inst=40, seed=9, n_lo=512, n_hi=16384),
-                            WL.long_periodic(N=50000), WL.dam_break()])
-    s = Solver.from_workload(wl)
+    wl = WL.concat("mixed plan", [WL.batched_bar(n_inst=6, seed=9, n_lo=600, n_hi=9000),
+                                  WL.solitary(N=5000, L=50.0, lam=3e5, t_end=0.0),
+                                  WL.dam_break(N=3000, xa=-45.0, xb=45.0)])
+    s = Solver.from_workload(wl, solver=solver)
     info = s.plan_info()
-    assert info["windows"] > 0
-    assert (info["halo"][info["mode"] == 0] > 0).all()
+    s.close()
+    mode = info["mode"]
+    assert mode[6] == 1 and (mode[:6] == 0).all(), mode
+    assert info["windows"] > 0 and info["exact_tiles"] > 0
+    assert (info["halo"][mode == 0] > 0).all()
+    compare(wl, 50, label="mixed plan", solver=solver, state_sens=True)
 
 
 @pytest.mark.parametrize("solver", ["auto", "exact"])
