@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhsgn.so")
 
 HSGN_OK, HSGN_EINVAL, HSGN_EHIP, HSGN_ENONPHYS, HSGN_ENONCOERCIVE, HSGN_ENOMEM = 0, -1, -2, -3, -4, -5
+HSGN_EWINDOW = -6
 FLAG_NONPHYS, FLAG_NONCOERCIVE = 1, 2
 KERNEL_KINDS = ("dt", "reduce1", "rsolve1", "stage1", "reduce2", "rsolve2", "stage2", "win1", "win2",
                 "ex1", "ex2", "sgn_rows", "sgn_solve", "sgn_update")

@@ -292,6 +292,53 @@ def test_mixed_plan_windows_and_two_pass_tiles(solver):
     compare(wl, 50, label="mixed plan", solver=solver, state_sens=True)
 
 
+def _far_from_equilibrium():
+    """lambda = 1e4, dx = 0.04, N = 8000, h ~ 0.4 at rest: one instance
+    starts at eta = 2 h (m = 2 h^2), one at eta = h."""
+    parts = []
+    for fac in (2.0, 1.0):
+        n, dx = 8000, 0.04
+        h = 0.4 * (1.0 + 0.01 * np.sin(2 * np.pi * np.arange(n) / n))
+        part = WL._part(n, dx, 1e4, 1, h, np.zeros(n), np.zeros(n))
+        part["m"] = np.ascontiguousarray(fac * h * h)
+        parts.append(part)
+    return WL._pack("far from equilibrium", parts, 3)
+
+
+@pytest.mark.parametrize("solver", ["auto", "auto_small"])
+def test_window_certificate_flags_an_insufficient_halo(solver):
+    """At eta = 2 h the stage's depth rows couple far more strongly than the
+    rest state the planner sizes the halo from (392 rows): from the
+    oracle's own rows, about 700 rows are needed for 2^-60.  The windowed
+    solve must then flag that instance (HSGN_EWINDOW, status bit 4) instead
+    of returning a truncated result; the instance at eta = h is not
+    flagged, and the exact solver matches the oracle on both (the state
+    bar follows the oracle's own half-ulp sensitivity: 1e-10 of the state
+    at eta = 2 h, where the relaxation drives W to about 12)."""
+    from paper_2510_07539_amd.hsgn import HSGN_EWINDOW
+    wl = _far_from_equilibrium()
+    # the oracle's rows at the first stage: decay rate of the depth system
+    n, prm, b, U0 = wl.instance(0)
+    p = O.make_params(**prm)
+    tau = (1.0 - 1.0 / np.sqrt(2.0)) * O.dt(p, U0[0], U0[1])
+    rc, _, A = O.stage(p, tau, b, U0, U0, debug=True)
+    assert rc == 0
+    ratio = np.max((np.abs(A["lo"]) + np.abs(A["up"])) / np.abs(A["di"]))
+    R = ratio / (2.0 * (1.0 - ratio))
+    qq = 1.0 + 0.5 / R
+    need = 60.0 * np.log(2.0) / -np.log(qq - np.sqrt(qq * qq - 1.0))
+    Solver = _solver()
+    s = Solver.from_workload(wl, solver=solver)
+    info = s.plan_info()
+    assert (info["mode"] == 0).all() and info["halo"][0] < 0.75 * need, (info["halo"], need)
+    s.step(1)
+    rc, flags = s.status()
+    s.close()
+    assert rc == HSGN_EWINDOW, rc
+    assert flags[0] & 4 and not flags[1] & 4, flags
+    compare(wl, 3, label="far from equilibrium, exact", solver="exact", state_sens=True)
+
+
 @pytest.mark.parametrize("solver", ["auto", "exact"])
 def test_coercivity_loss_flagged_at_the_oracle_step(solver):
     """Instance 84 of the batched bar (N = 586, lambda = 1e3): its solitary
