@@ -152,10 +152,14 @@ int hsgn_run(hsgn_ctx* ctx, int32_t nsteps, int32_t block);
  *  HSGN_SOLVER_AUTO: an instance that fits one 4096-row window is solved in
  *    one pass, exactly.  A longer instance is cut into windows that solve
  *    their core plus a halo of L rows per side (L from the decay of the
- *    inverse of the depth system at the loaded state, margin 2); each
- *    window bounds the effect of the truncation on its core and flags the
- *    instance (HSGN_FLAG_WINDOW) if it exceeds 2^-56 of the depth.  When L
- *    would exceed a quarter window the instance uses the exact solver.
+ *    inverse of the depth system at the rest-state coefficients of the
+ *    loaded state's deepest cell and speed bound, margin 2); each window
+ *    bounds the effect of the truncation on its core and flags the
+ *    instance (HSGN_FLAG_WINDOW) if it exceeds 2^-56 of the depth, as it
+ *    does for a start far from the relaxation equilibrium (eta far from h),
+ *    whose rows couple more strongly than that estimate: such an instance
+ *    needs HSGN_SOLVER_EXACT.  When L would exceed a quarter window the
+ *    instance uses the exact solver.
  *  HSGN_SOLVER_EXACT: two passes per stage for every instance longer than
  *    2048 cells: tiles reduce to two rows each, a per-instance reduced
  *    system is solved, and the tiles finish (no truncation anywhere).
