@@ -55,7 +55,7 @@ class Params(C.Structure):
     _fields_ = [("g", C.c_double), ("lam", C.c_double), ("dx", C.c_double),
                 ("cfl", C.c_double), ("mcfl", C.c_double), ("dt_fixed", C.c_double),
                 ("t_end", C.c_double), ("bc", C.c_int), ("has_b", C.c_int),
-                ("order", C.c_int), ("scheme", C.c_int)]
+                ("order", C.c_int), ("scheme", C.c_int), ("form", C.c_int)]
 
 
 class StageDbg(C.Structure):
@@ -69,38 +69,42 @@ def lib():
     if _lib is None:
         if _stale(_LIB) or _stale(_LIB_CS):
             build(force=False)
-        L = C.CDLL(_LIB)
-        dp = C.POINTER(C.c_double)
-        L.or_stage.restype = C.c_int
-        L.or_stage.argtypes = [C.c_int, C.POINTER(Params), C.c_double, dp] + [dp] * 12 + [C.POINTER(StageDbg)]
-        L.or_dt.restype = C.c_double
-        L.or_dt.argtypes = [C.c_int, C.POINTER(Params), dp, dp, C.c_double]
-        L.or_sgn_phi.restype = C.c_int
-        L.or_sgn_phi.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp]
-        L.or_dt_ex.restype = C.c_double
-        L.or_dt_ex.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, C.c_double]
-        L.or_step.restype = C.c_int
-        L.or_step.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, dp, dp]
-        L.or_run.restype = C.c_int
-        L.or_run.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, dp, C.c_int]
-        L.or_run_batch.restype = C.c_int
-        L.or_run_batch.argtypes = [C.c_int, C.POINTER(C.c_longlong), C.POINTER(Params), dp,
-                                   dp, dp, dp, dp, dp, C.c_int, C.c_int, C.POINTER(C.c_int)]
-        L.or_tridiag.restype = C.c_int
-        L.or_tridiag.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, dp]
-        L.or_gamma.restype = C.c_double
-        L.or_max_threads.restype = C.c_int
-        L.or_tableau.restype = None
-        L.or_tableau.argtypes = [dp]
-        ip = C.POINTER(C.c_int)
-        L.or_run_loss.restype = C.c_int
-        L.or_run_loss.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, C.c_int,
-                                  C.c_int, ip, dp, dp]
-        L.or_run_gauges.restype = C.c_int
-        L.or_run_gauges.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, C.c_int,
-                                    C.c_int, ip, dp]
-        _lib = L
+        _lib = _configure(C.CDLL(_LIB))
     return _lib
+
+
+def _configure(L):
+    """Declare the argument and result types of the double build."""
+    dp = C.POINTER(C.c_double)
+    L.or_stage.restype = C.c_int
+    L.or_stage.argtypes = [C.c_int, C.POINTER(Params), C.c_double, dp] + [dp] * 12 + [C.POINTER(StageDbg)]
+    L.or_dt.restype = C.c_double
+    L.or_dt.argtypes = [C.c_int, C.POINTER(Params), dp, dp, C.c_double]
+    L.or_sgn_phi.restype = C.c_int
+    L.or_sgn_phi.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp]
+    L.or_dt_ex.restype = C.c_double
+    L.or_dt_ex.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, C.c_double]
+    L.or_step.restype = C.c_int
+    L.or_step.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, dp, dp]
+    L.or_run.restype = C.c_int
+    L.or_run.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, dp, C.c_int]
+    L.or_run_batch.restype = C.c_int
+    L.or_run_batch.argtypes = [C.c_int, C.POINTER(C.c_longlong), C.POINTER(Params), dp,
+                               dp, dp, dp, dp, dp, C.c_int, C.c_int, C.POINTER(C.c_int)]
+    L.or_tridiag.restype = C.c_int
+    L.or_tridiag.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, dp]
+    L.or_gamma.restype = C.c_double
+    L.or_max_threads.restype = C.c_int
+    L.or_tableau.restype = None
+    L.or_tableau.argtypes = [dp]
+    ip = C.POINTER(C.c_int)
+    L.or_run_loss.restype = C.c_int
+    L.or_run_loss.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, C.c_int,
+                              C.c_int, ip, dp, dp]
+    L.or_run_gauges.restype = C.c_int
+    L.or_run_gauges.argtypes = [C.c_int, C.POINTER(Params), dp, dp, dp, dp, dp, C.c_int,
+                                C.c_int, ip, dp]
+    return L
 
 
 def _p(a):
@@ -113,10 +117,16 @@ def _p(a):
 SCHEME_SI, SCHEME_EXPLICIT, SCHEME_SGN = 0, 1, 2
 
 
+FORM_P, FORM_A = 0, 1
+
+
 def make_params(g=9.81, lam=100.0, dx=1.0, cfl=0.9, mcfl=0.5, dt_fixed=0.0,
-                t_end=0.0, bc=BC_PERIODIC, has_b=0, order=2, scheme=SCHEME_SI) -> Params:
+                t_end=0.0, bc=BC_PERIODIC, has_b=0, order=2, scheme=SCHEME_SI,
+                form=FORM_P) -> Params:
+    """form: FORM_P (conservative P-form, the oracle of the library) or
+    FORM_A (the printed lines of Sec. 4.2, CPU only, flat bottom)."""
     return Params(g, lam, dx, cfl, mcfl, dt_fixed, t_end, int(bc), int(has_b), int(order),
-                  int(scheme))
+                  int(scheme), int(form))
 
 
 def gamma() -> float:
@@ -226,17 +236,89 @@ def lib_cs():
     global _lib_cs
     if _lib_cs is None:
         lib()
-        L = C.CDLL(_LIB_CS)
-        cp = C.c_void_p
-        ip = C.POINTER(C.c_int)
-        dp = C.POINTER(C.c_double)
-        L.or_run_loss_cs.restype = C.c_int
-        L.or_run_loss_cs.argtypes = [C.c_int, C.POINTER(Params), cp, cp, cp, cp, cp, C.c_int,
-                                   C.c_int, ip, dp, cp]
-        L.or_run_cs.restype = C.c_int
-        L.or_run_cs.argtypes = [C.c_int, C.POINTER(Params), cp, cp, cp, cp, cp, dp, C.c_int]
-        _lib_cs = L
+        _lib_cs = _configure_cs(C.CDLL(_LIB_CS))
     return _lib_cs
+
+
+def _configure_cs(L):
+    cp = C.c_void_p
+    ip = C.POINTER(C.c_int)
+    dp = C.POINTER(C.c_double)
+    L.or_run_loss_cs.restype = C.c_int
+    L.or_run_loss_cs.argtypes = [C.c_int, C.POINTER(Params), cp, cp, cp, cp, cp, C.c_int,
+                                 C.c_int, ip, dp, cp]
+    L.or_run_cs.restype = C.c_int
+    L.or_run_cs.argtypes = [C.c_int, C.POINTER(Params), cp, cp, cp, cp, cp, dp, C.c_int]
+    L.or_step_cs.restype = C.c_int
+    L.or_step_cs.argtypes = [C.c_int, C.POINTER(Params), cp, cp, cp, cp, cp, dp, dp]
+    return L
+
+
+class using:
+    """Context manager: the functions of this module call the oracle built
+    from another copy of the source (libraries in `libdir`, built by
+    `build_at`), e.g. a copy with a planted mistake, for tests that check
+    that the pins detect it.  Restores the regular build on exit."""
+
+    def __init__(self, libdir):
+        self.libdir = libdir
+
+    def __enter__(self):
+        global _lib, _lib_cs
+        lib()
+        lib_cs()
+        self.saved = (_lib, _lib_cs)
+        _lib = _configure(C.CDLL(os.path.join(self.libdir, "liboracle.so")))
+        _lib_cs = _configure_cs(C.CDLL(os.path.join(self.libdir, "liboracle_cs.so")))
+        return self
+
+    def __exit__(self, *exc):
+        global _lib, _lib_cs
+        _lib, _lib_cs = self.saved
+        return False
+
+
+def build_at(libdir, source_text):
+    """Compile `source_text` (a variant of hsgn_oracle.c) into libdir as
+    liboracle.so and liboracle_cs.so with the regular flags."""
+    import shutil
+    os.makedirs(libdir, exist_ok=True)
+    for f in ("hsgn_oracle.h", "hsgn_oracle_cs.c"):
+        shutil.copy(os.path.join(_HERE, f), os.path.join(libdir, f))
+    with open(os.path.join(libdir, "hsgn_oracle.c"), "w") as f:
+        f.write(source_text)
+    _compile(os.path.join(libdir, "hsgn_oracle.c"), os.path.join(libdir, "liboracle.so"))
+    _compile(os.path.join(libdir, "hsgn_oracle_cs.c"), os.path.join(libdir, "liboracle_cs.so"))
+
+
+def source_text():
+    with open(_SRC) as f:
+        return f.read()
+
+
+def step_jacobian(p: Params, b, U, eps=1e-30):
+    """Jacobian of one step (scheme and order from p) with respect to the
+    state (h, q, m, W), by complex steps of the complex build: column k is
+    Im step(U + i eps e_k) / eps, exact to rounding.  Use a fixed dt
+    (p.dt_fixed > 0) so that dt does not depend on the state.  Returns
+    (rc, J) with J of shape (4n, 4n), fields stacked h, q, m, W."""
+    n = len(U[0])
+    base = np.concatenate([np.asarray(a, dtype=np.float64) for a in U])
+    J = np.empty((4 * n, 4 * n))
+    bb = None if b is None else np.ascontiguousarray(b, dtype=np.complex128)
+    vp = lambda a: None if a is None else C.c_void_p(a.ctypes.data)
+    for k in range(4 * n):
+        z = base.astype(np.complex128)
+        z[k] += 1j * eps
+        Uc = [np.ascontiguousarray(z[f * n:(f + 1) * n]) for f in range(4)]
+        t = C.c_double(0.0)
+        dtt = C.c_double(0.0)
+        rc = lib_cs().or_step_cs(n, C.byref(p), vp(bb), *[vp(a) for a in Uc], C.pointer(t),
+                                 C.pointer(dtt))
+        if rc:
+            return rc, None
+        J[:, k] = np.concatenate([a.imag for a in Uc]) / eps
+    return 0, J
 
 
 def run_loss(p: Params, b, U, nsteps, gauges, targets):

@@ -234,9 +234,14 @@ int FN(or_stage)(int n, const or_params* p, double tau, const real_t* bin,
   real_t* up = (real_t*)malloc(nc * sizeof(real_t));
   real_t* rhs = (real_t*)malloc(nc * sizeof(real_t));
   real_t* hb = (real_t*)malloc(nc * sizeof(real_t));
+  real_t* dl = (real_t*)malloc(nc * sizeof(real_t));
   if (!bz || !Fq || !Fm || !FW || !qd || !md || !Wd || !beta || !S || !phi ||
       !T || !P0 || !pt0 || !gL || !gR || !g0 || !qf || !lo || !di || !up ||
-      !rhs || !hb) {
+      !rhs || !hb || !dl) {
+    rc = OR_EINVAL;
+    goto done;
+  }
+  if (p->form == 1 && useb) { /* the print has no bathymetric SI scheme */
     rc = OR_EINVAL;
     goto done;
   }
@@ -312,6 +317,52 @@ int FN(or_stage)(int n, const or_params* p, double tau, const real_t* bin,
     real_t den = h * h + lam * tau * tau;
     phi[i] = 2.0 * lam / 3.0 * md[i] * h / (den * den);
     T[i] = pt0[i] - phi[i] * h;
+    dl[i] = alpha / beta1; /* delta of Sec. 4.2 (mode A only) */
+  }
+
+  if (p->form == 1) {
+    /* Mode A: the remaining printed lines of Sec. 4.2 (eq.
+     * GN_hyp_eq_semi_fully_discrete), flat bottom.  Face values are means of
+     * the two cells; the delta Laplacian of h*eta-dagger carries the weight
+     * lambda tau^2 / dx^2 on those means (with the printed 1/2 the implicit
+     * coefficients at rest would not add up to g h).  Ghost cells as for the
+     * fluxes: periodic wrap, or copies of the boundary cell (transmissive),
+     * which folds the outer coupling of a boundary row into its diagonal. */
+    const real_t r = tau * tau / (dx * dx);
+    for (int i = 0; i < n; ++i) {
+      int im = gidx(i - 1, n, bc), ip = gidx(i + 1, n, bc);
+      real_t bp = 0.5 * (beta[i] + beta[ip]), bm = 0.5 * (beta[i] + beta[im]);
+      real_t dp = 0.5 * (dl[i] + dl[ip]), dm = 0.5 * (dl[i] + dl[im]);
+      /* Delta[h]_i = h_i (1 + r (beta_{i+1/2} + beta_{i-1/2}))
+       *              - r beta_{i+1/2} h_{i+1} - r beta_{i-1/2} h_{i-1} */
+      lo[i] = -r * bm;
+      up[i] = -r * bp;
+      di[i] = 1.0 + r * (bp + bm);
+      /* h-dagger */
+      rhs[i] = ho[i] - tau / (2.0 * dx) * (qd[ip] - qd[im]) +
+               lam * r * (dp * (md[ip] - md[i]) - dm * (md[i] - md[im]));
+      if (bc != 0 && i == 0) { di[i] += lo[i]; lo[i] = 0.0; }
+      if (bc != 0 && i == n - 1) { di[i] += up[i]; up[i] = 0.0; }
+    }
+    {
+      int trc = FN(or_tridiag)(n, bc == 0, lo, di, up, rhs, hb);
+      if (trc) rc = trc;
+    }
+    /* momentum as printed, then the relaxation pair as in the P-form */
+    for (int i = 0; i < n; ++i) {
+      int im = gidx(i - 1, n, bc), ip = gidx(i + 1, n, bc);
+      real_t hbi = hb[i];
+      if (!(RE(hbi) > 0.0)) rc = OR_ENONPHYS;
+      qn[i] = qd[i] - tau / (2.0 * dx) * beta[i] * (hb[ip] - hb[im]) -
+              lam * tau / (2.0 * dx) * dl[i] * (md[ip] - md[im]);
+      mn[i] = md[i] / (1.0 + lam * tau * tau / (hbi * hbi));
+      Wn[i] = Wd[i] - lam * tau * mn[i] / (hbi * hbi);
+      hn[i] = hbi;
+      if (!isfinite(RE(qn[i])) || !isfinite(RE(mn[i])) || !isfinite(RE(Wn[i])) ||
+          !isfinite(RE(hn[i])))
+        rc = OR_ENONPHYS;
+    }
+    goto debug_out;
   }
 
   /* (4) Implicit face force G = [P_R - P_L + (g/2)(hb_L + hb_R) db
@@ -371,6 +422,7 @@ int FN(or_stage)(int n, const or_params* p, double tau, const real_t* bin,
       rc = OR_ENONPHYS;
   }
 
+debug_out:
 #ifndef OR_COMPLEX
   if (dbg) {
 #define OR_CP(dst, src, cnt) \
@@ -391,7 +443,7 @@ done:
   free(bz); free(Fq); free(Fm); free(FW); free(qd); free(md); free(Wd);
   free(beta); free(S); free(phi); free(T); free(P0); free(pt0);
   free(gL); free(gR); free(g0); free(qf); free(lo); free(di); free(up);
-  free(rhs); free(hb);
+  free(rhs); free(hb); free(dl);
   return rc;
 }
 

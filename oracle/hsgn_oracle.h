@@ -34,6 +34,15 @@ typedef struct {
                       Heun's method (flat bottom; cfl applies to |u| + c);
                       2: standard SGN, elliptic-hyperbolic form, Heun's
                       method (flat bottom; lambda unused; m, W untouched) */
+  int form;        /* semi-implicit stage only.  0: the implicit pressure
+                      differenced in conservative P-form (the oracle of the
+                      library).  1: "mode A", the printed lines of Sec. 4.2
+                      (eq. GN_hyp_eq_semi_fully_discrete: the beta
+                      Laplacian Delta[h], the delta Laplacian of h*eta in
+                      h-dagger with weight lambda tau^2/dx^2 on face means,
+                      and the printed momentum update); flat bottom only.
+                      CPU only: it exists to compare the P-form with the
+                      print. */
 } or_params;
 
 /* Optional per-stage intermediates (any pointer may be NULL). Cell arrays
