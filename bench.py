@@ -133,12 +133,26 @@ def per_instance_rate(wl, n_sample, steps, order=2):
     return float(order) * cells * steps / el, el, n_sample
 
 
+def cpu_model():
+    """Model name of the host CPU (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, budget_s=15.0, n_sample=1024, max_steps=200, order=2):
     """The oracle (OpenMP over instances, all host threads) on a bounded
     sample: the first n_sample instances, in chunks of 5 steps until the time
     budget is spent or max_steps are done (past about 370 steps one
     instance of the batched bar loses coercivity, so the sample stays in the
-    range the benchmark times)."""
+    range the benchmark times).  The value is the median of the chunks'
+    rates; the mean over the whole sample is reported beside it."""
+    import numpy as np
     import oracle as O
     sub = wl.subset(range(min(n_sample, wl.n_inst)))
     plist = [O.make_params(**sub.instance(j)[1], order=order) for j in range(sub.n_inst)]
@@ -146,18 +160,24 @@ def cpu_baseline(wl, budget_s=15.0, n_sample=1024, max_steps=200, order=2):
     t = [0.0] * sub.n_inst
     steps, el = 0, 0.0
     chunk = 5
+    rates = []
     while el < budget_s and steps < max_steps:
         t0 = time.perf_counter()
         rc, U, t, st = O.run_batch(sub.offsets, plist, sub.b, U, t, chunk, nthreads=0)
-        el += time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        el += dt
         steps += chunk
+        rates.append(float(order) * sub.n_cells * chunk / dt)
         if rc != 0:
             break
     cores = min(O.max_threads(), sub.n_inst)
-    rate = float(order) * sub.n_cells * steps / el
-    return {"value": rate, "unit": "cell-stage updates/s", "cores": cores, "kind": "oracle",
-            "sample": "first %d instances (%d cells) of the same workload, %d IMEX steps, %.1f s"
-                      % (sub.n_inst, sub.n_cells, steps, el)}
+    return {"value": float(np.median(rates)), "unit": "cell-stage updates/s", "cores": cores,
+            "kind": "oracle", "mean": float(order) * sub.n_cells * steps / el,
+            "runs": len(rates), "cpu_model": cpu_model(),
+            "compiler": "gcc " + " ".join(O.COMPILE_FLAGS),
+            "sample": "first %d instances (%d cells) of the same workload, %d IMEX steps in "
+                      "%d runs of %d steps, %.1f s; value = median run" %
+                      (sub.n_inst, sub.n_cells, steps, len(rates), chunk, el)}
 
 
 def scheme_comparison(si_steps=20):
@@ -273,6 +293,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-instance", action="store_true")
     ap.add_argument("--timed-steps", type=int, default=10)
+    ap.add_argument("--legs", type=int, default=5,
+                    help="timed legs of --steps steps each; the value is their median")
     ap.add_argument("--solver", default="tune", choices=["tune", "auto", "exact", "auto_small"],
                     help="tune: the library times every mode on the workload and keeps the fastest")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -338,13 +360,31 @@ def main():
         print(json.dumps({"probe": True, "copy_bytes": a.numel() * 8, "cells": wl.n_cells}))
         return
 
-    # warmup (also captures the graph)
-    s.run(args.warmup, block=args.block)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.run(args.steps, block=args.block)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    # Every timed leg starts from the initial state (reloaded untimed; the
+    # reload also restarts the buffer rotation, so the captured graph is the
+    # one replayed).  Graph blocks hold at most the timed steps (even: the
+    # rotation repeats every two steps), so the timed steps replay a graph;
+    # fewer than two timed steps run eagerly.
+    init_state = [torch.from_numpy(a).cuda() for a in wl.state()]
+    block = min(args.block, args.steps) & ~1
+    s.run(args.warmup, block=max(block, 2))
+    graph_warm = 0
+    if block >= 2:  # capture the graph outside the timed legs (its steps run untimed)
+        s.set_state(*init_state)
+        s.run(block, block=block)
+        graph_warm = block
+    legs = []
+    for _ in range(max(args.legs, 1)):
+        s.set_state(*init_state)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if block >= 2:
+            s.run(args.steps, block=block)
+        else:
+            s.step(args.steps)
+        torch.cuda.synchronize()
+        legs.append(time.perf_counter() - t0)
+    el = float(np.median(legs))
     rc, flags = s.status()
     if rc != 0:
         print("solver flagged %d instances" % int((flags != 0).sum()), file=sys.stderr)
@@ -354,6 +394,7 @@ def main():
     ms_step = 1e3 * el / args.steps
 
     # per-kernel durations from HIP events on the library's stream
+    s.set_state(*init_state)
     kt = s.step_timed(args.timed_steps)
     sizes = wl.sizes()
     mode = plan["mode"]
@@ -408,7 +449,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "n_inst": wl.n_inst, "cells": wl.n_cells,
-                   "graph_block_steps": args.block, "order": args.order, "scheme": args.scheme,
+                   "graph_block_steps": block if block >= 2 else None,
+                   "timed_legs_ms_per_step": [round(1e3 * x / args.steps, 4) for x in legs],
+                   "graph_warmup_steps": graph_warm, "order": args.order, "scheme": args.scheme,
                    "solver": tuned["kept"] if tuned else args.solver, "autotune": tuned,
                    "windows": plan["windows"], "window_rows": plan["window_rows"],
                    "two_pass_tiles": plan["exact_tiles"]},

@@ -126,9 +126,14 @@ int hsgn_init(hsgn_ctx** ctx, int32_t n_inst, const int64_t* offsets,
 
 /* Load the state (device arrays of offsets[n_inst] doubles).
  *  d_m: NULL means m = h*h (eta = h, the initial data of Sec. 6.3).
- *  d_W: NULL means W = 0.
+ *  d_W: NULL means W = -h^2 u_x (w = -h u_x, the same initial data), with
+ *       the central difference u_x,i = (u_{i+1} - u_{i-1}) / (2 dx) of
+ *       u = q/h: periodic instances wrap, transmissive ones take the
+ *       boundary cell's own u beyond each end.
  *  d_t: device, n_inst times, or NULL for t = 0.
- * Clears the status flags and computes the first step's speed bound. */
+ * Clears the status flags and step counts, computes the first step's speed
+ * bound and plans the solver (synchronises the stream).  Graphs captured by
+ * hsgn_run are kept when the new plan has the same launch configuration. */
 int hsgn_set_state(hsgn_ctx* ctx, const double* d_h, const double* d_q,
                    const double* d_m, const double* d_W, const double* d_t);
 
@@ -160,6 +165,15 @@ int hsgn_run(hsgn_ctx* ctx, int32_t nsteps, int32_t block);
  *    whose rows couple more strongly than that estimate: such an instance
  *    needs HSGN_SOLVER_EXACT.  When L would exceed a quarter window the
  *    instance uses the exact solver.
+ *    Conservation: the sums of h and q telescope only where neighbouring
+ *    cells use one new depth.  At a seam between two windows each takes its
+ *    neighbour's depth from its own halo row, which differs from the other
+ *    window's core value by at most the certified truncation (2^-56 of the
+ *    depth at the core edge, 1/rho times that one row further out, rho the
+ *    decay per row).  So in windowed mode the momentum sum of a periodic,
+ *    flat instance moves per stage and seam by at most
+ *    (tau/dx) beta_max h_max 2^-56 (1 + 1/rho), beyond rounding; the exact
+ *    solver conserves it to rounding.
  *  HSGN_SOLVER_EXACT: two passes per stage for every instance longer than
  *    2048 cells: tiles reduce to two rows each, a per-instance reduced
  *    system is solved, and the tiles finish (no truncation anywhere).
@@ -234,22 +248,32 @@ int hsgn_step_timed(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_coun
  * hsgn_set_state); the reverse stages solve the transposed depth system
  * exactly (no truncation).
  * On return the state is the state after nsteps steps and t is reset to 0.
+ * If an instance is flagged during the forward pass (HSGN_FLAG_*), it was
+ * frozen from that step on and its loss would be that of another map: the
+ * call then returns that flag's error code (precedence and message as for
+ * hsgn_status) before the reverse sweep, with d_loss written and the
+ * gradients not.
  * The recompute of a segment runs on a second stream of the library while
  * the previous segment is swept in reverse (two tape buffers).  The adjoint
  * workspace (22 + 16 K doubles per cell, plus 4 (nsteps/K + 1) doubles per
  * cell of checkpoints) is kept until hsgn_destroy.
- * Synchronises the stream once, after the initial state. */
+ * Synchronises the stream twice: after the initial state (to plan) and
+ * after the forward pass (to read the status flags). */
 int hsgn_adjoint(hsgn_ctx* ctx, int32_t nsteps, int32_t K, int32_t n_gauge,
                  const int32_t* d_gauge, const double* d_target, const double* d_zeta0,
                  double* d_loss, double* d_grad_zeta0, double* d_grad_b);
 
 /* Synchronise the stream and copy the per-instance status bits to host
  * (h_flags: n_inst int32, may be NULL).  Returns HSGN_OK if no instance is
- * flagged, else HSGN_ENONPHYS, HSGN_EWINDOW or HSGN_ENONCOERCIVE. */
+ * flagged, else HSGN_ENONPHYS, HSGN_EWINDOW or HSGN_ENONCOERCIVE (in that
+ * order of precedence); hsgn_last_error then names the first instance with
+ * that flag, the step (counted from the last hsgn_set_state) in which the
+ * flag was raised, its time, and how many instances carry the flag. */
 int hsgn_status(hsgn_ctx* ctx, int32_t* h_flags);
 
-/* Message describing the last failure of this context ("" if none).  The
- * string is owned by the context. */
+/* Message describing the last failure of this context ("" if none): the
+ * failing call and, for a flagged instance, the instance, the step and the
+ * time (see hsgn_status).  The string is owned by the context. */
 const char* hsgn_last_error(const hsgn_ctx* ctx);
 
 /* Library version string. */

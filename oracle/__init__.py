@@ -28,11 +28,15 @@ OK, ENONPHYS, ENONCOERCIVE, EINVAL = 0, 1, 2, 3
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 
 
+# gcc flags of both builds: portable code, no FMA contraction, no fast math,
+# OpenMP over instances
+COMPILE_FLAGS = ["-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                 "-fno-fast-math", "-Wall", "-Wno-unused-label"]
+
+
 def _compile(src, lib):
     tmp = lib + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wno-unused-label",
-           src, "-o", tmp, "-lm"]
+    cmd = ["gcc", *COMPILE_FLAGS, src, "-o", tmp, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, lib)
 

@@ -88,6 +88,7 @@ struct hsgn_ctx {
   unsigned long long* d_smax = nullptr;
   unsigned long long* d_umax = nullptr;
   int32_t* d_status = nullptr;
+  int32_t* d_nstep = nullptr;  // steps taken per instance since the state was loaded
   double *d_rlo = nullptr, *d_rdi = nullptr, *d_rup = nullptr, *d_rrhs = nullptr,
          *d_rx = nullptr, *d_scp = nullptr, *d_sy = nullptr, *d_sv = nullptr, *d_sw = nullptr;
   std::vector<GraphEntry> graphs;
@@ -167,7 +168,8 @@ void free_all(hsgn_ctx* c) {
   for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
   c->graphs.clear();
   void* ptrs[] = {c->d_inst, c->d_tiles_all, c->d_tiles_multi, c->d_multi, c->d_b,
-                  c->d_dt, c->d_t, c->d_smax, c->d_umax, c->d_status, c->d_rlo, c->d_rdi,
+                  c->d_dt, c->d_t, c->d_smax, c->d_umax, c->d_status, c->d_nstep, c->d_rlo,
+                  c->d_rdi,
                   c->d_rup, c->d_rrhs, c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw,
                   c->d_ex_tiles, c->d_ex_tiles_multi, c->d_ex_multi, c->d_win, c->d_hmax,
                   c->d_xtiles, c->d_sgn};
@@ -277,7 +279,7 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
   if (!c->io_skip_dt) {
     mark(HSGN_K_DT, true);
     hipLaunchKernelGGL(hsgn::k_dt, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_inst, c->d_dt,
-                       c->d_t, c->d_smax, c->d_umax, c->d_status);
+                       c->d_t, c->d_smax, c->d_umax, c->d_status, c->d_nstep);
     mark(HSGN_K_DT, false);
   }
   if (c->scheme == HSGN_SCHEME_SGN) {
@@ -721,6 +723,7 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_umax, (size_t)n_inst);
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_hmax, (size_t)n_inst);
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_status, (size_t)n_inst);
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_nstep, (size_t)n_inst);
   double** rp[] = {&c->d_rlo, &c->d_rdi, &c->d_rup, &c->d_rrhs, &c->d_rx,
                    &c->d_scp, &c->d_sy, &c->d_sv, &c->d_sw};
   for (double** p : rp)
@@ -763,7 +766,8 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
         hipMemsetAsync(c->d_dt, 0, n_inst * sizeof(double), c->stream) != hipSuccess ||
         hipMemsetAsync(c->d_smax, 0, n_inst * sizeof(unsigned long long), c->stream) != hipSuccess ||
         hipMemsetAsync(c->d_umax, 0, n_inst * sizeof(unsigned long long), c->stream) != hipSuccess ||
-        hipMemsetAsync(c->d_status, 0, n_inst * sizeof(int32_t), c->stream) != hipSuccess)
+        hipMemsetAsync(c->d_status, 0, n_inst * sizeof(int32_t), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_nstep, 0, n_inst * sizeof(int32_t), c->stream) != hipSuccess)
       rc = fail(c, HSGN_EHIP, "hipMemsetAsync failed");
   }
   // host vectors are freed on return: wait for the uploads
@@ -787,6 +791,8 @@ static int reset_and_plan(hsgn_ctx* c) {
   double** U = c->buf[c->cur];
   const int nb = (c->n_inst + 255) / 256;
   hipLaunchKernelGGL(hsgn::k_fill_i32, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_status,
+                     0);
+  hipLaunchKernelGGL(hsgn::k_fill_i32, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_nstep,
                      0);
   hipLaunchKernelGGL(hsgn::k_fill_u64, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_smax,
                      0ull);
@@ -825,16 +831,19 @@ int hsgn_set_state(hsgn_ctx* c, const double* d_h, const double* d_q, const doub
   int rc = enter(c);
   if (rc) return rc;
   const size_t bytes = (size_t)c->ncell * sizeof(double);
+  // the buffer rotation restarts: a graph captured after an earlier load
+  // replays from the same buffers
+  c->cur = 0;
+  c->nxt = 2;
   double** U = c->buf[c->cur];
   HIPCHK(c, hipMemcpyAsync(U[0], d_h, bytes, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(U[1], d_q, bytes, hipMemcpyDeviceToDevice, c->stream));
   if (d_m) HIPCHK(c, hipMemcpyAsync(U[2], d_m, bytes, hipMemcpyDeviceToDevice, c->stream));
   if (d_W) HIPCHK(c, hipMemcpyAsync(U[3], d_W, bytes, hipMemcpyDeviceToDevice, c->stream));
-  if (!d_m || !d_W) {
-    const int64_t nb = (c->ncell + 255) / 256;
-    hipLaunchKernelGGL(hsgn::k_default_mW, dim3((unsigned)nb), dim3(256), 0, c->stream, c->ncell,
-                       U[0], U[2], U[3], d_m ? 0 : 1, d_W ? 0 : 1);
-  }
+  if (!d_m || !d_W)
+    hipLaunchKernelGGL(hsgn::k_default_mW<256>, dim3(c->ntiles_all), dim3(256), 0, c->stream,
+                       c->d_inst, c->d_tiles_all, U[0], U[1], U[2], U[3], d_m ? 0 : 1,
+                       d_W ? 0 : 1);
   if (d_t) {
     HIPCHK(c, hipMemcpyAsync(c->d_t, d_t, c->n_inst * sizeof(double), hipMemcpyDeviceToDevice,
                              c->stream));
@@ -1052,30 +1061,58 @@ int hsgn_autotune(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_mode) {
   return leave(c);
 }
 
-int hsgn_status(hsgn_ctx* c, int32_t* h_flags) {
-  if (!c) return HSGN_EINVAL;
-  std::vector<int32_t> f(c->n_inst);
+}  // extern "C"
+
+namespace {
+
+// Read the status flags and step counts (synchronises the stream); on a
+// flagged instance set the context's message (naming the instance, the step
+// in which the flag was raised and the time reached) and return its code.
+int read_status(hsgn_ctx* c, const char* what, int32_t* h_flags) {
+  std::vector<int32_t> f(c->n_inst), ns(c->n_inst);
+  std::vector<double> t(c->n_inst);
   HIPCHK(c, hipMemcpyAsync(f.data(), c->d_status, c->n_inst * sizeof(int32_t),
                            hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(ns.data(), c->d_nstep, c->n_inst * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(t.data(), c->d_t, c->n_inst * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (h_flags) std::memcpy(h_flags, f.data(), f.size() * sizeof(int32_t));
   int any = 0;
   for (int j = 0; j < c->n_inst; ++j) any |= f[j];
-  if (any & hsgn::kFlagNonPhys) {
+  struct Kind {
+    int32_t bit;
+    int code;
+    const char* text;
+  };
+  const Kind kinds[3] = {
+      {hsgn::kFlagNonPhys, HSGN_ENONPHYS, "h <= 0 or a non-finite value"},
+      {hsgn::kFlagWindow, HSGN_EWINDOW,
+       "window truncation not negligible (use HSGN_SOLVER_EXACT)"},
+      {hsgn::kFlagNonCoercive, HSGN_ENONCOERCIVE, "beta <= 0 (coercivity lost)"}};
+  for (const Kind& k : kinds) {
+    if (!(any & k.bit)) continue;
+    int count = 0, first = -1;
     for (int j = 0; j < c->n_inst; ++j)
-      if (f[j] & hsgn::kFlagNonPhys) return fail(c, HSGN_ENONPHYS, "instance %d: h <= 0 or non-finite value", j);
-  }
-  if (any & hsgn::kFlagWindow) {
-    for (int j = 0; j < c->n_inst; ++j)
-      if (f[j] & hsgn::kFlagWindow)
-        return fail(c, HSGN_EWINDOW,
-                    "instance %d: window truncation not negligible; use HSGN_SOLVER_EXACT", j);
-  }
-  if (any & hsgn::kFlagNonCoercive) {
-    for (int j = 0; j < c->n_inst; ++j)
-      if (f[j] & hsgn::kFlagNonCoercive) return fail(c, HSGN_ENONCOERCIVE, "instance %d: beta <= 0", j);
+      if (f[j] & k.bit) {
+        if (first < 0) first = j;
+        ++count;
+      }
+    return fail(c, k.code, "%s: instance %d: %s in step %d after its state was loaded "
+                "(t = %.6g); %d instance(s) flagged",
+                what, first, k.text, ns[first], t[first], count);
   }
   return HSGN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hsgn_status(hsgn_ctx* c, int32_t* h_flags) {
+  if (!c) return HSGN_EINVAL;
+  return read_status(c, "hsgn_status", h_flags);
 }
 
 const char* hsgn_last_error(const hsgn_ctx* c) { return c ? c->err.c_str() : "null context"; }
@@ -1321,6 +1358,11 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
     hipLaunchKernelGGL(k_gauge_fwd, dim3(nbi), dim3(256), 0, c->stream, c->n_inst, c->d_inst, ng,
                        d_gauge, d_target, nsteps, s, hnew, d_loss, a.res);
   }
+  // A flagged instance is frozen (dt = 0) from the step of its flag on; its
+  // loss and gradients would belong to another map, and the segment
+  // recompute would reuse that dt = 0: report it instead.
+  rc = read_status(c, "hsgn_adjoint", nullptr);
+  if (rc) return rc;
   if (!grad) {  // loss only
     hipLaunchKernelGGL(k_fill_f64, dim3(nbi), dim3(256), 0, c->stream, (int64_t)c->n_inst,
                        c->d_t, 0.0);

@@ -833,9 +833,13 @@ __global__ __launch_bounds__(NT) void k_rsolve(const InstDesc* __restrict__ inst
 // Time step per instance from the speed bound of the current state
 // (CFL on |u| + sqrt(g h), material-CFL cap, t_end clamp).  Resets the
 // accumulators for the next step.
+// (nstep counts the steps each instance has taken since its state was
+// loaded: a flagged instance stops counting, so its count names the step in
+// which the flag was raised)
 __global__ void k_dt(int n_inst, const InstDesc* __restrict__ inst, double* __restrict__ dt,
                      double* __restrict__ tt, unsigned long long* __restrict__ smax,
-                     unsigned long long* __restrict__ umax, const int32_t* __restrict__ status) {
+                     unsigned long long* __restrict__ umax, const int32_t* __restrict__ status,
+                     int32_t* __restrict__ nstep) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_inst) return;
   const InstDesc I = inst[j];
@@ -856,6 +860,7 @@ __global__ void k_dt(int n_inst, const InstDesc* __restrict__ inst, double* __re
     else if (t0 + d > I.t_end) d = I.t_end - t0;
   }
   if (!(d > 0.0) || !isfinite(d)) d = 0.0;
+  if (d > 0.0) nstep[j] += 1;
   dt[j] = d;
   tt[j] = t0 + d;
   smax[j] = 0ull;
@@ -896,12 +901,39 @@ __global__ __launch_bounds__(NT) void k_speed(const InstDesc* __restrict__ inst,
 }
 
 // m = h^2 and W = 0 where the caller gave none.
-__global__ void k_default_mW(int64_t ncell, const double* __restrict__ h, double* __restrict__ m,
-                             double* __restrict__ W, int set_m, int set_W) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ncell) return;
-  if (set_m) m[i] = h[i] * h[i];
-  if (set_W) W[i] = 0.0;
+// Default auxiliary variables of a loaded state (initial data of Sec. 6.3:
+// eta = h and w = -h u_x): m = h^2 and W = -h^2 u_x with the central
+// difference u_x,i = (u_{i+1} - u_{i-1}) / (2 dx) of u = q/h; periodic
+// instances wrap, transmissive ones use a copy of the boundary cell beyond
+// each end.  One workgroup per two-pass tile.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_default_mW(const InstDesc* __restrict__ inst,
+                                                   const TileDesc* __restrict__ tiles,
+                                                   const double* __restrict__ h,
+                                                   const double* __restrict__ q,
+                                                   double* __restrict__ m, double* __restrict__ W,
+                                                   int set_m, int set_W) {
+  const TileDesc td = tiles[blockIdx.x];
+  const InstDesc I = inst[td.inst];
+  for (int k = threadIdx.x; k < td.len; k += NT) {
+    const int i = td.start + k;
+    const int64_t gi = I.off + i;
+    const double hi = h[gi];
+    if (set_m) m[gi] = hi * hi;
+    if (set_W) {
+      int im = i - 1, ip = i + 1;
+      if (I.bc == 0) {
+        if (im < 0) im += I.n;
+        if (ip >= I.n) ip -= I.n;
+      } else {
+        if (im < 0) im = 0;
+        if (ip >= I.n) ip = I.n - 1;
+      }
+      const double um = q[I.off + im] / h[I.off + im];
+      const double up = q[I.off + ip] / h[I.off + ip];
+      W[gi] = -hi * hi * (up - um) / (2.0 * I.dx);
+    }
+  }
 }
 
 // Fill (used instead of memset so that the calls stay capturable).

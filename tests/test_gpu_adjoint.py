@@ -316,6 +316,43 @@ def test_adjoint_rejects_bad_input(mixed):
                 mixed["K"])
 
 
+def test_adjoint_reports_an_instance_flagged_in_the_forward_pass(mixed):
+    """An instance whose initial surface lies below the bed at one cell
+    (h < 0) is flagged in the first step and frozen; its gradient would be
+    that of another map, so hsgn_adjoint returns HSGN_ENONPHYS before the
+    reverse sweep and names the instance and the step."""
+    hs = _hsgn()
+    wl = mixed["wl"]
+    z_bad = mixed["z_all"].copy()
+    j = 1
+    o0 = int(wl.offsets[j])
+    z_bad[o0 + 37] = -0.2  # below the bed: negative depth
+    s = hs.Solver.from_workload(wl)
+    try:
+        dev = "cuda"
+        with pytest.raises(hs.HsgnError) as err:
+            s.adjoint(mixed["nsteps"], mixed["K"], torch.from_numpy(mixed["gauges"]).to(dev),
+                      torch.from_numpy(mixed["targets"]).to(dev),
+                      torch.from_numpy(z_bad).to(dev))
+        msg = str(err.value)
+        note("  " + msg)
+        assert "(%d)" % hs.HSGN_ENONPHYS in msg
+        assert "instance %d:" % j in msg and "in step 1 " in msg, msg
+        with pytest.raises(hs.HsgnError):  # the loss-only path reports it too
+            s.adjoint(mixed["nsteps"], mixed["K"], torch.from_numpy(mixed["gauges"]).to(dev),
+                      torch.from_numpy(mixed["targets"]).to(dev),
+                      torch.from_numpy(z_bad).to(dev), grad=False)
+        # the context still works: the healthy surface gives the fixture's loss
+        loss, gz, _ = s.adjoint(mixed["nsteps"], mixed["K"],
+                                torch.from_numpy(mixed["gauges"]).to(dev),
+                                torch.from_numpy(mixed["targets"]).to(dev),
+                                torch.from_numpy(mixed["z_all"]).to(dev))
+        assert np.array_equal(loss.cpu().numpy(), mixed["loss"])
+        assert np.array_equal(gz.cpu().numpy(), mixed["gz"])
+    finally:
+        s.close()
+
+
 # ---------------------------------------------------------------------------
 # The gradient workload at full size: 1024 instances x 4096 cells, 200 steps,
 # checkpoints every 20 steps, in the configuration the benchmark times.
