@@ -263,6 +263,39 @@ int hsgn_adjoint(hsgn_ctx* ctx, int32_t nsteps, int32_t K, int32_t n_gauge,
                  const int32_t* d_gauge, const double* d_target, const double* d_zeta0,
                  double* d_loss, double* d_grad_zeta0, double* d_grad_b);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation): the
+ * work of hsgn_init + hsgn_set_state + hsgn_step(nsteps) + hsgn_get_state in
+ * one call that allocates nothing.  The library's buffers (the U^(1) and
+ * stage-output state copies, descriptors, plan lists, per-instance values,
+ * reduced rows) are carved from one static device array of about 66 MiB,
+ * which every GPU the library runs on holds until the process ends; the
+ * kernels are those of hsgn_step and the results are bitwise those of the
+ * context path with the same solver mode.
+ *  offsets, params, d_b: as for hsgn_init (host, host, device or NULL);
+ *    semi-implicit scheme only (scheme 0), order 1 or 2.
+ *  d_h, d_q, d_m, d_W: device, offsets[n_inst] doubles each, all required:
+ *    the state, advanced in place by nsteps steps.
+ *  d_t: device, n_inst times (advanced in place), or NULL for t = 0.
+ *  solver: HSGN_SOLVER_AUTO, HSGN_SOLVER_EXACT or HSGN_SOLVER_AUTO_SMALL.
+ *  hip_stream: the stream every copy and kernel is enqueued on.
+ *  h_flags: host, n_inst int32 status bits after the steps, or NULL.
+ *  h_msg: host, HSGN_MSG_LEN chars or NULL: the error message ("" on
+ *    success), as hsgn_last_error gives it for a context.
+ * Limits: at most HSGN_NOALLOC_MAX_CELLS cells and HSGN_NOALLOC_MAX_INST
+ * instances (else HSGN_EINVAL, before anything is enqueued).  Returns as
+ * hsgn_status after the steps (a flagged instance: its code).  Synchronises
+ * the stream (to plan, and at the end).  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (from several host threads, or
+ * on several streams) race and must be serialised by the caller. */
+#define HSGN_NOALLOC_MAX_CELLS (1 << 20)
+#define HSGN_NOALLOC_MAX_INST 4096
+#define HSGN_MSG_LEN 512
+int hsgn_step_noalloc(int32_t n_inst, const int64_t* offsets, const hsgn_params* params,
+                      const double* d_b, double* d_h, double* d_q, double* d_m, double* d_W,
+                      double* d_t, int32_t nsteps, int32_t solver, void* hip_stream,
+                      int32_t* h_flags, char* h_msg);
+
 /* Synchronise the stream and copy the per-instance status bits to host
  * (h_flags: n_inst int32, may be NULL).  Returns HSGN_OK if no instance is
  * flagged, else HSGN_ENONPHYS, HSGN_EWINDOW or HSGN_ENONCOERCIVE (in that

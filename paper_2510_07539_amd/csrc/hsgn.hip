@@ -16,6 +16,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -96,6 +97,7 @@ struct hsgn_ctx {
   // that reproduces it (same counts, same descriptor buffers) keeps them
   std::vector<uintptr_t> graph_sig;
   std::string err;
+  bool no_alloc = false;  // hsgn_step_noalloc: every device buffer is carved from the static scratch
   // host copy of the full two-pass tiling (all instances)
   std::vector<TileDesc> h_tiles_all;
   std::vector<int32_t> h_ntiles;
@@ -469,6 +471,9 @@ int halo_width(const hsgn_params& p, double smax, double hmax, double tau_factor
 
 template <typename T>
 int upload(hsgn_ctx* c, T** d, size_t* cap, const std::vector<T>& h) {
+  if (h.size() > *cap && c->no_alloc)
+    return fail(c, HSGN_EINVAL, "plan list of %zu entries exceeds the static scratch (%zu)",
+                h.size(), *cap);
   if (h.size() > *cap) {
     if (*d) hipFree(*d);
     *d = nullptr;
@@ -586,28 +591,28 @@ int make_plan(hsgn_ctx* c) {
   return HSGN_OK;
 }
 
-}  // namespace
+// Host layout of a batch (shared by hsgn_init and hsgn_step_noalloc): the
+// parameters checked, the per-instance descriptors and the two-pass tiling
+// (tiles of at most kTileMax cells), with the context's counts set from them.
+struct Layout {
+  std::vector<InstDesc> inst;
+  std::vector<TileDesc> tall, tmulti, xt;
+  std::vector<int32_t> multi;
+};
 
-extern "C" {
-
-const char* hsgn_version(void) { return "hsgn-gfx950 0.2"; }
-
-int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn_params* params,
-              const double* d_b, void* hip_stream) {
-  if (!out) return HSGN_EINVAL;
-  *out = nullptr;
-  if (n_inst <= 0 || !offsets || !params) return HSGN_EINVAL;
-  hsgn_ctx* c = new (std::nothrow) hsgn_ctx();
-  if (!c) return HSGN_ENOMEM;
+int build_layout(hsgn_ctx* c, int32_t n_inst, const int64_t* offsets, const hsgn_params* params,
+                 const double* d_b, Layout& lay) {
   int rc = HSGN_OK;
   c->n_inst = n_inst;
   c->offsets.assign(offsets, offsets + n_inst + 1);
   c->params.assign(params, params + n_inst);
-  c->user_stream = (hipStream_t)hip_stream;
   if (offsets[0] != 0) rc = fail(c, HSGN_EINVAL, "offsets[0] must be 0");
-  std::vector<InstDesc> inst(n_inst);
-  std::vector<TileDesc> tall, tmulti, xt;
-  std::vector<int32_t> multi;
+  std::vector<InstDesc>& inst = lay.inst;
+  std::vector<TileDesc>& tall = lay.tall;
+  std::vector<TileDesc>& tmulti = lay.tmulti;
+  std::vector<TileDesc>& xt = lay.xt;
+  std::vector<int32_t>& multi = lay.multi;
+  inst.assign(n_inst, InstDesc{});
   int64_t red = 0;
   for (int j = 0; j < n_inst && rc == HSGN_OK; ++j) {
     const int64_t n = offsets[j + 1] - offsets[j];
@@ -692,6 +697,32 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   c->n_multi_inst = (int)multi.size();
   c->any_multi = c->n_multi_inst > 0;
   c->red_total = red;
+  c->nxtiles = (int)xt.size();
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hsgn_version(void) { return "hsgn-gfx950 0.2"; }
+
+int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn_params* params,
+              const double* d_b, void* hip_stream) {
+  if (!out) return HSGN_EINVAL;
+  *out = nullptr;
+  if (n_inst <= 0 || !offsets || !params) return HSGN_EINVAL;
+  hsgn_ctx* c = new (std::nothrow) hsgn_ctx();
+  if (!c) return HSGN_ENOMEM;
+  c->user_stream = (hipStream_t)hip_stream;
+  Layout lay;
+  int rc = build_layout(c, n_inst, offsets, params, d_b, lay);
+  const std::vector<InstDesc>& inst = lay.inst;
+  const std::vector<TileDesc>& tall = lay.tall;
+  const std::vector<TileDesc>& tmulti = lay.tmulti;
+  const std::vector<TileDesc>& xt = lay.xt;
+  const std::vector<int32_t>& multi = lay.multi;
+  const int64_t red = c->red_total;
   if (rc == HSGN_OK) {
     if (c->user_stream) {
       c->stream = c->user_stream;
@@ -712,7 +743,6 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_tiles_multi, tmulti.size());
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_xtiles, xt.size());
   if (rc == HSGN_OK && c->scheme == HSGN_SCHEME_SGN) rc = dmalloc(c, &c->d_sgn, 5 * nc);
-  c->nxtiles = (int)xt.size();
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_multi, multi.size());
   for (int i = 0; i < 3 && rc == HSGN_OK; ++i)
     for (int f = 0; f < 4 && rc == HSGN_OK; ++f) rc = dmalloc(c, &c->buf[i][f], nc);
@@ -1479,4 +1509,178 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
                      0.0);
   HIPCHK(c, hipGetLastError());
   return leave(c);
+}
+
+// ---------------------------------------------------------------------------
+// hsgn_step_noalloc: the steps of hsgn_step on the caller's arrays with every
+// device buffer the library needs carved from one static array (one copy
+// per GPU, kept until the process ends), so that the call allocates nothing.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kNaCells = HSGN_NOALLOC_MAX_CELLS;
+constexpr int64_t kNaInst = HSGN_NOALLOC_MAX_INST;
+// two-pass tiles of at most kTileMax cells: at most one partial tile per instance
+constexpr int64_t kNaTiles = kNaInst + kNaCells / kTileMax;
+// windows per instance: at most 3 plus one per core of at least half a
+// 2048-row window minus 8 rows (the halo is at most a quarter window)
+constexpr int64_t kNaWins = 3 * kNaInst + kNaCells / 1016 + 1;
+constexpr size_t na_round(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kNaBytes =
+    na_round(8 * kNaCells * sizeof(double)) +                   // U^(1), U^{n+1}
+    na_round(kNaInst * sizeof(InstDesc)) +                      // instance descriptors
+    4 * na_round(kNaTiles * sizeof(TileDesc)) +                 // tilings and plan lists
+    2 * na_round(kNaInst * sizeof(int32_t)) +                   // multi-tile instance lists
+    na_round(kNaWins * sizeof(WinDesc)) +                       // window descriptors
+    5 * na_round(kNaInst * sizeof(double)) +                    // dt, t, speed and depth maxima
+    2 * na_round(kNaInst * sizeof(int32_t)) +                   // status, step counts
+    9 * na_round(2 * kNaTiles * sizeof(double));                // reduced rows and solver scratch
+
+}  // namespace
+
+// The static workspace.  Host code never uses this name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+std::mutex na_mutex;
+constexpr int kNaMaxDevices = 64;
+unsigned char* na_ptr[kNaMaxDevices] = {};
+
+// Device address of this device's copy of the static workspace.
+int na_scratch(hsgn_ctx* c, unsigned char** out) {
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNaMaxDevices)
+    return fail(c, HSGN_EINVAL, "device %d beyond the %d this entry point supports", dev,
+                kNaMaxDevices);
+  std::lock_guard<std::mutex> lock(na_mutex);
+  if (!na_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(c, HSGN_EHIP, "hipGetSymbolAddress returned a null address");
+    na_ptr[dev] = (unsigned char*)p;
+  }
+  *out = na_ptr[dev];
+  return HSGN_OK;
+}
+
+int na_run(hsgn_ctx* c, int32_t n_inst, const int64_t* offsets, const hsgn_params* params,
+           const double* d_b, double* const* U, double* d_t, int32_t nsteps, int32_t solver,
+           int32_t* h_flags) {
+  Layout lay;
+  int rc = build_layout(c, n_inst, offsets, params, d_b, lay);
+  if (rc) return rc;
+  if (c->ncell > kNaCells)
+    return fail(c, HSGN_EINVAL, "%lld cells exceed the static scratch (at most %lld cells)",
+                (long long)c->ncell, (long long)kNaCells);
+  if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
+    return fail(c, HSGN_EINVAL, "only the semi-implicit step (scheme 0) runs without allocation");
+  unsigned char* base = nullptr;
+  rc = na_scratch(c, &base);
+  if (rc) return rc;
+  // carve the buffers; every one is written before it is read, or cleared below
+  size_t pos = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base + pos;
+    pos += na_round(bytes);
+    return (void*)p;
+  };
+  double* st = (double*)take(8 * kNaCells * sizeof(double));
+  for (int f = 0; f < 4; ++f) {
+    c->buf[0][f] = U[f];  // U^n: the caller's arrays
+    c->buf[1][f] = st + (size_t)f * kNaCells;
+    c->buf[2][f] = st + (size_t)(4 + f) * kNaCells;
+  }
+  c->d_inst = (InstDesc*)take(kNaInst * sizeof(InstDesc));
+  c->d_tiles_all = (TileDesc*)take(kNaTiles * sizeof(TileDesc));
+  c->d_tiles_multi = (TileDesc*)take(kNaTiles * sizeof(TileDesc));
+  c->d_ex_tiles = (TileDesc*)take(kNaTiles * sizeof(TileDesc));
+  c->d_ex_tiles_multi = (TileDesc*)take(kNaTiles * sizeof(TileDesc));
+  c->cap_ex_tiles = c->cap_ex_tiles_multi = (size_t)kNaTiles;
+  c->d_multi = (int32_t*)take(kNaInst * sizeof(int32_t));
+  c->d_ex_multi = (int32_t*)take(kNaInst * sizeof(int32_t));
+  c->cap_ex_multi = (size_t)kNaInst;
+  c->d_win = (WinDesc*)take(kNaWins * sizeof(WinDesc));
+  c->cap_win = (size_t)kNaWins;
+  c->d_dt = (double*)take(kNaInst * sizeof(double));
+  double* t_scr = (double*)take(kNaInst * sizeof(double));
+  c->d_t = d_t ? d_t : t_scr;
+  c->d_smax = (unsigned long long*)take(kNaInst * sizeof(double));
+  c->d_umax = (unsigned long long*)take(kNaInst * sizeof(double));
+  c->d_hmax = (unsigned long long*)take(kNaInst * sizeof(double));
+  c->d_status = (int32_t*)take(kNaInst * sizeof(int32_t));
+  c->d_nstep = (int32_t*)take(kNaInst * sizeof(int32_t));
+  double** rp[] = {&c->d_rlo, &c->d_rdi, &c->d_rup, &c->d_rrhs, &c->d_rx,
+                   &c->d_scp, &c->d_sy, &c->d_sv, &c->d_sw};
+  for (double** q : rp) *q = (double*)take(2 * kNaTiles * sizeof(double));
+  if (pos > kNaBytes || (int64_t)lay.tall.size() > kNaTiles || c->red_total > 2 * kNaTiles)
+    return fail(c, HSGN_EINVAL, "the layout exceeds the static scratch");
+  c->d_b = (double*)d_b;  // read only where an instance has a bed
+  c->d_xtiles = nullptr;
+  c->nxtiles = 0;
+  c->cur = 0;
+  c->s1 = 1;
+  c->nxt = 2;
+  c->solver = solver == HSGN_SOLVER_EXACT ? HSGN_SOLVER_EXACT : HSGN_SOLVER_AUTO;
+  c->win_nt = solver == HSGN_SOLVER_AUTO_SMALL ? 256 : 512;
+  auto up = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (!bytes) return HSGN_OK;
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    return HSGN_OK;
+  };
+  rc = up(c->d_inst, lay.inst.data(), lay.inst.size() * sizeof(InstDesc));
+  if (!rc) rc = up(c->d_tiles_all, lay.tall.data(), lay.tall.size() * sizeof(TileDesc));
+  if (!rc) rc = up(c->d_tiles_multi, lay.tmulti.data(), lay.tmulti.size() * sizeof(TileDesc));
+  if (!rc) rc = up(c->d_multi, lay.multi.data(), lay.multi.size() * sizeof(int32_t));
+  if (rc) return rc;
+  if (!d_t) {
+    const unsigned nb = (unsigned)((n_inst + 255) / 256);
+    hipLaunchKernelGGL(k_fill_f64, dim3(nb), dim3(256), 0, c->stream, (int64_t)n_inst, c->d_t, 0.0);
+  }
+  // flags, step counts and speed bounds cleared, the plan made (this
+  // synchronises the stream, so the uploads above are complete on return)
+  rc = reset_and_plan(c);
+  if (rc) return rc;
+  for (int s = 0; s < nsteps && rc == HSGN_OK; ++s) rc = enqueue_step(c);
+  if (rc) return rc;
+  if (c->cur != 0) {  // odd step count: the state is in the scratch
+    const size_t bytes = (size_t)c->ncell * sizeof(double);
+    for (int f = 0; f < 4; ++f)
+      HIPCHK(c, hipMemcpyAsync(U[f], c->buf[c->cur][f], bytes, hipMemcpyDeviceToDevice,
+                               c->stream));
+  }
+  return read_status(c, "hsgn_step_noalloc", h_flags);
+}
+
+}  // namespace
+
+extern "C" int hsgn_step_noalloc(int32_t n_inst, const int64_t* offsets,
+                                 const hsgn_params* params, const double* d_b, double* d_h,
+                                 double* d_q, double* d_m, double* d_W, double* d_t,
+                                 int32_t nsteps, int32_t solver, void* hip_stream,
+                                 int32_t* h_flags, char* h_msg) {
+  if (h_msg) h_msg[0] = '\0';
+  hsgn_ctx c;  // host bookkeeping only; its device pointers all point into the scratch
+  c.no_alloc = true;
+  c.user_stream = c.stream = (hipStream_t)hip_stream;
+  int rc = HSGN_OK;
+  if (n_inst <= 0 || !offsets || !params || !d_h || !d_q || !d_m || !d_W || nsteps < 0)
+    rc = fail(&c, HSGN_EINVAL, "hsgn_step_noalloc: bad arguments");
+  else if (n_inst > kNaInst)
+    rc = fail(&c, HSGN_EINVAL, "hsgn_step_noalloc: %d instances exceed the static scratch "
+              "(at most %lld)", n_inst, (long long)kNaInst);
+  else if (solver != HSGN_SOLVER_AUTO && solver != HSGN_SOLVER_EXACT &&
+           solver != HSGN_SOLVER_AUTO_SMALL)
+    rc = fail(&c, HSGN_EINVAL, "hsgn_step_noalloc: unknown solver mode %d", solver);
+  else {
+    double* U[4] = {d_h, d_q, d_m, d_W};
+    rc = na_run(&c, n_inst, offsets, params, d_b, U, d_t, nsteps, solver, h_flags);
+  }
+  if (rc && h_msg) {
+    std::strncpy(h_msg, c.err.c_str(), HSGN_MSG_LEN - 1);
+    h_msg[HSGN_MSG_LEN - 1] = '\0';
+  }
+  return rc;
 }

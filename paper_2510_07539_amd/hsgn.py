@@ -74,6 +74,10 @@ def lib():
         L.hsgn_version.restype = C.c_char_p
         L.hsgn_destroy.restype = None
         L.hsgn_destroy.argtypes = [vp]
+        L.hsgn_step_noalloc.restype = C.c_int
+        L.hsgn_step_noalloc.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(HsgnParams),
+                                        dp, dp, dp, dp, dp, dp, C.c_int32, C.c_int32, vp,
+                                        C.POINTER(C.c_int32), C.c_char_p]
         _lib = L
     return _lib
 
@@ -103,11 +107,7 @@ class Solver:
         offs = np.ascontiguousarray(offsets, dtype=np.int64)
         self.n_inst = len(offs) - 1
         self.ncell = int(offs[-1])
-        pa = (HsgnParams * self.n_inst)()
-        for j, p in enumerate(params):
-            pa[j] = HsgnParams(p["g"], p["lam"], p["dx"], p["cfl"], p["mcfl"], p["dt_fixed"],
-                               p["t_end"], int(p["bc"]), int(p["has_b"]), int(p.get("order", 2)),
-                               int(p.get("scheme", SCHEME_SEMI_IMPLICIT)))
+        pa = _params_array(params)
         if b is not None:
             b = b.to(self.device, torch.float64).contiguous()
         self._b = b
@@ -235,6 +235,37 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+MSG_LEN = 512  # HSGN_MSG_LEN
+NOALLOC_MAX_CELLS, NOALLOC_MAX_INST = 1 << 20, 4096
+
+
+def _params_array(params):
+    pa = (HsgnParams * len(params))()
+    for j, p in enumerate(params):
+        pa[j] = HsgnParams(p["g"], p["lam"], p["dx"], p["cfl"], p["mcfl"], p["dt_fixed"],
+                           p["t_end"], int(p["bc"]), int(p["has_b"]), int(p.get("order", 2)),
+                           int(p.get("scheme", SCHEME_SEMI_IMPLICIT)))
+    return pa
+
+
+def step_noalloc(offsets, params, b, h, q, m, W, t=None, nsteps=1, solver="auto", stream=None):
+    """hsgn_step_noalloc: advance the state tensors (h, q, m, W; t if given)
+    in place by nsteps semi-implicit steps without any device allocation by
+    the library.  Returns (rc, flags, message)."""
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_inst = len(offs) - 1
+    pa = _params_array(params)
+    flags = np.zeros(n_inst, dtype=np.int32)
+    msg = C.create_string_buffer(MSG_LEN)
+    s = stream if stream is not None else torch.cuda.current_stream(h.device)
+    m_ = SOLVERS[solver] if isinstance(solver, str) else int(solver)
+    rc = lib().hsgn_step_noalloc(n_inst, offs.ctypes.data_as(C.POINTER(C.c_int64)), pa, _ptr(b),
+                                 _ptr(h), _ptr(q), _ptr(m), _ptr(W), _ptr(t), int(nsteps), m_,
+                                 C.c_void_p(s.cuda_stream),
+                                 flags.ctypes.data_as(C.POINTER(C.c_int32)), msg)
+    return rc, flags, msg.value.decode()
 
 
 class HsgnAdjointFn(torch.autograd.Function):
