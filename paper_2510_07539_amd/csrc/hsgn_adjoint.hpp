@@ -172,7 +172,7 @@ __device__ __forceinline__ void face_flux(const TC& I, const LT& L, int f, doubl
   const double mL = m0 + 0.25 * (m1 - mm), mR = m1 - 0.25 * (m2 - m0);
   const double WL = w0 + 0.25 * (w1 - wm), WR = w1 - 0.25 * (w2 - w0);
   const double uL = qL * frcp(hL), uR = qR * frcp(hR);
-  const double sL = fabs(uL) + sqrt(I.g * hL), sR = fabs(uR) + sqrt(I.g * hR);
+  const double sL = fabs(uL) + fsqrt(I.g * hL), sR = fabs(uR) + fsqrt(I.g * hR);
   const double a = sL >= sR ? sL : sR;
   double jm = mR - mL;
   if (I.has_b) {
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
     const double WL = wv[1] + 0.25 * (wv[2] - wv[0]), WR = wv[2] - 0.25 * (wv[3] - wv[1]);
     const double ihL = frcp(hL), ihR = frcp(hR);
     const double uL = qL * ihL, uR = qR * ihR;
-    const double gsL = sqrt(I.g * hL), gsR = sqrt(I.g * hR);
+    const double gsL = fsqrt(I.g * hL), gsR = fsqrt(I.g * hR);
     const double sL = fabs(uL) + gsL, sR = fabs(uR) + gsR;
     const bool leftmax = sL >= sR;
     const double a = leftmax ? sL : sR;

@@ -56,6 +56,23 @@ __device__ __forceinline__ double frcp(double x) {
   return r;
 }
 
+// Square root of a positive normal operand: hardware reciprocal square-root
+// estimate (about 2^-24 relative), one Goldschmidt step (2^-48) and one
+// residual correction (about 1 ulp).  The operands here are g h with h
+// checked positive, so the library's scaling for tiny and special operands
+// is not needed; a non-positive h yields a NaN, on an instance that is
+// flagged anyway.
+__device__ __forceinline__ double fsqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = 0.5 * y;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 template <bool BED>
 __device__ __forceinline__ Flux face_flux_fast(const Cell& cm, const Cell& c0, const Cell& c1,
                                                const Cell& c2, double bm, double b0, double b1,
@@ -71,8 +88,8 @@ __device__ __forceinline__ Flux face_flux_fast(const Cell& cm, const Cell& c0, c
   bad |= !(hL > 0.0) || !(hR > 0.0);
   const double uL = qL * frcp(hL);
   const double uR = qR * frcp(hR);
-  const double sL = fabs(uL) + sqrt(g * hL);
-  const double sR = fabs(uR) + sqrt(g * hR);
+  const double sL = fabs(uL) + fsqrt(g * hL);
+  const double sR = fabs(uR) + fsqrt(g * hR);
   const double a = fmax(sL, sR);
   double jm = mR - mL;
   if (BED) {
@@ -251,6 +268,13 @@ struct WinLds {
       double beta[2][NT], S[2][NT], qd[2][NT], phi[2][NT], T[2][NT], b[2][NT];
     } nb;
   } u;
+  // The record exchange (nb) and the level-1 system (sys) reuse the storage
+  // of the staging buffers e and o, and must not reach the bed or the old
+  // depth, which are still read after them.
+  static_assert(sizeof(Lds<NT>) <= 2 * SP * sizeof(double) &&
+                    12 * NT * sizeof(double) <= 2 * SP * sizeof(double),
+                "the level-1 system and the record exchange must fit in the staging buffers "
+                "e and o");
   double misc[16];
   // inputs of the outer rows of truncated edges (window rows -1 and wl):
   // U_E of five staged cells, the row's old state, the bed (side 0 left,
@@ -502,8 +526,8 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       const double qR = xq[f + 2] - P.sl * (xq[f + 3] - xq[f + 1]);
       uL[f] = qL * frcp(hL[f]);
       uR[f] = qR * frcp(hR[f]);
-      const double sL = fabs(uL[f]) + sqrt(P.g * hL[f]);
-      const double sR = fabs(uR[f]) + sqrt(P.g * hR[f]);
+      const double sL = fabs(uL[f]) + fsqrt(P.g * hL[f]);
+      const double sR = fabs(uR[f]) + fsqrt(P.g * hR[f]);
       ap[f] = fmax(sL, sR);
       Fq[f] = 0.5 * (qL * uL[f] + qR * uR[f] - ap[f] * (qR - qL));
     }
@@ -862,7 +886,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
         on[3][j] = Wn;
         if (STAGE == 2) {
           const double u = fabs(qn * ih);
-          smax = fmax(smax, u + sqrt(P.g * h));
+          smax = fmax(smax, u + fsqrt(P.g * h));
           umax = fmax(umax, u);
         }
       }
