@@ -192,6 +192,7 @@ __device__ __forceinline__ Flux face_flux(const Cell& cm, const Cell& c0, const 
 struct PhysC {
   double g, lam, dx, tau, tdx, lt2, rr, tdx2;
   double sl;  // reconstruction slope factor (1/4, or 0 for the first-order scheme)
+  double lam3, lam23;  // lambda/3 and 2 lambda/3 (set by the window kernel only)
 };
 
 // Dagger updates (Sec. 4.2, first three lines, with tau for dt) and frozen

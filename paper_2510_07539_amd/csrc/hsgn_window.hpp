@@ -45,6 +45,16 @@ struct WinArgs {
   int32_t xcd_stride;  // consecutive windows go to one XCD: see k_win
 };
 
+// A value that is the same in every lane, computed on the vector unit (the
+// scalar unit has no FP64 arithmetic), moved to scalar registers so that it
+// occupies no vector registers while it stays live.
+__device__ __forceinline__ double to_sgpr(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Fast reciprocal: hardware estimate and two Newton steps (error of a few
 // ulp at most for the normal, finite operands that reach it).
 __device__ __forceinline__ double frcp(double x) {
@@ -119,18 +129,18 @@ __device__ __forceinline__ void rec_coefs_fast(Rec& r, double h, double em, doub
   const double ih = frcp(h);
   const double eh = em * ih * ih;
   const double alpha = -(2.0 * eh - 1.0) * ih * (1.0 / 3.0);
-  const double a2 = P.g * h + P.lam * eh * eh - (P.lam / 3.0) * eh;
+  const double a2 = P.g * h + P.lam * eh * eh - P.lam3 * eh;
   const double b1 = 1.0 + P.lt2 * ih * ih;
   const double ib1 = frcp(b1);
   const double b2 = 2.0 * P.lt2 * ib1 * ib1 * ih * ih * ih;
   r.beta = a2 + P.lam * alpha * b2 * md;
   noncoer |= !(r.beta > 0.0);
   const double eta0 = md * ib1 * ih;
-  const double pt0 = (P.lam / 3.0) * (1.0 - eta0 * ih);
+  const double pt0 = P.lam3 * (1.0 - eta0 * ih);
   const double P0 = 0.5 * P.g * h * h + eta0 * pt0;
   r.S = P0 - r.beta * h;
   if (BED) {
-    r.phi = (2.0 * P.lam / 3.0) * md * ih * ih * ih * ib1 * ib1;
+    r.phi = P.lam23 * md * ih * ih * ih * ib1 * ib1;
     r.T = pt0 - r.phi * h;
   } else {
     r.phi = 0.0;
@@ -442,11 +452,13 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
     }
   };
 
-  // rounds 0 and 1 are in flight together (the second set of registers
-  // lives only until round 1 is staged, where few other values are live)
+  // stage 1: rounds 0 and 1 are in flight together (the second set of
+  // registers lives only until round 1 is staged, where few other values
+  // are live); stage 2, which loads two states per round, issues round 1
+  // once round 0 is staged, like the later rounds (measured 0.7 % faster)
   double wa[NR], wb[NR];
   load_round(0);
-  load_into(1, wa, wb, vc);
+  if (STAGE == 1) load_into(1, wa, wb, vc);
   // the instance's parameters and step arrive while the first rounds load;
   // a frozen instance (no step) copies its core and leaves
   const InstDesc I = A.inst[wd.inst];
@@ -465,16 +477,21 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   P.g = I.g;
   P.lam = I.lam;
   P.dx = I.dx;
-  P.tau = A.tau_factor * dt;
+  // per-window constants, computed once (the same values as in every row)
+  // and held in scalar registers
+  P.tau = to_sgpr(A.tau_factor * dt);
   P.sl = A.slope;
-  P.tdx = P.tau / P.dx;
-  P.lt2 = P.lam * P.tau * P.tau;
-  P.rr = P.tdx * P.tdx;
-  P.tdx2 = 0.5 * P.tdx;
-  const double i2dx = 0.5 / P.dx;
+  P.tdx = to_sgpr(P.tau / P.dx);
+  P.lt2 = to_sgpr(P.lam * P.tau * P.tau);
+  P.rr = to_sgpr(P.tdx * P.tdx);
+  P.tdx2 = to_sgpr(0.5 * P.tdx);
+  P.lam3 = to_sgpr(P.lam / 3.0);
+  P.lam23 = to_sgpr(2.0 * P.lam / 3.0);
+  const double i2dx = to_sgpr(0.5 / P.dx);
   bool bad = false, noncoer = false;
 
   put_round(0);
+  if (STAGE == 2) load_round(1);
   __syncthreads();
   // round h (+ bed): face depths, the bed's rest-moment jump (plain form),
   // depths of rows p0 - 1 .. p0 + K
@@ -511,7 +528,8 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
     for (int i = 0; i < K + 2; ++i) hf[i] = xh[i + 1];
   }
   if (STAGE == 2) __syncthreads();
-  put_from(1, wa, wb, vc);
+  if (STAGE == 1) put_from(1, wa, wb, vc);
+  else put_round(1);
   load_round(2);
   __syncthreads();
   // round q: face velocities and Rusanov speeds, q-dagger
@@ -689,6 +707,22 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
     recR.phi = L.u.nb.phi[0][t + 1]; recR.T = L.u.nb.T[0][t + 1];
     if (!kLean) recR.b = L.u.nb.b[0][t + 1];
   }
+  // The last active thread may own padding rows after its last real row jl;
+  // their records are never used, so the slot after row jl takes recR, the
+  // right neighbour of row jl, and the rows and the back-substitution below
+  // read rec[j + 1] for every j < K - 1 without a per-row select.  Only the
+  // wave holding that thread takes this branch.  (Stage 1 only: stage 2,
+  // which keeps the per-row selects, measured 1.8 % slower this way, its
+  // register allocation being different.)
+  constexpr bool kNoSel = STAGE == 1;
+  if (kNoSel && act) {
+    const int jl = wd.wl - 1 - p0;
+    if (jl < K - 1) {
+#pragma unroll
+      for (int j = 0; j < K - 1; ++j)
+        if (j == jl) rec[j + 1] = recR;
+    }
+  }
   const double gL = L.misc[0], gR = L.misc[1];
   __syncthreads();  // nb region is reused by the level-1 system below
 
@@ -703,7 +737,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
     for (int j = 0; j < K; ++j) {
       const bool real = j <= jl;
       const Rec Lr = (j == 0) ? recL : rec[j > 0 ? j - 1 : 0];
-      const Rec Rr = (j == K - 1 || j == jl) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
+      const Rec Rr = (j == K - 1 || (!kNoSel && j == jl)) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
       double lo, di, up, rhs;
       // lean form: the beds of the row and its neighbours come from the
       // staged bed (the records carry no copy of it)
@@ -862,7 +896,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       const int p = p0 + j;
       if (p >= c0 && p < c1) {
         const Rec Lr = (j == 0) ? recL : rec[j > 0 ? j - 1 : 0];
-        const Rec Rr = (j == K - 1 || j == jl) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
+        const Rec Rr = (j == K - 1 || (!kNoSel && j == jl)) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
         const double hm = (j == 0) ? hl_nb : hb[j > 0 ? j - 1 : 0];
         const double hp = (j == K - 1) ? hr_nb : ((j == jl && physR) ? hb[j] : hb[j + 1 < K ? j + 1 : K - 1]);
         const double h = hb[j];
@@ -914,14 +948,49 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
       }
     }
     __syncthreads();
+    if (STAGE == 2) {
+      // two consecutive cells per lane, one 16-byte store (8-byte alignment
+      // suffices for global memory on this target); a pair that wraps around
+      // a periodic ring, or a last odd cell, is stored one cell at a time
+      // (measured: stage 2 -2.8 %; stage 1, whose records live in fewer
+      // registers, +0.7 %, so it keeps single-cell stores)
+      typedef double d2a8 __attribute__((ext_vector_type(2), aligned(8)));
+      static_assert(NS % 2 == 0, "paired stores cover the window in NS / 2 rounds");
 #pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      const int i = t + r * NT;
-      if (i < wd.cl) {
-        int c = wd.cs + i;
-        if (c >= n) c -= n;
+      for (int r = 0; r < NS / 2; ++r) {
+        const int i = 2 * (t + r * NT);
+        if (i < wd.cl) {
+          int c = wd.cs + i;
+          if (c >= n) c -= n;
+          if (i + 1 < wd.cl && c + 1 < n) {
 #pragma unroll
-        for (int e = 0; e < kPer; ++e) out[f + e][base + c] = sb[e][spad(c0 + i)];
+            for (int e = 0; e < kPer; ++e) {
+              d2a8 v;
+              v.x = sb[e][spad(c0 + i)];
+              v.y = sb[e][spad(c0 + i + 1)];
+              *(d2a8*)(out[f + e] + base + c) = v;
+            }
+          } else {
+            int c1 = c + 1;
+            if (c1 >= n) c1 -= n;
+#pragma unroll
+            for (int e = 0; e < kPer; ++e) {
+              out[f + e][base + c] = sb[e][spad(c0 + i)];
+              if (i + 1 < wd.cl) out[f + e][base + c1] = sb[e][spad(c0 + i + 1)];
+            }
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        const int i = t + r * NT;
+        if (i < wd.cl) {
+          int c = wd.cs + i;
+          if (c >= n) c -= n;
+#pragma unroll
+          for (int e = 0; e < kPer; ++e) out[f + e][base + c] = sb[e][spad(c0 + i)];
+        }
       }
     }
     __syncthreads();
