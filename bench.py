@@ -298,6 +298,10 @@ def main():
     ap.add_argument("--solver", default="tune", choices=["tune", "auto", "exact", "auto_small"],
                     help="tune: the library times every mode on the workload and keeps the fastest")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--table-out", default=None,
+                    help="write the autotuner's table (JSON) to this file")
+    ap.add_argument("--table-in", default=None,
+                    help="apply a stored autotuner table (JSON) instead of tuning")
     ap.add_argument("--order", type=int, default=2, choices=[1, 2],
                     help="2: the two-stage IMEX step; 1: the first-order scheme (one stage)")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -343,9 +347,20 @@ def main():
         s = Solver.from_workload(wl, solver=None if args.solver == "tune" else args.solver,
                                  order=args.order)
     tuned = None
-    if args.solver == "tune" and not args.probe and not explicit:
-        chosen, tms = s.autotune(4)
-        tuned = {"kept": chosen, "ms_per_step": {k: round(v, 4) for k, v in tms.items()}}
+    if args.table_in and not explicit:
+        # a stored autotuner table: each instance takes its class's mode
+        with open(args.table_in) as fh:
+            tuned = json.load(fh)
+        s.apply_table(tuned)
+        tuned = dict(tuned, source=os.path.basename(args.table_in))
+    elif args.solver == "tune" and not args.probe and not explicit:
+        # the library's tuner: a mode per class of instances (N bucket,
+        # boundary, bed, halo bucket), then that plan against the three
+        # uniform modes on the whole batch
+        tuned = s.autotune_classes(4)
+        if args.table_out:
+            with open(args.table_out, "w") as fh:
+                json.dump(tuned, fh, indent=1)
     plan = s.plan_info()
 
     if args.probe:
@@ -453,6 +468,7 @@ def main():
                    "timed_legs_ms_per_step": [round(1e3 * x / args.steps, 4) for x in legs],
                    "graph_warmup_steps": graph_warm, "order": args.order, "scheme": args.scheme,
                    "solver": tuned["kept"] if tuned else args.solver, "autotune": tuned,
+                   "window_launches": plan["window_launches"],
                    "windows": plan["windows"], "window_rows": plan["window_rows"],
                    "two_pass_tiles": plan["exact_tiles"]},
         "roofline": roof,

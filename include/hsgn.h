@@ -195,10 +195,48 @@ int hsgn_set_solver(hsgn_ctx* ctx, int32_t mode);
  * step has solver modes (else HSGN_EINVAL). */
 int hsgn_autotune(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_mode);
 
+/* Per-instance solver modes: h_modes (host, n_inst values of
+ * HSGN_SOLVER_AUTO, HSGN_SOLVER_EXACT or HSGN_SOLVER_AUTO_SMALL) choose, for
+ * each instance, 4096-row windows, the exact two-pass solve or 2048-row
+ * windows (with the same fall-back to the exact solve as the uniform
+ * modes).  Instances of each window width go to one launch per stage of the
+ * kernel of that width.  Re-plans at once; hsgn_set_solver and hsgn_autotune
+ * return to one mode for every instance.  Semi-implicit scheme only. */
+int hsgn_set_instance_solvers(hsgn_ctx* ctx, const int32_t* h_modes);
+
+/* Autotuner tables (the tile and schedule choice per class of instances):
+ * instances are grouped into classes by the key (N bucket = bit length of
+ * n - 1, boundary type, bed flag, halo bucket = bit length of the windowed
+ * solve's halo estimate L of the loaded state, as hsgn_plan_info reports
+ * it); each class is timed alone,
+ * in a context of its own holding a copy of its instances, in each solver
+ * mode (hsgn_autotune on that context, nsteps eager steps); each instance
+ * then takes its class's fastest mode.  That per-class plan is timed on the
+ * whole batch against the three uniform modes, and the fastest of the four
+ * is kept.  The loaded state, time, status and speed bounds are left as
+ * they were.
+ *  max_classes: room in the class arrays; more classes give HSGN_EINVAL;
+ *  h_nclass: host, the number of classes;
+ *  h_class_of: host, n_inst class indices, or NULL;
+ *  h_keys: host, max_classes x 4 ints (N bucket, bc, bed, halo bucket), or NULL;
+ *  h_ms: host, max_classes x 3 ms per step, indexed by mode, or NULL;
+ *  h_kept: host, max_classes modes, or NULL;
+ *  h_whole: host, 5 doubles or NULL: whole-batch ms per step of the three
+ *    uniform modes (indexed by mode), of the per-class plan, and the plan
+ *    kept (its mode, or -1 for the per-class plan).
+ * Allocates the class contexts and a copy of the state for its duration;
+ * synchronises the stream. */
+int hsgn_autotune_classes(hsgn_ctx* ctx, int32_t nsteps, int32_t max_classes, int32_t* h_nclass,
+                          int32_t* h_class_of, int32_t* h_keys, double* h_ms, int32_t* h_kept,
+                          double* h_whole);
+
 /* Plan of the loaded state (host arrays, any may be NULL): h_mode[j] = 0
- * windowed / 1 exact two-pass; h_halo[j] = halo rows L of instance j;
+ * windowed / 1 exact two-pass; h_halo[j] = halo rows L of instance j's
+ * windows (the estimate from the loaded state, also for an instance in the
+ * exact mode; 0 before a state is loaded; 1 << 30 where no finite halo
+ * would do);
  * h_counts[4] = {windows, two-pass tiles, two-pass instances with more than
- * one tile, window rows}. */
+ * one tile, window rows (2048 or 4096; -1 when both widths are used)}. */
 int hsgn_plan_info(hsgn_ctx* ctx, int32_t* h_mode, int32_t* h_halo, int32_t* h_counts);
 
 /* Kernel kinds timed by hsgn_step_timed. */

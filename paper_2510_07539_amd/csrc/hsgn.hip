@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <utility>
 #include <cstdarg>
 #include <cstdio>
@@ -104,6 +105,10 @@ struct hsgn_ctx {
   // execution plan (rebuilt by hsgn_set_state / hsgn_set_solver)
   int32_t solver = HSGN_SOLVER_AUTO;
   int win_nt = 512;
+  // per-instance solver modes (HSGN_SOLVER_*), empty: every instance uses
+  // the context-wide mode (solver, win_nt)
+  std::vector<int32_t> h_inst_solver;
+  int nwin_g[2] = {0, 0};  // windows of 256 threads (2048 rows) and of 512 (4096 rows)
   std::vector<double> h_smax, h_hmax;  // speed bound and depth maximum of the loaded state
   std::vector<int32_t> h_mode;         // per instance: 0 window, 1 two-pass
   std::vector<int32_t> h_halo;         // per instance window halo L (0 if none)
@@ -404,15 +409,20 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
       mark(stage == 1 ? HSGN_K_STAGE1 : HSGN_K_STAGE2, false);
     }
     if (c->nwin > 0) {
-      hsgn::WinArgs w;
-      w.s = a;
-      w.win = c->d_win;
-      w.nwin = c->nwin;
-      w.xcd_stride = (c->nwin + 7) / 8;
-      const int grid = 8 * w.xcd_stride;
+      // one launch per window geometry in use: the window list holds the
+      // 2048-row windows first, then the 4096-row ones
       mark(stage == 1 ? HSGN_K_WIN1 : HSGN_K_WIN2, true);
-      if (c->win_nt == 512) launch_win<512, kWK>(c, w, grid, stage);
-      else launch_win<256, kWK>(c, w, grid, stage);
+      for (int g = 0; g < 2; ++g) {
+        if (c->nwin_g[g] == 0) continue;
+        hsgn::WinArgs w;
+        w.s = a;
+        w.win = c->d_win + (g == 0 ? 0 : c->nwin_g[0]);
+        w.nwin = c->nwin_g[g];
+        w.xcd_stride = (w.nwin + 7) / 8;
+        const int grid = 8 * w.xcd_stride;
+        if (g == 1) launch_win<512, kWK>(c, w, grid, stage);
+        else launch_win<256, kWK>(c, w, grid, stage);
+      }
       mark(stage == 1 ? HSGN_K_WIN1 : HSGN_K_WIN2, false);
     }
   }
@@ -492,9 +502,7 @@ int upload(hsgn_ctx* c, T** d, size_t* cap, const std::vector<T>& h) {
 int make_plan(hsgn_ctx* c) {
   std::vector<TileDesc> ex_all, ex_multi;
   std::vector<int32_t> ex_inst;
-  std::vector<WinDesc> win;
-  const int WN = c->win_nt * kWK;
-  const int Lmax = WN / 4;
+  std::vector<WinDesc> win, win512;  // windows of 2048 and of 4096 rows
   c->h_mode.assign(c->n_inst, 1);
   c->h_halo.assign(c->n_inst, 0);
   size_t tpos = 0;
@@ -504,9 +512,21 @@ int make_plan(hsgn_ctx* c) {
     const int nt = c->h_ntiles[j];
     bool use_win = false;
     std::vector<WinDesc> wj;
-    if (c->solver != HSGN_SOLVER_EXACT && !c->h_smax.empty() && c->h_smax[j] > 0 &&
-        c->h_hmax[j] > 0) {
-      const int L = halo_width(p, c->h_smax[j], c->h_hmax[j], c->order == 1 ? 1.0 : hsgn::kGamma);
+    // this instance's mode: its own, or the context's
+    const int32_t mj = !c->h_inst_solver.empty()
+                           ? c->h_inst_solver[j]
+                           : (c->solver == HSGN_SOLVER_EXACT
+                                  ? HSGN_SOLVER_EXACT
+                                  : (c->win_nt == 256 ? HSGN_SOLVER_AUTO_SMALL : HSGN_SOLVER_AUTO));
+    const int WN = (mj == HSGN_SOLVER_AUTO_SMALL ? 256 : 512) * kWK;
+    const int Lmax = WN / 4;
+    // the halo estimate of the loaded state (reported for every instance)
+    const bool have_state = !c->h_smax.empty() && c->h_smax[j] > 0 && c->h_hmax[j] > 0;
+    const int L = have_state ? halo_width(p, c->h_smax[j], c->h_hmax[j],
+                                          c->order == 1 ? 1.0 : hsgn::kGamma)
+                             : 0;
+    c->h_halo[j] = L;
+    if (mj != HSGN_SOLVER_EXACT && have_state) {
       auto add = [&](int ws, int wl, int cs, int cl, int flags) {
         WinDesc d;
         std::memset(&d, 0, sizeof d);
@@ -554,11 +574,11 @@ int make_plan(hsgn_ctx* c) {
           use_win = true;
         }
       }
-      if (use_win) c->h_halo[j] = L;
     }
     if (use_win) {
       c->h_mode[j] = 0;
-      win.insert(win.end(), wj.begin(), wj.end());
+      std::vector<WinDesc>& dst = WN == 2048 ? win : win512;
+      dst.insert(dst.end(), wj.begin(), wj.end());
     } else {
       for (int k = 0; k < nt; ++k) {
         ex_all.push_back(c->h_tiles_all[tpos + k]);
@@ -568,6 +588,9 @@ int make_plan(hsgn_ctx* c) {
     }
     tpos += nt;
   }
+  c->nwin_g[0] = (int)win.size();
+  c->nwin_g[1] = (int)win512.size();
+  win.insert(win.end(), win512.begin(), win512.end());
   int rc = upload(c, &c->d_ex_tiles, &c->cap_ex_tiles, ex_all);
   if (!rc) rc = upload(c, &c->d_ex_tiles_multi, &c->cap_ex_tiles_multi, ex_multi);
   if (!rc) rc = upload(c, &c->d_ex_multi, &c->cap_ex_multi, ex_inst);
@@ -580,7 +603,8 @@ int make_plan(hsgn_ctx* c) {
   // uploads read host vectors that die here
   HIPCHK(c, hipStreamSynchronize(c->stream));
   const std::vector<uintptr_t> sig = {
-      (uintptr_t)c->win_nt, (uintptr_t)c->n_ex_tiles, (uintptr_t)c->n_ex_tiles_multi,
+      (uintptr_t)c->nwin_g[0], (uintptr_t)c->nwin_g[1], (uintptr_t)c->n_ex_tiles,
+      (uintptr_t)c->n_ex_tiles_multi,
       (uintptr_t)c->n_ex_multi, (uintptr_t)c->nwin, (uintptr_t)c->d_ex_tiles,
       (uintptr_t)c->d_ex_tiles_multi, (uintptr_t)c->d_ex_multi, (uintptr_t)c->d_win};
   if (sig != c->graph_sig) {
@@ -916,6 +940,7 @@ int hsgn_set_solver(hsgn_ctx* c, int32_t mode) {
     return fail(c, HSGN_EINVAL, "hsgn_set_solver: unknown mode %d", mode);
   c->solver = mode == HSGN_SOLVER_EXACT ? HSGN_SOLVER_EXACT : HSGN_SOLVER_AUTO;
   c->win_nt = mode == HSGN_SOLVER_AUTO_SMALL ? 256 : 512;
+  c->h_inst_solver.clear();
   int rc = enter(c);
   if (rc) return rc;
   rc = make_plan(c);
@@ -931,7 +956,9 @@ int hsgn_plan_info(hsgn_ctx* c, int32_t* h_mode, int32_t* h_halo, int32_t* h_cou
     h_counts[0] = c->nwin;
     h_counts[1] = c->n_ex_tiles;
     h_counts[2] = c->n_ex_multi;
-    h_counts[3] = c->win_nt * kWK;
+    h_counts[3] = c->nwin_g[0] > 0 && c->nwin_g[1] > 0 ? -1
+                  : (c->nwin_g[1] > 0 ? 512 * kWK
+                     : (c->nwin_g[0] > 0 ? 256 * kWK : c->win_nt * kWK));
   }
   return HSGN_OK;
 }
@@ -1006,16 +1033,17 @@ int hsgn_step_timed(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_count)
   return leave(c);
 }
 
-// Autotuner: time every solver configuration on the loaded state and keep
-// the fastest.  The state (and time, status, speed bounds) is saved before
-// the trials and restored after each of them.
-int hsgn_autotune(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_mode) {
-  if (!c) return HSGN_EINVAL;
-  if (nsteps < 1) return fail(c, HSGN_EINVAL, "hsgn_autotune: nsteps < 1");
-  if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
-    return fail(c, HSGN_EINVAL, "hsgn_autotune: only the semi-implicit step has solver modes");
-  int rc = enter(c);
-  if (rc) return rc;
+}  // extern "C"
+
+namespace {
+
+// Time candidate plans on the loaded state and keep the fastest.  The state
+// (and time, status, step counts and speed bounds) is saved before the
+// trials and restored after each of them.  set_plan(k) makes plan k; its
+// milliseconds per step go to ms[k]; the fastest plan is made again at the
+// end and returned in *best.
+template <class SetPlan>
+int time_plans(hsgn_ctx* c, int32_t nsteps, int nplans, SetPlan set_plan, double* ms, int* best) {
   const size_t nc = (size_t)c->ncell, ni = (size_t)c->n_inst;
   double *s_state = nullptr, *s_t = nullptr;
   unsigned long long* s_sp = nullptr;
@@ -1029,12 +1057,12 @@ int hsgn_autotune(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_mode) {
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
   };
-  rc = dmalloc(c, &s_state, 4 * nc);
+  int rc = dmalloc(c, &s_state, 4 * nc);
   if (!rc) rc = dmalloc(c, &s_t, ni);
   if (!rc) rc = dmalloc(c, &s_sp, 3 * ni);
-  if (!rc) rc = dmalloc(c, &s_st, ni);
+  if (!rc) rc = dmalloc(c, &s_st, 2 * ni);
   if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
-    rc = fail(c, HSGN_EHIP, "hsgn_autotune: hipEventCreate failed");
+    rc = fail(c, HSGN_EHIP, "autotune: hipEventCreate failed");
   if (rc) {
     cleanup();
     return rc;
@@ -1042,58 +1070,48 @@ int hsgn_autotune(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_mode) {
   auto cp = [&](void* dst, const void* src, size_t bytes) {
     return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream) == hipSuccess;
   };
-  const size_t fb = nc * sizeof(double), ib = ni * sizeof(double), ub = ni * sizeof(unsigned long long);
+  const size_t fb = nc * sizeof(double), ib = ni * sizeof(double), ub = ni * sizeof(unsigned long long),
+               sb = ni * sizeof(int32_t);
   auto save = [&]() {
     bool ok = true;
     for (int f = 0; f < 4; ++f) ok &= cp(s_state + f * nc, c->buf[c->cur][f], fb);
     ok &= cp(s_t, c->d_t, ib) && cp(s_sp, c->d_smax, ub) && cp(s_sp + ni, c->d_umax, ub) &&
-          cp(s_sp + 2 * ni, c->d_hmax, ub) && cp(s_st, c->d_status, ni * sizeof(int32_t));
+          cp(s_sp + 2 * ni, c->d_hmax, ub) && cp(s_st, c->d_status, sb) &&
+          cp(s_st + ni, c->d_nstep, sb);
     return ok;
   };
   auto restore = [&]() {
     bool ok = true;
     for (int f = 0; f < 4; ++f) ok &= cp(c->buf[c->cur][f], s_state + f * nc, fb);
     ok &= cp(c->d_t, s_t, ib) && cp(c->d_smax, s_sp, ub) && cp(c->d_umax, s_sp + ni, ub) &&
-          cp(c->d_hmax, s_sp + 2 * ni, ub) && cp(c->d_status, s_st, ni * sizeof(int32_t));
+          cp(c->d_hmax, s_sp + 2 * ni, ub) && cp(c->d_status, s_st, sb) &&
+          cp(c->d_nstep, s_st + ni, sb);
     return ok;
   };
-  auto set_mode = [&](int mode) {
-    c->solver = mode == HSGN_SOLVER_EXACT ? HSGN_SOLVER_EXACT : HSGN_SOLVER_AUTO;
-    c->win_nt = mode == HSGN_SOLVER_AUTO_SMALL ? 256 : 512;
-    return make_plan(c);
-  };
-  const int modes[3] = {HSGN_SOLVER_AUTO, HSGN_SOLVER_EXACT, HSGN_SOLVER_AUTO_SMALL};
-  double ms[3] = {0, 0, 0};
-  if (!save()) rc = fail(c, HSGN_EHIP, "hsgn_autotune: state copy failed");
-  for (int k = 0; k < 3 && !rc; ++k) {
-    rc = set_mode(modes[k]);
+  if (!save()) rc = fail(c, HSGN_EHIP, "autotune: state copy failed");
+  for (int k = 0; k < nplans && !rc; ++k) {
+    rc = set_plan(k);
     if (!rc) rc = enqueue_step(c);  // first launch of this configuration
-    if (!rc && !restore()) rc = fail(c, HSGN_EHIP, "hsgn_autotune: state copy failed");
+    if (!rc && !restore()) rc = fail(c, HSGN_EHIP, "autotune: state copy failed");
     if (!rc && hipEventRecord(e0, c->stream) != hipSuccess) rc = fail(c, HSGN_EHIP, "hipEventRecord");
-    for (int s = 0; s < nsteps && !rc; ++s) rc = enqueue_step(c);
+    for (int st = 0; st < nsteps && !rc; ++st) rc = enqueue_step(c);
     if (!rc && hipEventRecord(e1, c->stream) != hipSuccess) rc = fail(c, HSGN_EHIP, "hipEventRecord");
     float f = 0.0f;
     if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&f, e0, e1) != hipSuccess))
-      rc = fail(c, HSGN_EHIP, "hsgn_autotune: event timing failed");
-    ms[modes[k]] = (double)f / nsteps;
-    if (!rc && !restore()) rc = fail(c, HSGN_EHIP, "hsgn_autotune: state copy failed");
+      rc = fail(c, HSGN_EHIP, "autotune: event timing failed");
+    ms[k] = (double)f / nsteps;
+    if (!rc && !restore()) rc = fail(c, HSGN_EHIP, "autotune: state copy failed");
   }
-  int best = HSGN_SOLVER_AUTO;
-  for (int m : modes)
-    if (ms[m] < ms[best]) best = m;
-  if (!rc) rc = set_mode(best);
+  int b = 0;
+  for (int k = 1; k < nplans; ++k)
+    if (ms[k] < ms[b]) b = k;
+  if (!rc) rc = set_plan(b);
   if (!rc && hipStreamSynchronize(c->stream) != hipSuccess)
-    rc = fail(c, HSGN_EHIP, "hsgn_autotune: hipStreamSynchronize failed");
+    rc = fail(c, HSGN_EHIP, "autotune: hipStreamSynchronize failed");
   cleanup();
-  if (rc) return rc;
-  if (h_ms) std::memcpy(h_ms, ms, sizeof ms);
-  if (h_mode) *h_mode = best;
-  return leave(c);
+  *best = b;
+  return rc;
 }
-
-}  // extern "C"
-
-namespace {
 
 // Read the status flags and step counts (synchronises the stream); on a
 // flagged instance set the context's message (naming the instance, the step
@@ -1136,13 +1154,61 @@ int read_status(hsgn_ctx* c, const char* what, int32_t* h_flags) {
   return HSGN_OK;
 }
 
+
+// Make the uniform plan of a solver mode (every instance in that mode).
+int set_uniform_mode(hsgn_ctx* c, int mode) {
+  c->solver = mode == HSGN_SOLVER_EXACT ? HSGN_SOLVER_EXACT : HSGN_SOLVER_AUTO;
+  c->win_nt = mode == HSGN_SOLVER_AUTO_SMALL ? 256 : 512;
+  c->h_inst_solver.clear();
+  return make_plan(c);
+}
+
 }  // namespace
 
 extern "C" {
 
+// Autotuner: time the three uniform solver modes and keep the fastest.
+int hsgn_autotune(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_mode) {
+  if (!c) return HSGN_EINVAL;
+  if (nsteps < 1) return fail(c, HSGN_EINVAL, "hsgn_autotune: nsteps < 1");
+  if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
+    return fail(c, HSGN_EINVAL, "hsgn_autotune: only the semi-implicit step has solver modes");
+  int rc = enter(c);
+  if (rc) return rc;
+  const int modes[3] = {HSGN_SOLVER_AUTO, HSGN_SOLVER_EXACT, HSGN_SOLVER_AUTO_SMALL};
+  double t[3] = {0, 0, 0};
+  int best = 0;
+  rc = time_plans(c, nsteps, 3, [&](int k) { return set_uniform_mode(c, modes[k]); }, t, &best);
+  if (rc) return rc;
+  double ms[3] = {0, 0, 0};
+  for (int k = 0; k < 3; ++k) ms[modes[k]] = t[k];
+  if (h_ms) std::memcpy(h_ms, ms, sizeof ms);
+  if (h_mode) *h_mode = modes[best];
+  return leave(c);
+}
+
 int hsgn_status(hsgn_ctx* c, int32_t* h_flags) {
   if (!c) return HSGN_EINVAL;
   return read_status(c, "hsgn_status", h_flags);
+}
+
+int hsgn_set_instance_solvers(hsgn_ctx* c, const int32_t* h_modes) {
+  if (!c) return HSGN_EINVAL;
+  if (!h_modes) return fail(c, HSGN_EINVAL, "hsgn_set_instance_solvers: h_modes is NULL");
+  if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
+    return fail(c, HSGN_EINVAL, "hsgn_set_instance_solvers: only the semi-implicit step has "
+                "solver modes");
+  for (int j = 0; j < c->n_inst; ++j)
+    if (h_modes[j] != HSGN_SOLVER_AUTO && h_modes[j] != HSGN_SOLVER_EXACT &&
+        h_modes[j] != HSGN_SOLVER_AUTO_SMALL)
+      return fail(c, HSGN_EINVAL, "hsgn_set_instance_solvers: instance %d: unknown mode %d", j,
+                  h_modes[j]);
+  c->h_inst_solver.assign(h_modes, h_modes + c->n_inst);
+  int rc = enter(c);
+  if (rc) return rc;
+  rc = make_plan(c);
+  if (rc) return rc;
+  return leave(c);
 }
 
 const char* hsgn_last_error(const hsgn_ctx* c) { return c ? c->err.c_str() : "null context"; }
@@ -1508,6 +1574,161 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   hipLaunchKernelGGL(k_fill_f64, dim3(nbi), dim3(256), 0, c->stream, (int64_t)c->n_inst, c->d_t,
                      0.0);
   HIPCHK(c, hipGetLastError());
+  return leave(c);
+}
+
+// ---------------------------------------------------------------------------
+// hsgn_autotune_classes: the solver mode chosen per class of instances.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Copy runs of cells: entry k of tab is (source offset, destination offset,
+// length); one workgroup per entry.
+__global__ void k_gather_runs(const int64_t* __restrict__ tab, const double* __restrict__ src,
+                              double* __restrict__ dst) {
+  const int64_t so = tab[3 * blockIdx.x], dof = tab[3 * blockIdx.x + 1],
+                len = tab[3 * blockIdx.x + 2];
+  for (int64_t i = threadIdx.x; i < len; i += blockDim.x) dst[dof + i] = src[so + i];
+}
+
+// Class key of instance j: bit length of n - 1 (the N bucket), boundary
+// type, bed flag, and the bit length of the halo estimate of the windowed
+// solve (0 before a state is loaded).
+void class_key(const hsgn_ctx* c, int j, int32_t key[4]) {
+  const int64_t n = c->offsets[j + 1] - c->offsets[j];
+  int nb = 0;
+  while (((int64_t)1 << nb) < n) ++nb;
+  int hb = 0;
+  const int L = c->h_halo.empty() ? 0 : c->h_halo[j];
+  while (L > 0 && (1 << hb) < L && hb < 30) ++hb;
+  key[0] = nb;
+  key[1] = c->params[j].bc;
+  key[2] = c->params[j].has_bathymetry ? 1 : 0;
+  key[3] = hb;
+}
+
+// Time every solver mode on the instances of one class in a context of
+// their own (a copy of their state, time, bed and parameters).
+int tune_class(hsgn_ctx* c, const std::vector<int>& idx, int32_t nsteps, double ms[3],
+               int32_t* kept) {
+  const int m = (int)idx.size();
+  std::vector<int64_t> off(m + 1, 0);
+  std::vector<hsgn_params> prm(m);
+  std::vector<int64_t> tab, tabt;
+  for (int k = 0; k < m; ++k) {
+    const int j = idx[k];
+    const int64_t n = c->offsets[j + 1] - c->offsets[j];
+    off[k + 1] = off[k] + n;
+    prm[k] = c->params[j];
+    tab.insert(tab.end(), {c->offsets[j], off[k], n});
+    tabt.insert(tabt.end(), {(int64_t)j, (int64_t)k, (int64_t)1});
+  }
+  const int64_t nc = off[m];
+  bool any_b = false;
+  for (const hsgn_params& p : prm) any_b |= p.has_bathymetry != 0;
+  double* tmp = nullptr;
+  int64_t* dtab = nullptr;
+  int rc = dmalloc(c, &tmp, (size_t)(5 * nc + m));
+  if (!rc) rc = dmalloc(c, &dtab, tab.size() + tabt.size());
+  hsgn_ctx* sub = nullptr;
+  if (!rc) {
+    HIPCHK(c, hipMemcpyAsync(dtab, tab.data(), tab.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dtab + tab.size(), tabt.data(), tabt.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, c->stream));
+    for (int f = 0; f < 4; ++f)
+      hipLaunchKernelGGL(k_gather_runs, dim3(m), dim3(256), 0, c->stream, dtab,
+                         c->buf[c->cur][f], tmp + (size_t)f * nc);
+    if (any_b)
+      hipLaunchKernelGGL(k_gather_runs, dim3(m), dim3(256), 0, c->stream, dtab, c->d_b,
+                         tmp + (size_t)4 * nc);
+    hipLaunchKernelGGL(k_gather_runs, dim3(m), dim3(64), 0, c->stream, dtab + tab.size(), c->d_t,
+                       tmp + (size_t)5 * nc);
+    HIPCHK(c, hipGetLastError());
+    rc = hsgn_init(&sub, m, off.data(), prm.data(), any_b ? tmp + (size_t)4 * nc : nullptr,
+                   (void*)c->stream);
+    if (rc) rc = fail(c, rc, "hsgn_autotune_classes: sub-context init failed");
+  }
+  if (!rc) {
+    rc = hsgn_set_state(sub, tmp, tmp + nc, tmp + 2 * (size_t)nc, tmp + 3 * (size_t)nc,
+                        tmp + 5 * (size_t)nc);
+    if (!rc) rc = hsgn_autotune(sub, nsteps, ms, kept);
+    if (rc) rc = fail(c, rc, "hsgn_autotune_classes: %s", hsgn_last_error(sub));
+  }
+  if (sub) hsgn_destroy(sub);
+  // the sub-context's work is on this stream: wait before freeing its inputs
+  if (hipStreamSynchronize(c->stream) != hipSuccess && !rc)
+    rc = fail(c, HSGN_EHIP, "hsgn_autotune_classes: hipStreamSynchronize failed");
+  if (tmp) hipFree(tmp);
+  if (dtab) hipFree(dtab);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int hsgn_autotune_classes(hsgn_ctx* c, int32_t nsteps, int32_t max_classes,
+                                     int32_t* h_nclass, int32_t* h_class_of, int32_t* h_keys,
+                                     double* h_ms, int32_t* h_kept, double* h_whole) {
+  if (!c) return HSGN_EINVAL;
+  if (nsteps < 1 || max_classes < 1 || !h_nclass)
+    return fail(c, HSGN_EINVAL, "hsgn_autotune_classes: bad arguments");
+  if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
+    return fail(c, HSGN_EINVAL, "hsgn_autotune_classes: only the semi-implicit step has solver "
+                "modes");
+  int rc = enter(c);
+  if (rc) return rc;
+  // classes in order of first appearance
+  std::vector<std::array<int32_t, 4>> keys;
+  std::vector<std::vector<int>> members;
+  std::vector<int32_t> cls(c->n_inst);
+  for (int j = 0; j < c->n_inst; ++j) {
+    std::array<int32_t, 4> k;
+    class_key(c, j, k.data());
+    int id = -1;
+    for (size_t q = 0; q < keys.size(); ++q)
+      if (keys[q] == k) id = (int)q;
+    if (id < 0) {
+      id = (int)keys.size();
+      keys.push_back(k);
+      members.emplace_back();
+    }
+    members[id].push_back(j);
+    cls[j] = id;
+  }
+  const int ncls = (int)keys.size();
+  if (ncls > max_classes)
+    return fail(c, HSGN_EINVAL, "hsgn_autotune_classes: %d classes, room for %d", ncls,
+                max_classes);
+  std::vector<double> ms(3 * ncls, 0.0);
+  std::vector<int32_t> kept(ncls, HSGN_SOLVER_AUTO);
+  for (int q = 0; q < ncls && !rc; ++q) rc = tune_class(c, members[q], nsteps, &ms[3 * q], &kept[q]);
+  if (rc) return rc;
+  // the per-class plan (which may need a launch per window geometry) against
+  // the three uniform modes on the whole batch: the fastest is kept
+  std::vector<int32_t> modes(c->n_inst);
+  for (int j = 0; j < c->n_inst; ++j) modes[j] = kept[cls[j]];
+  const int umodes[3] = {HSGN_SOLVER_AUTO, HSGN_SOLVER_EXACT, HSGN_SOLVER_AUTO_SMALL};
+  double whole[4] = {0, 0, 0, 0};
+  int best = 0;
+  rc = time_plans(c, nsteps, 4,
+                  [&](int k) {
+                    if (k < 3) return set_uniform_mode(c, umodes[k]);
+                    c->h_inst_solver = modes;
+                    return make_plan(c);
+                  },
+                  whole, &best);
+  if (rc) return rc;
+  *h_nclass = ncls;
+  if (h_whole) {
+    for (int k = 0; k < 3; ++k) h_whole[umodes[k]] = whole[k];
+    h_whole[3] = whole[3];
+    h_whole[4] = best == 3 ? -1.0 : (double)umodes[best];
+  }
+  if (h_class_of) std::memcpy(h_class_of, cls.data(), cls.size() * sizeof(int32_t));
+  if (h_keys)
+    for (int q = 0; q < ncls; ++q) std::memcpy(h_keys + 4 * q, keys[q].data(), 4 * sizeof(int32_t));
+  if (h_ms) std::memcpy(h_ms, ms.data(), ms.size() * sizeof(double));
+  if (h_kept) std::memcpy(h_kept, kept.data(), kept.size() * sizeof(int32_t));
   return leave(c);
 }
 

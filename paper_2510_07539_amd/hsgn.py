@@ -74,6 +74,13 @@ def lib():
         L.hsgn_version.restype = C.c_char_p
         L.hsgn_destroy.restype = None
         L.hsgn_destroy.argtypes = [vp]
+        L.hsgn_set_instance_solvers.restype = C.c_int
+        L.hsgn_set_instance_solvers.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.hsgn_autotune_classes.restype = C.c_int
+        L.hsgn_autotune_classes.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                            C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                            C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                            C.POINTER(C.c_double)]
         L.hsgn_step_noalloc.restype = C.c_int
         L.hsgn_step_noalloc.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(HsgnParams),
                                         dp, dp, dp, dp, dp, dp, C.c_int32, C.c_int32, vp,
@@ -108,6 +115,8 @@ class Solver:
         self.n_inst = len(offs) - 1
         self.ncell = int(offs[-1])
         pa = _params_array(params)
+        self._offsets = offs
+        self._params = [dict(p) for p in params]
         if b is not None:
             b = b.to(self.device, torch.float64).contiguous()
         self._b = b
@@ -136,6 +145,76 @@ class Solver:
         names = {v: k for k, v in SOLVERS.items()}
         return names[mode.value], {names[m]: ms[m] for m in range(3)}
 
+    def set_instance_solvers(self, modes):
+        """Per-instance solver modes (names or HSGN_SOLVER_* values)."""
+        m = np.ascontiguousarray([SOLVERS[x] if isinstance(x, str) else int(x) for x in modes],
+                                 dtype=np.int32)
+        assert len(m) == self.n_inst
+        self._check(lib().hsgn_set_instance_solvers(self._h, m.ctypes.data_as(C.POINTER(C.c_int32))),
+                    "hsgn_set_instance_solvers")
+
+    def autotune_classes(self, nsteps=4, max_classes=256):
+        """hsgn_autotune_classes: the per-class autotuner table (a dict that
+        json can store) and the plan it kept."""
+        P32, PD = C.POINTER(C.c_int32), C.POINTER(C.c_double)
+        ncls = C.c_int32(0)
+        cls = np.zeros(self.n_inst, dtype=np.int32)
+        keys = np.zeros((max_classes, 4), dtype=np.int32)
+        ms = np.zeros((max_classes, 3), dtype=np.float64)
+        kept = np.zeros(max_classes, dtype=np.int32)
+        whole = np.zeros(5, dtype=np.float64)
+        self._check(lib().hsgn_autotune_classes(self._h, int(nsteps), int(max_classes),
+                                                C.byref(ncls), cls.ctypes.data_as(P32),
+                                                keys.ctypes.data_as(P32), ms.ctypes.data_as(PD),
+                                                kept.ctypes.data_as(P32), whole.ctypes.data_as(PD)),
+                    "hsgn_autotune_classes")
+        names = {v: k for k, v in SOLVERS.items()}
+        sizes = np.diff(self._offsets)
+        table = []
+        for q in range(ncls.value):
+            sel = cls == q
+            table.append({"key": {"n_bucket": int(keys[q, 0]), "bc": int(keys[q, 1]),
+                                  "bed": int(keys[q, 2]), "halo_bucket": int(keys[q, 3])},
+                          "instances": int(sel.sum()), "cells": int(sizes[sel].sum()),
+                          "ms_per_step": {names[m]: round(float(ms[q, m]), 4) for m in range(3)},
+                          "kept": names[int(kept[q])]})
+        kept_plan = "per_class" if whole[4] < 0 else names[int(whole[4])]
+        return {"classes": table, "kept": kept_plan,
+                "whole_batch_ms_per_step": {**{names[m]: round(float(whole[m]), 4) for m in range(3)},
+                                            "per_class": round(float(whole[3]), 4)}}
+
+    def apply_table(self, table):
+        """The plan a stored table (autotune_classes) kept: a uniform mode, or
+        per-instance modes where each instance takes the mode kept for its
+        class key (instances whose key the table lacks take the table's most
+        common mode)."""
+        if table["kept"] != "per_class":
+            self.set_solver(table["kept"])
+            return
+        keymode = {tuple(c["key"][k] for k in ("n_bucket", "bc", "bed", "halo_bucket")): c["kept"]
+                   for c in table["classes"]}
+        modes = [c["kept"] for c in table["classes"]]
+        default = max(set(modes), key=modes.count) if modes else "auto"
+        keys = self.class_keys()
+        self.set_instance_solvers([keymode.get(tuple(k), default) for k in keys])
+
+    def class_keys(self):
+        """Class key (N bucket, bc, bed, halo bucket) of every instance, as the
+        library's tuner forms it (the halo from the plan of the loaded state)."""
+        info = self.plan_info()
+        sizes = np.diff(self._offsets)
+        out = []
+        for j in range(self.n_inst):
+            nb = 0
+            while (1 << nb) < sizes[j]:
+                nb += 1
+            L = int(info["halo"][j])
+            hb = 0
+            while L > 0 and (1 << hb) < L and hb < 30:
+                hb += 1
+            out.append((nb, int(self._params[j]["bc"]), int(self._params[j]["has_b"]), hb))
+        return out
+
     def plan_info(self):
         mode = np.zeros(self.n_inst, dtype=np.int32)
         halo = np.zeros(self.n_inst, dtype=np.int32)
@@ -144,7 +223,8 @@ class Solver:
         self._check(lib().hsgn_plan_info(self._h, mode.ctypes.data_as(P), halo.ctypes.data_as(P),
                                          cnt.ctypes.data_as(P)), "hsgn_plan_info")
         return dict(mode=mode, halo=halo, windows=int(cnt[0]), exact_tiles=int(cnt[1]),
-                    exact_multi=int(cnt[2]), window_rows=int(cnt[3]))
+                    exact_multi=int(cnt[2]), window_rows=int(cnt[3]),
+                    window_launches=(2 if int(cnt[3]) < 0 else (1 if int(cnt[0]) > 0 else 0)))
 
     @classmethod
     def from_workload(cls, wl, device="cuda", solver=None, order=2, scheme=SCHEME_SEMI_IMPLICIT,

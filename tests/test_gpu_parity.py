@@ -424,6 +424,81 @@ def test_paper_test_problems(solver):
     compare(WL.paper_tests(), 300, label="paper tests", solver=solver)
 
 
+def _modes_case():
+    return WL.concat("per-instance modes", [WL.batched_bar(n_inst=6, seed=9, n_lo=600, n_hi=9000),
+                                           WL.solitary(N=5000, L=1250.0, lam=1000.0, t_end=0.0),
+                                           WL.dam_break(N=3000, xa=-45.0, xb=45.0)])
+
+
+def test_per_instance_solver_modes_match_the_oracle():
+    """hsgn_set_instance_solvers: one batch with instances in each of the
+    three modes (4096-row windows, 2048-row windows, the exact two-pass
+    solve: two window launches and the two-pass launches in every stage)
+    matches the oracle instance by instance."""
+    Solver = _solver()
+    wl = _modes_case()
+    modes = ["auto", "auto_small", "exact", "auto_small", "auto", "exact", "auto_small", "auto"]
+    s = Solver.from_workload(wl)
+    s.set_instance_solvers(modes)
+    info = s.plan_info()
+    note("  plan: %d windows (rows %d), %d two-pass tiles" % (
+        info["windows"], info["window_rows"], info["exact_tiles"]))
+    assert info["window_rows"] == -1 and info["exact_tiles"] > 0
+    assert [int(x) for x in info["mode"]] == [0, 0, 1, 0, 0, 1, 0, 0]
+    s.step(30)
+    (h, q, m, W), t = s.get_state()
+    rc, _ = s.status()
+    s.close()
+    assert rc == 0
+    U = [x.cpu().numpy() for x in (h, q, m, W)]
+    for j in range(wl.n_inst):
+        check_instance(j, U, wl, 30)
+
+
+def test_autotune_classes_table_round_trip():
+    """hsgn_autotune_classes: every instance is in one class, the loaded
+    state is left bitwise as it was, and a context that applies the stored
+    table (through JSON) gets the same plan: both step bitwise alike, and
+    match the oracle."""
+    import json
+    Solver = _solver()
+    wl = WL.concat("tuner", [WL.batched_bar(n_inst=20, seed=13, n_lo=512, n_hi=12000),
+                             WL.solitary(N=800, t_end=0.0)])
+    s = Solver.from_workload(wl)
+    (h0, q0, m0, W0), t0 = s.get_state()
+    table = s.autotune_classes(2)
+    note("  kept %s; whole batch %s; %d classes" % (table["kept"], table["whole_batch_ms_per_step"],
+                                                    len(table["classes"])))
+    (h1, q1, m1, W1), t1 = s.get_state()
+    for a, b in zip((h0, q0, m0, W0, t0), (h1, q1, m1, W1, t1)):
+        assert torch.equal(a, b)
+    assert sum(c["instances"] for c in table["classes"]) == wl.n_inst
+    assert sum(c["cells"] for c in table["classes"]) == wl.n_cells
+    keys = [tuple(sorted(c["key"].items())) for c in table["classes"]]
+    assert len(set(keys)) == len(keys)
+    for c in table["classes"]:
+        assert c["kept"] in ("auto", "exact", "auto_small")
+        assert min(c["ms_per_step"].values()) > 0
+    assert table["kept"] in ("auto", "exact", "auto_small", "per_class")
+    stored = json.loads(json.dumps(table))
+    s2 = Solver.from_workload(wl)
+    s2.apply_table(stored)
+    p1, p2 = s.plan_info(), s2.plan_info()
+    assert np.array_equal(p1["mode"], p2["mode"]) and p1["windows"] == p2["windows"]
+    assert p1["window_rows"] == p2["window_rows"] and p1["exact_tiles"] == p2["exact_tiles"]
+    s.step(20)
+    s2.step(20)
+    Ua, _ = s.get_state()
+    Ub, _ = s2.get_state()
+    for a, b in zip(Ua, Ub):
+        assert torch.equal(a, b)
+    U = [x.cpu().numpy() for x in Ua]
+    s.close()
+    s2.close()
+    for j in (0, 7, 19, 20):
+        check_instance(j, U, wl, 20)
+
+
 def test_autotune_keeps_state_and_fastest_mode():
     """The autotuner leaves the loaded state, time and status untouched
     (bitwise), keeps the mode with the smallest measured time, and the
