@@ -30,15 +30,15 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # hash of the sources of its kernels and reported as null once they change.
 TRAFFIC = [
     {"kernel": "win2", "workload": "batched_bar", "solver": "auto_small",
-     "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp"], "hash": "0f45e66be4d9d410",
-     "fetch_bytes": 2812629309, "write_bytes": 1544248213, "bytes_per_launch": 4356877522},
+     "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp"], "hash": "0c27ad949886b9ea",
+     "fetch_bytes": 2674880436, "write_bytes": 1412813323, "bytes_per_launch": 4087693759},
     {"kernel": "ex2", "workload": "batched_flat", "scheme": "explicit",
-     "sources": ["hsgn_kernels.hpp", "hsgn_explicit.hpp"], "hash": "aa640bfae82747bf",
-     "fetch_bytes": 2232930559, "write_bytes": 1118178346, "bytes_per_launch": 3351108905},
+     "sources": ["hsgn_kernels.hpp", "hsgn_explicit.hpp"], "hash": "9de8412d86e0c6a4",
+     "fetch_bytes": 2233082922, "write_bytes": 1118370752, "bytes_per_launch": 3351453674},
     {"kernel": "sgn_solve", "workload": "batched_flat", "scheme": "sgn",
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp",
-                 "hsgn_explicit.hpp"], "hash": "2c7c57d314257748",
-     "fetch_bytes": 2227124592, "write_bytes": 280497749, "bytes_per_launch": 2507622342},
+                 "hsgn_explicit.hpp"], "hash": "d9fc151161de7be3",
+     "fetch_bytes": 2207553446, "write_bytes": 276611424, "bytes_per_launch": 2484164870},
 ]
 
 def src_hash(sources):
