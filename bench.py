@@ -297,6 +297,8 @@ def main():
                     help="timed legs of --steps steps each; the value is their median")
     ap.add_argument("--solver", default="tune", choices=["tune", "auto", "exact", "auto_small"],
                     help="tune: the library times every mode on the workload and keeps the fastest")
+    ap.add_argument("--launch", default="tune", choices=["tune", "grid", "persistent"],
+                    help="window-stage launch; tune: the library times both and keeps the faster")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--table-out", default=None,
                     help="write the autotuner's table (JSON) to this file")
@@ -361,6 +363,14 @@ def main():
         if args.table_out:
             with open(args.table_out, "w") as fh:
                 json.dump(tuned, fh, indent=1)
+    launch, launch_ms = "grid", None
+    if not explicit:
+        if args.launch == "tune" and not args.probe:
+            launch, launch_ms = s.autotune_launch(4)
+            launch_ms = {k: round(v, 4) for k, v in launch_ms.items()}
+        elif args.launch != "tune":
+            launch = args.launch
+            s.set_launch(launch)
     plan = s.plan_info()
 
     if args.probe:
@@ -431,11 +441,13 @@ def main():
         if (tr["kernel"] == dom and tr["workload"] == args.workload and
                 tr.get("solver", solver_used) == solver_used and
                 tr.get("scheme", args.scheme) == args.scheme and
+                tr.get("launch", "grid") == launch and
                 src_hash(tr["sources"]) == tr["hash"]):
             traffic = tr["bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-            "kernel": ("k_win<%s>" if dom.startswith("win") else
+            "kernel": (("k_win_persist<%s>" if launch == "persistent" else "k_win<%s>")
+                       if dom.startswith("win") else
                        "k_ex<%s>" if dom.startswith("ex") else
                        "k_%s" if dom.startswith("sgn") else "k_stage<%s>") % dom,
             "avg_launch_ms": round(ms_avg, 4),
@@ -469,6 +481,7 @@ def main():
                    "graph_warmup_steps": graph_warm, "order": args.order, "scheme": args.scheme,
                    "solver": tuned["kept"] if tuned else args.solver, "autotune": tuned,
                    "window_launches": plan["window_launches"],
+                   "launch": launch, "launch_ms_per_step": launch_ms,
                    "windows": plan["windows"], "window_rows": plan["window_rows"],
                    "two_pass_tiles": plan["exact_tiles"]},
         "roofline": roof,

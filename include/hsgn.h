@@ -230,6 +230,33 @@ int hsgn_autotune_classes(hsgn_ctx* ctx, int32_t nsteps, int32_t max_classes, in
                           int32_t* h_class_of, int32_t* h_keys, double* h_ms, int32_t* h_kept,
                           double* h_whole);
 
+/* Launch of the window stages:
+ *  HSGN_LAUNCH_GRID (the default): one workgroup per window, consecutive
+ *    windows of an instance dealt to one XCD; the hardware dispatcher
+ *    refills a finished workgroup's slot.
+ *  HSGN_LAUNCH_PERSISTENT: as many workgroups as are resident at once, each
+ *    taking windows from eight work queues (one per XCD, atomic tickets; a
+ *    workgroup drains its own XCD's queue first, then the others).  The
+ *    kernel resets its queue counters at its end, so graphs replay it as
+ *    they are.
+ * Both give bitwise the same results (each window is computed the same
+ * way).  A change drops the cached hsgn_run graphs.  Contexts of
+ * hsgn_step_noalloc have no queues (HSGN_EINVAL for the persistent launch).
+ * Two window launches of one context must not overlap: the context's
+ * stream orders them (the adjoint's recompute stream has queues of its
+ * own). */
+#define HSGN_LAUNCH_GRID 0
+#define HSGN_LAUNCH_PERSISTENT 1
+int hsgn_set_launch(hsgn_ctx* ctx, int32_t launch);
+
+/* Time both launches (nsteps eager steps each, on the current plan and the
+ * loaded state), keep the faster, and leave the state, time, status and
+ * speed bounds as they were.  h_ms (host, 2 doubles or NULL): milliseconds
+ * per step indexed by launch; h_launch (host or NULL): the launch kept.
+ * Allocates a copy of the state for its duration; synchronises the stream.
+ * Semi-implicit scheme only (else HSGN_EINVAL). */
+int hsgn_autotune_launch(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_launch);
+
 /* Plan of the loaded state (host arrays, any may be NULL): h_mode[j] = 0
  * windowed / 1 exact two-pass; h_halo[j] = halo rows L of instance j's
  * windows (the estimate from the loaded state, also for an instance in the

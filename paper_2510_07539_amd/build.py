@@ -7,6 +7,11 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "hsgn.hip")
+# the persistent window kernels, built on their own without machine-level
+# loop-invariant code motion (it hoists per-window values out of the window
+# loop and spills registers)
+SRC_PERSIST = os.path.join(HERE, "csrc", "hsgn_persist.hip")
+PERSIST_FLAGS = ["-mllvm", "-disable-machine-licm"]
 DEPS = [os.path.join(HERE, "csrc", f) for f in sorted(os.listdir(os.path.join(HERE, "csrc")))
         if f.endswith((".hip", ".hpp"))] + [os.path.join(ROOT, "include", "hsgn.h")]
 LIB = os.path.join(HERE, "libhsgn.so")
@@ -23,10 +28,19 @@ HIPCC_FLAGS = [
 def build(verbose: bool = False) -> str:
     """Compile libhsgn.so (always recompiles)."""
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", *HIPCC_FLAGS, "-I" + os.path.join(ROOT, "include"), SRC, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    obj = tmp + ".persist.o"
+    inc = "-I" + os.path.join(ROOT, "include")
+    flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    cmds = [["hipcc", *flags, *PERSIST_FLAGS, inc, "-c", SRC_PERSIST, "-o", obj],
+            ["hipcc", *HIPCC_FLAGS, inc, SRC, "-x", "none", obj, "-o", tmp]]
+    try:
+        for cmd in cmds:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.check_call(cmd)
+    finally:
+        if os.path.exists(obj):
+            os.remove(obj)
     os.replace(tmp, LIB)
     return LIB
 

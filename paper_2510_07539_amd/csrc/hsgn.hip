@@ -26,6 +26,7 @@
 #include "hsgn.h"
 #include "hsgn_kernels.hpp"
 #include "hsgn_window.hpp"
+#include "hsgn_persist.hpp"
 #include "hsgn_adjoint.hpp"
 #include "hsgn_explicit.hpp"
 
@@ -36,6 +37,7 @@ constexpr int kKMAX = 8;      // max cells per thread
 constexpr int kTileMax = kNT * kKMAX;
 constexpr int kNTR = 256;     // threads of the reduced-system solve
 constexpr int kWK = 8;        // rows per thread of the windowed kernel
+static_assert(kWK == hsgn::kPersistRows, "the persistent kernels are built for kWK rows");
 constexpr double kWinMargin = 2.0;  // safety factor on the decay estimate
 constexpr int kAdjNT = 256;    // threads (cell positions) per reverse-stage tile
 
@@ -119,6 +121,15 @@ struct hsgn_ctx {
   int n_ex_tiles = 0, n_ex_tiles_multi = 0, n_ex_multi = 0, nwin = 0;
   size_t cap_ex_tiles = 0, cap_ex_tiles_multi = 0, cap_ex_multi = 0, cap_win = 0;
   unsigned long long* d_hmax = nullptr;
+  // window-stage launch: one workgroup per window (HSGN_LAUNCH_GRID) or the
+  // persistent kernel walking per-XCD work queues (HSGN_LAUNCH_PERSISTENT)
+  int32_t launch = HSGN_LAUNCH_GRID;
+  // 2 x 9 queue counters of the persistent kernel: the first set for the
+  // library's stream, the second for the adjoint's recompute stream (zero
+  // between launches: every launch resets its own)
+  int32_t* d_queue = nullptr;
+  int n_cu = 0;              // compute units of the device
+  int occ[2][2] = {};        // resident workgroups per CU: [geometry][stage - 1], 0 = not read yet
   // adjoint workspace (allocated by the first hsgn_adjoint call)
   struct Adj {
     int K = 0, nseg = 0;
@@ -179,7 +190,7 @@ void free_all(hsgn_ctx* c) {
                   c->d_rdi,
                   c->d_rup, c->d_rrhs, c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw,
                   c->d_ex_tiles, c->d_ex_tiles_multi, c->d_ex_multi, c->d_win, c->d_hmax,
-                  c->d_xtiles, c->d_sgn};
+                  c->d_xtiles, c->d_sgn, c->d_queue};
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (int i = 0; i < 3; ++i)
@@ -258,15 +269,30 @@ StageArgs stage_args(hsgn_ctx* c, int stage) {
 
 // Enqueue one IMEX step (no synchronisation), then rotate the buffers.
 // With `tm`, every launch is bracketed by a pair of events (kind k).
-template <int NT, int K>
-void launch_win(hsgn_ctx* c, const hsgn::WinArgs& w, int grid, int stage) {
-  if (c->any_b) {
-    if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<NT, K, true, 1>), dim3(grid), dim3(NT), 0, c->stream, w);
-    else hipLaunchKernelGGL((hsgn::k_win<NT, K, true, 2>), dim3(grid), dim3(NT), 0, c->stream, w);
-  } else {
-    if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<NT, K, false, 1>), dim3(grid), dim3(NT), 0, c->stream, w);
-    else hipLaunchKernelGGL((hsgn::k_win<NT, K, false, 2>), dim3(grid), dim3(NT), 0, c->stream, w);
+template <int NT, int K, bool BED>
+hipError_t launch_win_b(hsgn_ctx* c, hsgn::WinArgs& w, int stage) {
+  const int g = NT == 512 ? 1 : 0;
+  if (c->launch == HSGN_LAUNCH_PERSISTENT && c->d_queue) {
+    int& occ = c->occ[g][stage - 1];
+    if (occ == 0 && hsgn::win_persist_occupancy(NT, BED, stage, &occ) != hipSuccess) occ = 0;
+    if (occ > 0 && c->n_cu >= 8) {
+      // as many workgroups as are resident at once (a multiple of 8, so
+      // that block b runs on XCD b mod 8), at most one per window
+      const int grid = std::min(8 * w.xcd_stride, (c->n_cu / 8) * 8 * occ);
+      w.queue = c->d_queue + (c->adj.rstream && c->stream == c->adj.rstream ? 9 : 0);
+      return hsgn::launch_win_persist(NT, BED, stage, grid, c->stream, w);
+    }
   }
+  const int grid = 8 * w.xcd_stride;
+  if (stage == 1) hipLaunchKernelGGL((hsgn::k_win<NT, K, BED, 1>), dim3(grid), dim3(NT), 0, c->stream, w);
+  else hipLaunchKernelGGL((hsgn::k_win<NT, K, BED, 2>), dim3(grid), dim3(NT), 0, c->stream, w);
+  return hipSuccess;  // errors of this launch reach hipGetLastError
+}
+
+template <int NT, int K>
+hipError_t launch_win(hsgn_ctx* c, hsgn::WinArgs& w, int stage) {
+  if (c->any_b) return launch_win_b<NT, K, true>(c, w, stage);
+  return launch_win_b<NT, K, false>(c, w, stage);
 }
 
 int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>>* tm = nullptr) {
@@ -419,9 +445,9 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
         w.win = c->d_win + (g == 0 ? 0 : c->nwin_g[0]);
         w.nwin = c->nwin_g[g];
         w.xcd_stride = (w.nwin + 7) / 8;
-        const int grid = 8 * w.xcd_stride;
-        if (g == 1) launch_win<512, kWK>(c, w, grid, stage);
-        else launch_win<256, kWK>(c, w, grid, stage);
+        w.queue = nullptr;
+        const hipError_t le = g == 1 ? launch_win<512, kWK>(c, w, stage) : launch_win<256, kWK>(c, w, stage);
+        if (le != hipSuccess) return fail(c, HSGN_EHIP, "window launch: %s", hipGetErrorString(le));
       }
       mark(stage == 1 ? HSGN_K_WIN1 : HSGN_K_WIN2, false);
     }
@@ -757,6 +783,12 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
     }
   }
   if (rc == HSGN_OK) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      rc = fail(c, HSGN_EHIP, "hipDeviceGetAttribute failed");
+  }
+  if (rc == HSGN_OK) {
     if (hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
       rc = fail(c, HSGN_EHIP, "hipEventCreate failed");
@@ -778,6 +810,7 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_hmax, (size_t)n_inst);
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_status, (size_t)n_inst);
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_nstep, (size_t)n_inst);
+  if (rc == HSGN_OK) rc = dmalloc(c, &c->d_queue, (size_t)18);
   double** rp[] = {&c->d_rlo, &c->d_rdi, &c->d_rup, &c->d_rrhs, &c->d_rx,
                    &c->d_scp, &c->d_sy, &c->d_sv, &c->d_sw};
   for (double** p : rp)
@@ -821,7 +854,8 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
         hipMemsetAsync(c->d_smax, 0, n_inst * sizeof(unsigned long long), c->stream) != hipSuccess ||
         hipMemsetAsync(c->d_umax, 0, n_inst * sizeof(unsigned long long), c->stream) != hipSuccess ||
         hipMemsetAsync(c->d_status, 0, n_inst * sizeof(int32_t), c->stream) != hipSuccess ||
-        hipMemsetAsync(c->d_nstep, 0, n_inst * sizeof(int32_t), c->stream) != hipSuccess)
+        hipMemsetAsync(c->d_nstep, 0, n_inst * sizeof(int32_t), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_queue, 0, 18 * sizeof(int32_t), c->stream) != hipSuccess)
       rc = fail(c, HSGN_EHIP, "hipMemsetAsync failed");
   }
   // host vectors are freed on return: wait for the uploads
@@ -1208,6 +1242,39 @@ int hsgn_set_instance_solvers(hsgn_ctx* c, const int32_t* h_modes) {
   if (rc) return rc;
   rc = make_plan(c);
   if (rc) return rc;
+  return leave(c);
+}
+
+int hsgn_set_launch(hsgn_ctx* c, int32_t launch) {
+  if (!c) return HSGN_EINVAL;
+  if (launch != HSGN_LAUNCH_GRID && launch != HSGN_LAUNCH_PERSISTENT)
+    return fail(c, HSGN_EINVAL, "hsgn_set_launch: unknown launch %d", launch);
+  if (launch == HSGN_LAUNCH_PERSISTENT && !c->d_queue)
+    return fail(c, HSGN_EINVAL, "hsgn_set_launch: this context has no work queues");
+  if (launch != c->launch) {  // cached graphs hold the other kernels
+    for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+    c->launch = launch;
+  }
+  return HSGN_OK;
+}
+
+// Time the two window-stage launches on the current plan and keep the faster.
+int hsgn_autotune_launch(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_launch) {
+  if (!c) return HSGN_EINVAL;
+  if (nsteps < 1) return fail(c, HSGN_EINVAL, "hsgn_autotune_launch: nsteps < 1");
+  if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
+    return fail(c, HSGN_EINVAL, "hsgn_autotune_launch: only the semi-implicit step has windows");
+  if (!c->d_queue)
+    return fail(c, HSGN_EINVAL, "hsgn_autotune_launch: this context has no work queues");
+  int rc = enter(c);
+  if (rc) return rc;
+  double ms[2] = {0, 0};
+  int best = 0;
+  rc = time_plans(c, nsteps, 2, [&](int k) { return hsgn_set_launch(c, k); }, ms, &best);
+  if (rc) return rc;
+  if (h_ms) std::memcpy(h_ms, ms, sizeof ms);
+  if (h_launch) *h_launch = best;
   return leave(c);
 }
 

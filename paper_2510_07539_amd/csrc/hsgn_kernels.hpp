@@ -837,7 +837,7 @@ __global__ __launch_bounds__(NT) void k_rsolve(const InstDesc* __restrict__ inst
 // (nstep counts the steps each instance has taken since its state was
 // loaded: a flagged instance stops counting, so its count names the step in
 // which the flag was raised)
-__global__ void k_dt(int n_inst, const InstDesc* __restrict__ inst, double* __restrict__ dt,
+static __global__ void k_dt(int n_inst, const InstDesc* __restrict__ inst, double* __restrict__ dt,
                      double* __restrict__ tt, unsigned long long* __restrict__ smax,
                      unsigned long long* __restrict__ umax, const int32_t* __restrict__ status,
                      int32_t* __restrict__ nstep) {
@@ -938,11 +938,11 @@ __global__ __launch_bounds__(NT) void k_default_mW(const InstDesc* __restrict__ 
 }
 
 // Fill (used instead of memset so that the calls stay capturable).
-__global__ void k_fill_u64(int n, unsigned long long* __restrict__ p, unsigned long long v) {
+static __global__ void k_fill_u64(int n, unsigned long long* __restrict__ p, unsigned long long v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
-__global__ void k_fill_i32(int n, int32_t* __restrict__ p, int32_t v) {
+static __global__ void k_fill_i32(int n, int32_t* __restrict__ p, int32_t v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }

@@ -43,6 +43,8 @@ struct WinArgs {
   const WinDesc* __restrict__ win;
   int32_t nwin;
   int32_t xcd_stride;  // consecutive windows go to one XCD: see k_win
+  int32_t* queue;      // k_win_persist: 8 queue counters + 1 count of ended
+                       // workgroups (zero between launches)
 };
 
 // A value that is the same in every lane, computed on the vector unit (the
@@ -167,8 +169,7 @@ __device__ __forceinline__ Rec cell_record_fast(const Cell& e, const Cell& o, co
 
 // Level-1 interior solve with one reciprocal per row and level.
 template <int NT>
-__device__ void level1_interior_fast(Lds<NT>& S, int n1) {
-  const int t = threadIdx.x;
+__device__ void level1_interior_fast(Lds<NT>& S, int n1, const int t = threadIdx.x) {
   const int last = n1 - 2;
   const int m = n1 - 2;
   if (m <= 0) return;
@@ -292,9 +293,12 @@ struct WinLds {
   double side[2][4][5], sideo[2][4], sideb[2][5];
 };
 
+// One window of a stage: the body of k_win (one window per workgroup) and of
+// the persistent k_win_persist below.  t is the thread index (passed in so
+// that the persistent loop can keep it opaque).
 template <int NT, int K, bool BED, int STAGE>
-__global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
-  __shared__ WinLds<NT, K, BED> L;
+__device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L, const int bid,
+                                        const int t) {
   // Register budget: 256 per lane (two waves per SIMD).  Stage 1 fits it
   // when it also (i) addresses the staged loads with 32-bit offsets from
   // per-instance base pointers, (ii) forms the bed's rest-moment jump in
@@ -304,14 +308,6 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   // so it keeps the plain forms.  Both give the same values.
   constexpr bool kLean = STAGE == 1;
   const StageArgs& A = W.s;
-  // consecutive windows of an instance run on the same XCD (blocks are
-  // dealt round-robin over the 8 XCDs)
-  int bid = blockIdx.x;
-  if (W.xcd_stride > 0) {
-    const int x = bid & 7, r = bid >> 3;
-    bid = x * W.xcd_stride + r;
-  }
-  if (bid >= W.nwin) return;
   const WinDesc wd = W.win[bid];
   // Warm this XCD's L2 with the descriptor of the window that starts about
   // one block lifetime later (64 blocks run at once per XCD): a vector load
@@ -320,14 +316,13 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   // statement after the last staging round.
   int ahead = 0;
   {
-    int zero = threadIdx.x;
+    int zero = t;
     asm volatile("" : "+v"(zero));
     zero >>= 31;
     const int wa_ = bid + 64;
     const int lim = W.xcd_stride > 0 ? min(W.nwin, (bid / W.xcd_stride + 1) * W.xcd_stride) : W.nwin;
-    if (threadIdx.x == 0 && wa_ < lim) ahead = W.win[wa_ + zero].inst;
+    if (t == 0 && wa_ < lim) ahead = W.win[wa_ + zero].inst;
   }
-  const int t = threadIdx.x;
   const int n = wd.n, bc = wd.bc;
   const int64_t base = wd.off;
   constexpr int WN = NT * K;
@@ -823,7 +818,7 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   }
   __syncthreads();
   const int n1 = 2 * na;
-  level1_interior_fast<NT>(L.u.sys, n1);
+  level1_interior_fast<NT>(L.u.sys, n1, t);
 
   // ---- the window's end unknowns (couplings already on the right-hand side)
   if (t == 0) {
@@ -1008,6 +1003,67 @@ __global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
   }
   if (bad || noncoer) {
     atomicOr(&A.status[wd.inst], (bad ? kFlagNonPhys : 0) | (noncoer ? kFlagNonCoercive : 0));
+  }
+}
+
+// Stage kernel, one window per workgroup: consecutive windows of an
+// instance run on the same XCD (blocks are dealt round-robin over the 8
+// XCDs), so the halo rows they share hit that XCD's L2.
+template <int NT, int K, bool BED, int STAGE>
+__global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win(WinArgs W) {
+  __shared__ WinLds<NT, K, BED> L;
+  int bid = blockIdx.x;
+  if (W.xcd_stride > 0) {
+    const int x = bid & 7, r = bid >> 3;
+    bid = x * W.xcd_stride + r;
+  }
+  if (bid >= W.nwin) return;
+  win_one<NT, K, BED, STAGE>(W, L, bid, threadIdx.x);
+}
+
+// Persistent stage kernel: a grid of as many workgroups as are resident at
+// once (a multiple of 8) walks the windows through eight work queues, one
+// per XCD.  Queue x holds the contiguous window range [x stride,
+// (x + 1) stride), so consecutive windows of an instance stay on one XCD
+// (blocks are dealt round-robin over the XCDs).  A workgroup takes windows
+// from its own XCD's queue (one atomic ticket per window), then from the
+// others in turn; every workgroup ends once all eight are exhausted, and the
+// last to end resets the nine counters (queue[8] counts ended workgroups),
+// so the next launch, or graph replay, starts from zero.
+template <int NT, int K, bool BED, int STAGE>
+__global__ __launch_bounds__(NT, NT <= 256 ? 2 : 1) void k_win_persist(WinArgs W) {
+  __shared__ WinLds<NT, K, BED> L;
+  __shared__ int ticket;
+  const int x = blockIdx.x & 7;
+  for (int k = 0; k < 8; ++k) {
+    const int q = (x + k) & 7;
+    const int lo = q * W.xcd_stride;
+    const int hi = min(W.nwin, lo + W.xcd_stride);
+    while (true) {
+      __syncthreads();  // the previous window is done with the LDS and the ticket
+      if (threadIdx.x == 0) ticket = atomicAdd(&W.queue[q], 1);
+      __syncthreads();
+      const int w = lo + ticket;
+      if (w >= hi) break;
+      // the arguments are read again from the kernel-argument segment in
+      // every iteration (the pointer is made opaque), so the compiler does
+      // not keep them in scalar registers across the loop; likewise the
+      // thread index, so that no address derived from it is hoisted out of
+      // the loop and held in vector registers
+      typedef const WinArgs __attribute__((address_space(4)))* KargPtr;
+      KargPtr Wp = (KargPtr)__builtin_amdgcn_kernarg_segment_ptr();
+      asm volatile("" : "+s"(Wp));
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      win_one<NT, K, BED, STAGE>(*(const WinArgs*)Wp, L, w, tid);
+    }
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&W.queue[8], 1) == (int)gridDim.x - 1) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) atomicExch(&W.queue[i], 0);
+    }
   }
 }
 

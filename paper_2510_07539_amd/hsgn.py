@@ -22,6 +22,8 @@ KERNEL_KINDS = ("dt", "reduce1", "rsolve1", "stage1", "reduce2", "rsolve2", "sta
                 "ex1", "ex2", "sgn_rows", "sgn_solve", "sgn_update")
 SOLVER_AUTO, SOLVER_EXACT, SOLVER_AUTO_SMALL = 0, 1, 2
 SOLVERS = {"auto": SOLVER_AUTO, "exact": SOLVER_EXACT, "auto_small": SOLVER_AUTO_SMALL}
+LAUNCH_GRID, LAUNCH_PERSISTENT = 0, 1
+LAUNCHES = {"grid": LAUNCH_GRID, "persistent": LAUNCH_PERSISTENT}
 BC_PERIODIC, BC_TRANSMISSIVE = 0, 1
 SCHEME_SEMI_IMPLICIT, SCHEME_EXPLICIT, SCHEME_SGN = 0, 1, 2
 
@@ -81,6 +83,10 @@ def lib():
                                             C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                             C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                             C.POINTER(C.c_double)]
+        L.hsgn_set_launch.restype = C.c_int
+        L.hsgn_set_launch.argtypes = [vp, C.c_int32]
+        L.hsgn_autotune_launch.restype = C.c_int
+        L.hsgn_autotune_launch.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.hsgn_step_noalloc.restype = C.c_int
         L.hsgn_step_noalloc.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(HsgnParams),
                                         dp, dp, dp, dp, dp, dp, C.c_int32, C.c_int32, vp,
@@ -144,6 +150,23 @@ class Solver:
         self._check(lib().hsgn_autotune(self._h, int(nsteps), ms, C.byref(mode)), "hsgn_autotune")
         names = {v: k for k, v in SOLVERS.items()}
         return names[mode.value], {names[m]: ms[m] for m in range(3)}
+
+    def set_launch(self, launch):
+        """Window-stage launch: "grid" (one workgroup per window) or
+        "persistent" (resident workgroups walking per-XCD work queues)."""
+        k = LAUNCHES[launch] if isinstance(launch, str) else int(launch)
+        self._check(lib().hsgn_set_launch(self._h, k), "hsgn_set_launch")
+
+    def autotune_launch(self, nsteps=4):
+        """Time both window-stage launches on the current plan, keep the
+        faster, leave the state unchanged.  Returns (kept launch name,
+        {launch name: ms/step})."""
+        ms = (C.c_double * 2)()
+        k = C.c_int32(0)
+        self._check(lib().hsgn_autotune_launch(self._h, int(nsteps), ms, C.byref(k)),
+                    "hsgn_autotune_launch")
+        names = {v: n for n, v in LAUNCHES.items()}
+        return names[k.value], {names[i]: ms[i] for i in range(2)}
 
     def set_instance_solvers(self, modes):
         """Per-instance solver modes (names or HSGN_SOLVER_* values)."""

@@ -122,9 +122,10 @@ def oracle_dir(wl, j, z, target, gauges, nsteps, vz=None, vb=None):
     return J.imag / EPS_CS, J.real
 
 
-def run_gpu(wl, z_all, gauges, targets, nsteps, K, grad=True):
+def run_gpu(wl, z_all, gauges, targets, nsteps, K, grad=True, launch="grid"):
     hs = _hsgn()
     s = hs.Solver.from_workload(wl)
+    s.set_launch(launch)
     try:
         dev = "cuda"
         loss, gz, gb = s.adjoint(nsteps, K, torch.from_numpy(gauges).to(dev),
@@ -281,6 +282,17 @@ def test_adjoint_checkpoint_interval_invariant(mixed):
         assert np.array_equal(gb, mixed["gb"]), K
 
 
+def test_adjoint_persistent_launch_bitwise(mixed):
+    """The adjoint with the persistent window launch (the forward pass on
+    the library's stream, the recomputes on the recompute stream, each with
+    its own queues) gives the grid launch's loss and gradients bit for bit."""
+    loss, gz, gb = run_gpu(mixed["wl"], mixed["z_all"], mixed["gauges"], mixed["targets"],
+                           mixed["nsteps"], mixed["K"], launch="persistent")
+    assert np.array_equal(loss, mixed["loss"])
+    assert np.array_equal(gz, mixed["gz"])
+    assert np.array_equal(gb, mixed["gb"])
+
+
 def test_adjoint_autograd_function(mixed):
     hs = _hsgn()
     wl = mixed["wl"]
@@ -351,6 +363,23 @@ def test_adjoint_reports_an_instance_flagged_in_the_forward_pass(mixed):
         assert np.array_equal(gz.cpu().numpy(), mixed["gz"])
     finally:
         s.close()
+
+
+@pytest.mark.timeout(300)
+def test_adjoint_full_size_persistent_launch_bitwise():
+    """The gradient workload at full size (thousands of windows per launch)
+    over 40 steps with checkpoints every 20: the persistent window launch
+    gives the grid launch's loss and gradients bit for bit."""
+    case = WL.adjoint_bar()
+    wl, K = case.wl, case.K
+    nsteps = 40
+    rng = np.random.default_rng(8)
+    targets = 0.4 + 1e-3 * rng.standard_normal((wl.n_inst, nsteps, case.gauges.shape[1]))
+    note("adjoint full, persistent vs grid: %d instances, %d steps" % (wl.n_inst, nsteps))
+    ref = run_gpu(wl, case.zeta0, case.gauges, targets, nsteps, K)
+    got = run_gpu(wl, case.zeta0, case.gauges, targets, nsteps, K, launch="persistent")
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y)
 
 
 # ---------------------------------------------------------------------------

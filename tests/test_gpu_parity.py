@@ -455,6 +455,97 @@ def test_per_instance_solver_modes_match_the_oracle():
         check_instance(j, U, wl, 30)
 
 
+def _equal_states(a, b):
+    (Ua, ta), (Ub, tb) = a.get_state(), b.get_state()
+    for x, y in zip(Ua, Ub):
+        assert torch.equal(x, y)
+    assert torch.equal(ta, tb)
+    return Ua
+
+
+def test_persistent_launch_bitwise_equals_grid():
+    """HSGN_LAUNCH_PERSISTENT computes each window exactly as the grid launch
+    does: on a batch with both window widths and two-pass instances (flat
+    and bed instances, both boundary types), eager steps and replays of a
+    captured graph, with eager steps between them, equal the grid launch's
+    bitwise; the result matches the oracle."""
+    Solver = _solver()
+    wl = _modes_case()
+    modes = ["auto", "auto_small", "exact", "auto_small", "auto", "exact", "auto_small", "auto"]
+    a = Solver.from_workload(wl)
+    b = Solver.from_workload(wl)
+    for s in (a, b):
+        s.set_instance_solvers(modes)
+    b.set_launch("persistent")
+    a.step(10)
+    b.step(10)
+    _equal_states(a, b)
+    b.run(20, block=10)
+    b.step(3)
+    b.run(20, block=10)
+    a.step(43)
+    U = _equal_states(a, b)
+    for s in (a, b):
+        rc, _ = s.status()
+        assert rc == 0
+    a.close()
+    b.close()
+    U = [x.cpu().numpy() for x in U]
+    for j in range(wl.n_inst):
+        check_instance(j, U, wl, 53)
+
+
+@pytest.mark.parametrize("case", ["bar_auto", "bar_auto_small", "flat_long"])
+def test_persistent_launch_full_size_bitwise(case):
+    """At full size (thousands of windows: more than the resident
+    workgroups, so each takes many windows from its XCD's queue and then
+    from the other queues) the persistent launch equals the grid launch
+    bitwise, over graph replays and eager steps: the batched workload over
+    the bar in both window widths, and the 2^24-cell periodic flat run."""
+    Solver = _solver()
+    if case == "flat_long":
+        wl, solver = WL.long_periodic(), "auto_small"
+    else:
+        wl, solver = WL.batched_bar(), case[4:]
+    note("persistent vs grid: %s, %d cells, %s" % (case, wl.n_cells, solver))
+    a = Solver.from_workload(wl, solver=solver)
+    b = Solver.from_workload(wl, solver=solver)
+    b.set_launch("persistent")
+    note("  %d windows" % b.plan_info()["windows"])
+    for s in (a, b):
+        s.run(20, block=10)
+        s.step(3)
+        s.run(10, block=10)
+    _equal_states(a, b)
+    for s in (a, b):
+        rc, _ = s.status()
+        assert rc == 0
+    a.close()
+    b.close()
+
+
+def test_autotune_launch_keeps_state_and_faster_launch():
+    """hsgn_autotune_launch leaves the loaded state, time and status bitwise
+    as they were and keeps the launch with the smaller measured time; the
+    steps that follow equal the grid launch's bitwise."""
+    Solver = _solver()
+    wl = WL.batched_bar(n_inst=64, seed=17, n_lo=4000, n_hi=30000, nsteps=10)
+    s = Solver.from_workload(wl, solver="auto_small")
+    (h0, q0, m0, W0), t0 = s.get_state()
+    kept, ms = s.autotune_launch(3)
+    note("autotune_launch: kept %s, ms/step %s" % (kept, ms))
+    assert kept == min(ms, key=ms.get)
+    (h1, q1, m1, W1), t1 = s.get_state()
+    for x, y in ((h0, h1), (q0, q1), (m0, m1), (W0, W1), (t0, t1)):
+        assert torch.equal(x, y)
+    g = Solver.from_workload(wl, solver="auto_small")
+    s.step(10)
+    g.step(10)
+    _equal_states(s, g)
+    s.close()
+    g.close()
+
+
 def test_autotune_classes_table_round_trip():
     """hsgn_autotune_classes: every instance is in one class, the loaded
     state is left bitwise as it was, and a context that applies the stored
