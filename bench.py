@@ -30,15 +30,15 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # hash of the sources of its kernels and reported as null once they change.
 TRAFFIC = [
     {"kernel": "win2", "workload": "batched_bar", "solver": "auto_small",
-     "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp"], "hash": "0c27ad949886b9ea",
-     "fetch_bytes": 2674880436, "write_bytes": 1412813323, "bytes_per_launch": 4087693759},
+     "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp"], "hash": "1929140f522917c8",
+     "fetch_bytes": 2677900575, "write_bytes": 1412305931, "bytes_per_launch": 4090206506},
     {"kernel": "ex2", "workload": "batched_flat", "scheme": "explicit",
-     "sources": ["hsgn_kernels.hpp", "hsgn_explicit.hpp"], "hash": "9de8412d86e0c6a4",
-     "fetch_bytes": 2233082922, "write_bytes": 1118370752, "bytes_per_launch": 3351453674},
+     "sources": ["hsgn_kernels.hpp", "hsgn_explicit.hpp"], "hash": "7edb7460c755b98f",
+     "fetch_bytes": 2232878435, "write_bytes": 1118349045, "bytes_per_launch": 3351227480},
     {"kernel": "sgn_solve", "workload": "batched_flat", "scheme": "sgn",
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp",
-                 "hsgn_explicit.hpp"], "hash": "d9fc151161de7be3",
-     "fetch_bytes": 2207553446, "write_bytes": 276611424, "bytes_per_launch": 2484164870},
+                 "hsgn_explicit.hpp"], "hash": "161c9434df60ff3e",
+     "fetch_bytes": 2207025579, "write_bytes": 276548192, "bytes_per_launch": 2483573771},
 ]
 
 def src_hash(sources):
