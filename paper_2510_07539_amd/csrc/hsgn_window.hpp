@@ -248,6 +248,128 @@ __device__ void level1_interior_fast(Lds<NT>& S, int n1, const int t = threadIdx
   __syncthreads();
 }
 
+// Ordering of LDS accesses among the lanes of one wavefront: a wavefront's
+// LDS operations are performed in the order it issues them, so its lanes
+// exchange values through LDS without a workgroup barrier.  The fences
+// only keep the compiler from moving loads and stores across this point
+// (at wavefront scope they emit no instruction).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Level-1 solve of one wavefront's segment of rows [F, E] (F < E): the
+// interior rows F + 1 .. E - 1 are eliminated by parallel cyclic reduction
+// in terms of the segment's end unknowns x_F and x_E, by the wavefront's
+// 64 lanes (lane l) and with no workgroup barrier.  On exit d0, d1, d2 of an
+// interior row hold Y, V, W with x_j = Y_j + V_j x_F + W_j x_E; the end rows
+// keep their coefficients.  The reduction stops at the first level after
+// which every coupling left is below 2^-66 of its diagonal: the levels after
+// it would change no digit of the solution.
+template <int NT>
+__device__ void segment_pcr(Lds<NT>& S, const int F, const int E, const int l) {
+  const int m = E - F - 1;  // interior rows
+  if (m <= 0) return;
+  if (l == 0) {
+    S.d1[F + 1] = -S.a[F + 1];
+    S.a[F + 1] = 0.0;
+    S.d2[E - 1] = -S.c[E - 1];
+    S.c[E - 1] = 0.0;
+  }
+  wave_lds_sync();
+  for (int s = 1; s < m; s <<= 1) {
+    double na[2], nb[2], nc[2], n0[2], n1v[2], n2[2];
+    bool own[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int jr = 1 + l + 64 * r;  // segment-relative row
+      own[r] = jr <= m;
+      if (own[r]) {
+        const int j = F + jr;
+        const int jm = j - s, jp = j + s;
+        const bool hm = jr - s >= 1, hp = jr + s <= m;
+        const double a = S.a[j], c = S.c[j];
+        const double k1 = hm ? a * frcp(S.b[jm]) : 0.0;
+        const double k2 = hp ? c * frcp(S.b[jp]) : 0.0;
+        na[r] = hm ? -k1 * S.a[jm] : 0.0;
+        nc[r] = hp ? -k2 * S.c[jp] : 0.0;
+        double bb = S.b[j];
+        double e0 = S.d0[j], e1 = S.d1[j], e2 = S.d2[j];
+        if (hm) {
+          bb -= k1 * S.c[jm];
+          e0 -= k1 * S.d0[jm];
+          e1 -= k1 * S.d1[jm];
+          e2 -= k1 * S.d2[jm];
+        }
+        if (hp) {
+          bb -= k2 * S.a[jp];
+          e0 -= k2 * S.d0[jp];
+          e1 -= k2 * S.d1[jp];
+          e2 -= k2 * S.d2[jp];
+        }
+        nb[r] = bb;
+        n0[r] = e0;
+        n1v[r] = e1;
+        n2[r] = e2;
+      }
+    }
+    wave_lds_sync();
+    bool more = false;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (own[r]) {
+        const int j = F + 1 + l + 64 * r;
+        S.a[j] = na[r];
+        S.b[j] = nb[r];
+        S.c[j] = nc[r];
+        S.d0[j] = n0[r];
+        S.d1[j] = n1v[r];
+        S.d2[j] = n2[r];
+        const double lim = 1.3552527156068805e-20 * fabs(nb[r]);  // 2^-66
+        more |= !(fabs(na[r]) <= lim) || !(fabs(nc[r]) <= lim);
+      }
+    }
+    const bool again = __ballot(more) != 0;  // the same in every lane
+    wave_lds_sync();
+    if (!again) break;
+  }
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int jr = 1 + l + 64 * r;
+    if (jr <= m) {
+      const int j = F + jr;
+      const double ib = frcp(S.b[j]);
+      S.d0[j] *= ib;
+      S.d1[j] *= ib;
+      S.d2[j] *= ib;
+    }
+  }
+  wave_lds_sync();
+}
+
+// The end rows F and E of a segment solved by segment_pcr, with its
+// interior substituted (x_{F+1} and x_{E-1} from Y, V, W): rows of the
+// tridiagonal system in the segments' end unknowns (x_{F_0}, x_{E_0},
+// x_{F_1}, x_{E_1}, ...) as (lower, diagonal, upper, right-hand side).
+template <int NT>
+__device__ __forceinline__ void segment_ends(const Lds<NT>& S, int F, int E, double R0[4],
+                                             double R1[4]) {
+  if (E == F + 1) {
+    R0[0] = S.a[F]; R0[1] = S.b[F]; R0[2] = S.c[F]; R0[3] = S.d0[F];
+    R1[0] = S.a[E]; R1[1] = S.b[E]; R1[2] = S.c[E]; R1[3] = S.d0[E];
+    return;
+  }
+  R0[0] = S.a[F];
+  R0[1] = S.b[F] + S.c[F] * S.d1[F + 1];
+  R0[2] = S.c[F] * S.d2[F + 1];
+  R0[3] = S.d0[F] - S.c[F] * S.d0[F + 1];
+  R1[0] = S.a[E] * S.d1[E - 1];
+  R1[1] = S.b[E] + S.a[E] * S.d2[E - 1];
+  R1[2] = S.c[E];
+  R1[3] = S.d0[E] - S.a[E] * S.d0[E - 1];
+}
+
 // LDS layout of a staged window field: one pad double after every 8 so that
 // a thread reading its K consecutive values does not collide on banks.
 __device__ __forceinline__ int spad(int i) { return i + (i >> 3); }
@@ -287,6 +409,12 @@ struct WinLds {
                 "the level-1 system and the record exchange must fit in the staging buffers "
                 "e and o");
   double misc[16];
+  // system of the wavefront segments' end unknowns: rows (lower, diagonal,
+  // upper, right-hand side), then its solution and the solution's
+  // derivatives with respect to the left and right edge guesses
+  static constexpr int NW = NT / 64;
+  double l2[4][2 * NW];
+  double l2x[3][2 * NW];
   // inputs of the outer rows of truncated edges (window rows -1 and wl):
   // U_E of five staged cells, the row's old state, the bed (side 0 left,
   // side 1 right)
@@ -816,38 +944,128 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
     if (t == 0) L.misc[2] = loE;
     if (t == na - 1) L.misc[3] = upE;
   }
-  __syncthreads();
+  // ---- level-1 system (rows 2t, 2t + 1 of every active thread).  It yields
+  // the depths zf, zb of this thread's two level-1 rows and their
+  // derivatives with respect to the left and right edge guesses.
   const int n1 = 2 * na;
-  level1_interior_fast<NT>(L.u.sys, n1, t);
-
-  // ---- the window's end unknowns (couplings already on the right-hand side)
-  if (t == 0) {
-    double R0[4], R1[4];
-    tile_rows<NT>(L.u.sys, n1, R0, R1);
-    const double m00 = R0[1], m01 = R0[2], m10 = R1[0], m11 = R1[1];
-    const double idet = 1.0 / (m00 * m11 - m01 * m10);
-    const double i00 = m11 * idet, i01 = -m01 * idet, i10 = -m10 * idet, i11 = m00 * idet;
-    L.misc[4] = i00 * R0[3] + i01 * R1[3];  // z0
-    L.misc[5] = i10 * R0[3] + i11 * R1[3];  // zl
-    // d(z0, zl)/d(guess): left guess enters row 0 as -loE, right as -upE
-    L.misc[6] = -L.misc[2] * i00;
-    L.misc[7] = -L.misc[2] * i10;
-    L.misc[8] = -L.misc[3] * i01;
-    L.misc[9] = -L.misc[3] * i11;
+  double zf = 0.0, zb = 0.0, GfL = 0.0, GfR = 0.0, GbL = 0.0, GbR = 0.0;
+  // Windows of 256 threads solve it by wavefront segments: wavefront w
+  // eliminates the interior of its rows [128 w, 128 w + 128) by PCR (no
+  // workgroup barrier), one thread solves the system of the segments' end
+  // unknowns (two per wavefront), and every row follows from its segment's
+  // ends.  Windows of 512 threads (16 end unknowns for the one thread)
+  // measured faster with the workgroup-wide PCR of the interior rows in
+  // terms of the window's two end unknowns.
+  constexpr bool kWaveSeg = NT <= 256;
+  if constexpr (kWaveSeg) {
+    const int wv = t >> 6, ln = t & 63;
+    const int F = 128 * wv, E = min(F + 127, n1 - 1);
+    wave_lds_sync();  // this wavefront's rows are written
+    if (F < n1) {
+      segment_pcr<NT>(L.u.sys, F, E, ln);
+      if (ln == 0) {
+        double R0[4], R1[4];
+        segment_ends<NT>(L.u.sys, F, E, R0, R1);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          L.l2[e][2 * wv] = R0[e];
+          L.l2[e][2 * wv + 1] = R1[e];
+        }
+      }
+    }
+    __syncthreads();
+    if (t == 0) {
+      // Thomas on the end unknowns, for the right-hand side and for unit
+      // changes of the edge guesses (the left guess enters the first row as
+      // -loE, the right guess the last row as -upE)
+      const int nr = 2 * ((n1 + 127) / 128);
+      const double loE = L.misc[2], upE = L.misc[3];
+      double cp = 0.0, y0 = 0.0, yl = 0.0, yr = 0.0;
+      for (int k = 0; k < nr; ++k) {
+        const double lo = L.l2[0][k];
+        const double inv = frcp(L.l2[1][k] - lo * cp);
+        cp = L.l2[2][k] * inv;
+        L.l2[2][k] = cp;
+        y0 = (L.l2[3][k] - lo * y0) * inv;
+        yl = ((k == 0 ? -loE : 0.0) - lo * yl) * inv;
+        yr = ((k == nr - 1 ? -upE : 0.0) - lo * yr) * inv;
+        L.l2x[0][k] = y0;
+        L.l2x[1][k] = yl;
+        L.l2x[2][k] = yr;
+      }
+      for (int k = nr - 2; k >= 0; --k) {
+        const double c = L.l2[2][k];
+        y0 = L.l2x[0][k] - c * y0;
+        yl = L.l2x[1][k] - c * yl;
+        yr = L.l2x[2][k] - c * yr;
+        L.l2x[0][k] = y0;
+        L.l2x[1][k] = yl;
+        L.l2x[2][k] = yr;
+      }
+    }
+    __syncthreads();
+    if (act) {
+      const Lds<NT>& S = L.u.sys;
+      const double uF = L.l2x[0][2 * wv], uE = L.l2x[0][2 * wv + 1];
+      const double lF = L.l2x[1][2 * wv], lE = L.l2x[1][2 * wv + 1];
+      const double rF = L.l2x[2][2 * wv], rE = L.l2x[2][2 * wv + 1];
+      const int j0 = 2 * t, j1 = 2 * t + 1;
+      if (j0 == F) {
+        zf = uF; GfL = lF; GfR = rF;
+      } else {
+        const double V = S.d1[j0], Wv = S.d2[j0];
+        zf = S.d0[j0] + V * uF + Wv * uE;
+        GfL = V * lF + Wv * lE;
+        GfR = V * rF + Wv * rE;
+      }
+      if (j1 == E) {
+        zb = uE; GbL = lE; GbR = rE;
+      } else {
+        const double V = S.d1[j1], Wv = S.d2[j1];
+        zb = S.d0[j1] + V * uF + Wv * uE;
+        GbL = V * lF + Wv * lE;
+        GbR = V * rF + Wv * rE;
+      }
+    }
+  } else {
+    __syncthreads();
+    level1_interior_fast<NT>(L.u.sys, n1, t);
+    // the window's end unknowns (couplings already on the right-hand side)
+    if (t == 0) {
+      double R0[4], R1[4];
+      tile_rows<NT>(L.u.sys, n1, R0, R1);
+      const double m00 = R0[1], m01 = R0[2], m10 = R1[0], m11 = R1[1];
+      const double idet = 1.0 / (m00 * m11 - m01 * m10);
+      const double i00 = m11 * idet, i01 = -m01 * idet, i10 = -m10 * idet, i11 = m00 * idet;
+      L.misc[4] = i00 * R0[3] + i01 * R1[3];  // z0
+      L.misc[5] = i10 * R0[3] + i11 * R1[3];  // zl
+      // d(z0, zl)/d(guess): left guess enters row 0 as -loE, right as -upE
+      L.misc[6] = -L.misc[2] * i00;
+      L.misc[7] = -L.misc[2] * i10;
+      L.misc[8] = -L.misc[3] * i01;
+      L.misc[9] = -L.misc[3] * i11;
+    }
+    __syncthreads();
+    if (act) {
+      const double z0 = L.misc[4], zl = L.misc[5];
+      const double dz0L = L.misc[6], dzlL = L.misc[7], dz0R = L.misc[8], dzlR = L.misc[9];
+      const Lds<NT>& S = L.u.sys;
+      const int j0 = 2 * t, j1 = 2 * t + 1;
+      double Vf, Wf, Vb, Wb;  // d(zf, zb) / d(z0, zl)
+      if (j0 == 0) { zf = z0; Vf = 1.0; Wf = 0.0; }
+      else { zf = S.d0[j0] + S.d1[j0] * z0 + S.d2[j0] * zl; Vf = S.d1[j0]; Wf = S.d2[j0]; }
+      if (j1 == n1 - 1) { zb = zl; Vb = 0.0; Wb = 1.0; }
+      else { zb = S.d0[j1] + S.d1[j1] * z0 + S.d2[j1] * zl; Vb = S.d1[j1]; Wb = S.d2[j1]; }
+      GfL = Vf * dz0L + Wf * dzlL;
+      GfR = Vf * dz0R + Wf * dzlR;
+      GbL = Vb * dz0L + Wb * dzlL;
+      GbR = Vb * dz0R + Wb * dzlR;
+    }
+    __syncthreads();  // every thread has read its rows before a[] takes the depths
   }
-  __syncthreads();
-  const double z0 = L.misc[4], zl = L.misc[5];
-  double zf = 0.0, zb = 0.0, Vf = 0.0, Wf = 0.0, Vb = 0.0, Wb = 0.0;
   if (act) {
-    const Lds<NT>& S = L.u.sys;
-    const int j0 = 2 * t, j1 = 2 * t + 1;
-    if (j0 == 0) { zf = z0; Vf = 1.0; Wf = 0.0; }
-    else { zf = S.d0[j0] + S.d1[j0] * z0 + S.d2[j0] * zl; Vf = S.d1[j0]; Wf = S.d2[j0]; }
-    if (j1 == n1 - 1) { zb = zl; Vb = 0.0; Wb = 1.0; }
-    else { zb = S.d0[j1] + S.d1[j1] * z0 + S.d2[j1] * zl; Vb = S.d1[j1]; Wb = S.d2[j1]; }
-  }
-  __syncthreads();
-  if (act) {
+    // a[] of this thread's rows takes their depths (no other thread reads
+    // this thread's rows at this point)
     L.u.sys.a[2 * t] = zf;
     L.u.sys.a[2 * t + 1] = zb;
   }
@@ -869,17 +1087,16 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
     const int jl = wd.wl - 1 - p0;
     // certificate at the core's edge rows
     if ((truncL || truncR) && ((p0 <= c0 && c0 < p0 + K) || (p0 <= c1 - 1 && c1 - 1 < p0 + K))) {
-      const double dz0L = L.misc[6], dzlL = L.misc[7], dz0R = L.misc[8], dzlR = L.misc[9];
       const double X = 4.0 * fmax(fabs(gL), fabs(gR));
 #pragma unroll
       for (int j = 0; j < K; ++j) {
         const int p = p0 + j;
         if (p == c0 || p == c1 - 1) {
-          double s0, sl;  // d x_p / d z0, d x_p / d zl
-          if (j == 0) { s0 = Vf; sl = Wf; }
-          else if (j == K - 1) { s0 = Vb; sl = Wb; }
-          else { s0 = v[j] * Vf + w[j] * Vb; sl = v[j] * Wf + w[j] * Wb; }
-          const double sens = fabs(s0 * dz0L + sl * dzlL) + fabs(s0 * dz0R + sl * dzlR);
+          double sgL, sgR;  // d x_p / d (left guess), d x_p / d (right guess)
+          if (j == 0) { sgL = GfL; sgR = GfR; }
+          else if (j == K - 1) { sgL = GbL; sgR = GbR; }
+          else { sgL = v[j] * GfL + w[j] * GbL; sgR = v[j] * GfR + w[j] * GbR; }
+          const double sens = fabs(sgL) + fabs(sgR);
           if (!(sens * X <= 1.3877787807814457e-17 * fabs(hb[j]))) {  // 2^-56
             atomicOr(&A.status[wd.inst], kFlagWindow);
           }
