@@ -61,8 +61,7 @@ def bytes_per_cell(kind, bed):
             "reduce2": (8 + b) * 8,         # reads U^n, U^(1) (+ b)
             "ex1": (4 + 4) * 8,             # explicit Heun stage 1: reads U^n, writes U1
             "ex2": (8 + 4) * 8,             # stage 2: reads U^n and U1, writes U^{n+1}
-            "sgn_rows": (2 + 4) * 8,        # SGN: reads h, q; writes the 4 bands
-            "sgn_solve": (4 + 1) * 8,       # reads the bands, writes phi
+            "sgn_solve": (2 + 1) * 8,       # SGN: reads h, q (rows formed in the solve), writes phi
             "sgn_update": (2 + 1 + 2) * 8,  # reads h, q, phi; writes h, q (stage 1)
             }.get(kind, 0)
 
@@ -431,7 +430,7 @@ def main():
     ms_avg, launches = kt[dom][0] / max(kt[dom][1], 1), kt[dom][1]
     cells_launch = {"reduce1": ex_multi_cells, "reduce2": ex_multi_cells, "stage1": ex_cells,
                     "stage2": ex_cells, "win1": win_cells, "win2": win_cells,
-                    "ex1": wl.n_cells, "ex2": wl.n_cells, "sgn_rows": wl.n_cells,
+                    "ex1": wl.n_cells, "ex2": wl.n_cells,
                     "sgn_solve": wl.n_cells, "sgn_update": wl.n_cells}.get(dom, 0)
     alg_bytes = bytes_per_cell(dom, bed) * cells_launch
     achieved = alg_bytes / (ms_avg * 1e-3) / 1e9 if ms_avg > 0 else 0.0

@@ -278,7 +278,7 @@ int hsgn_plan_info(hsgn_ctx* ctx, int32_t* h_mode, int32_t* h_halo, int32_t* h_c
 #define HSGN_K_WIN2 8         /* stage 2, windowed single pass               */
 #define HSGN_K_EX1 9          /* explicit scheme, first Heun stage           */
 #define HSGN_K_EX2 10         /* explicit scheme, second Heun stage          */
-#define HSGN_K_SGN_ROWS 11    /* SGN: rows of the phi system (both stages)   */
+#define HSGN_K_SGN_ROWS 11    /* SGN: unused (rows are formed in the solve)  */
 #define HSGN_K_SGN_SOLVE 12   /* SGN: batched tridiagonal solve for phi      */
 #define HSGN_K_SGN_UPDATE 13  /* SGN: flux update with the source h phi      */
 #define HSGN_NKERNEL 14

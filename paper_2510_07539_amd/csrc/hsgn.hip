@@ -86,7 +86,7 @@ struct hsgn_ctx {
   int scheme = HSGN_SCHEME_SEMI_IMPLICIT;  // or the explicit Heun step
   TileDesc* d_xtiles = nullptr;  // tiles of the explicit and SGN kernels (kExTile cells)
   int nxtiles = 0;
-  double* d_sgn = nullptr;       // SGN: rows lo, di, up, rhs of the phi system, and phi
+  double* d_sgn = nullptr;       // SGN: phi
   double* d_dt = nullptr;
   double* d_t = nullptr;
   unsigned long long* d_smax = nullptr;
@@ -316,17 +316,15 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
     mark(HSGN_K_DT, false);
   }
   if (c->scheme == HSGN_SCHEME_SGN) {
-    // Heun on the SGN operator: rows of the phi system, batched tridiagonal
-    // solve (one workgroup per instance), flux update with the source h phi
+    // Heun on the SGN operator: exact tiled solve of the phi system (rows
+    // formed in the solve), flux update with the source h phi
     double* const* un = c->buf[c->cur];
     double* const* u1 = c->buf[c->s1];
     double* const* out = c->buf[c->nxt];
-    const size_t nc = (size_t)c->ncell;
     hsgn::SgnArgs x;
     std::memset(&x, 0, sizeof x);
     x.un_h = un[0]; x.un_q = un[1]; x.un_m = un[2]; x.un_W = un[3];
-    x.lo = c->d_sgn; x.di = c->d_sgn + nc; x.up = c->d_sgn + 2 * nc; x.rhs = c->d_sgn + 3 * nc;
-    x.phi = c->d_sgn + 4 * nc;
+    x.phi = c->d_sgn;
     x.inst = c->d_inst;
     x.tiles = c->d_xtiles;
     x.dt = c->d_dt;
@@ -334,33 +332,31 @@ int enqueue_step(hsgn_ctx* c, std::vector<std::pair<int, std::pair<hipEvent_t, h
     x.umax = c->d_umax;
     x.status = c->d_status;
     // exact tiled solve of phi on the two-pass tiling (tiles of kTileMax rows)
-    hsgn::TriArgs ta;
+    hsgn::SgnTriArgs ta;
     ta.inst = c->d_inst;
     ta.dt = c->d_dt;
-    ta.lo = x.lo; ta.di = x.di; ta.up = x.up; ta.rhs = x.rhs;
-    ta.x = c->d_sgn + 4 * nc;
+    ta.phi = c->d_sgn;
     ta.rlo = c->d_rlo; ta.rdi = c->d_rdi; ta.rup = c->d_rup; ta.rrhs = c->d_rrhs;
     ta.rx = c->d_rx;
+    ta.status = c->d_status;
     for (int stage = 1; stage <= 2; ++stage) {
       double* const* in = stage == 1 ? un : u1;
       double* const* o = stage == 1 ? u1 : out;
       x.in_h = in[0]; x.in_q = in[1];
       x.o_h = o[0]; x.o_q = o[1]; x.o_m = o[2]; x.o_W = o[3];
-      mark(HSGN_K_SGN_ROWS, true);
-      hipLaunchKernelGGL((hsgn::k_sgn_rows<hsgn::kSgnNT, hsgn::kSgnK>), dim3(c->nxtiles),
-                         dim3(hsgn::kSgnNT), 0, c->stream, x);
-      mark(HSGN_K_SGN_ROWS, false);
+      ta.h = in[0];
+      ta.q = in[1];
       mark(HSGN_K_SGN_SOLVE, true);
       if (c->n_multi_inst > 0) {
         ta.tiles = c->d_tiles_multi;
-        hipLaunchKernelGGL((hsgn::k_tri_tiles<kTileMax / 8, 8, true>), dim3(c->ntiles_multi),
+        hipLaunchKernelGGL((hsgn::k_sgn_tri<kTileMax / 8, 8, true>), dim3(c->ntiles_multi),
                            dim3(kTileMax / 8), 0, c->stream, ta);
         hipLaunchKernelGGL(hsgn::k_rsolve<kNTR>, dim3(c->n_multi_inst), dim3(kNTR), 0, c->stream,
                            c->d_inst, c->d_multi, c->d_dt, c->d_rlo, c->d_rdi, c->d_rup,
                            c->d_rrhs, c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw);
       }
       ta.tiles = c->d_tiles_all;
-      hipLaunchKernelGGL((hsgn::k_tri_tiles<kTileMax / 8, 8, false>), dim3(c->ntiles_all),
+      hipLaunchKernelGGL((hsgn::k_sgn_tri<kTileMax / 8, 8, false>), dim3(c->ntiles_all),
                          dim3(kTileMax / 8), 0, c->stream, ta);
       mark(HSGN_K_SGN_SOLVE, false);
       mark(HSGN_K_SGN_UPDATE, true);
@@ -798,7 +794,7 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_tiles_all, tall.size());
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_tiles_multi, tmulti.size());
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_xtiles, xt.size());
-  if (rc == HSGN_OK && c->scheme == HSGN_SCHEME_SGN) rc = dmalloc(c, &c->d_sgn, 5 * nc);
+  if (rc == HSGN_OK && c->scheme == HSGN_SCHEME_SGN) rc = dmalloc(c, &c->d_sgn, nc);
   if (rc == HSGN_OK) rc = dmalloc(c, &c->d_multi, multi.size());
   for (int i = 0; i < 3 && rc == HSGN_OK; ++i)
     for (int f = 0; f < 4 && rc == HSGN_OK; ++f) rc = dmalloc(c, &c->buf[i][f], nc);

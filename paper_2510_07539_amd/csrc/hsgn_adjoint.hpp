@@ -857,51 +857,24 @@ struct AdjSolveArgs {
 };
 
 // Register-resident chunk elimination of n <= NT * K rows (a whole system or
-// one tile of it): each thread eliminates its chunk (consecutive rows, read
-// straight from global memory) into two rows of the level-1 system in LDS,
+// one tile of it): each thread eliminates its chunk (consecutive rows) into
+// two rows of the level-1 system in LDS,
 // keeping the chunk's interior spikes (y, v, w) in registers.  All threads
 // call it; the caller synchronises before the level-1 solve.
-template <int NT, int K>
-__device__ __forceinline__ Chunk reg_chunk_elim(Lds<NT>& S, const double* __restrict__ lo,
-                                                const double* __restrict__ di,
-                                                const double* __restrict__ up,
-                                                const double* __restrict__ rhs, int n,
-                                                double (&y)[K], double (&v)[K], double (&w)[K]) {
+//
+// The rows come from rows(f, k, Lo, Di, Up, Rh), which fills the K rows of
+// the chunk of k rows starting at row f (rows k .. K - 1 repeat row k - 1).
+template <int NT, int K, class Rows>
+__device__ __forceinline__ Chunk reg_chunk_elim_rows(Lds<NT>& S, int n, double (&y)[K],
+                                                     double (&v)[K], double (&w)[K], Rows rows) {
   const int t = threadIdx.x;
   const Chunk ch = chunk_of(n, NT, t);
   const int k = ch.k;  // 2 <= k <= K for active threads
   const int f = ch.first;
   if (t < ch.active) {
-    // every row of the chunk is loaded before the elimination starts (the
-    // K loads of one lane share cache lines; issued together they are
-    // served by one fetch)
     double Lo[K], Di[K], Up[K], Rh[K];
-    if (k == K && K % 2 == 0) {
-      // a full chunk: two rows per 16-byte load (8-byte alignment suffices
-      // for global memory on this target; measured: transposed solve of the
-      // gradient -9 %, SGN solve -10 %)
-      typedef double d2a8 __attribute__((ext_vector_type(2), aligned(8)));
-#pragma unroll
-      for (int i = 0; i < K; i += 2) {
-        const d2a8 a = *(const d2a8*)(lo + f + i);
-        const d2a8 b = *(const d2a8*)(di + f + i);
-        const d2a8 c = *(const d2a8*)(up + f + i);
-        const d2a8 d = *(const d2a8*)(rhs + f + i);
-        Lo[i] = a.x; Lo[i + 1] = a.y;
-        Di[i] = b.x; Di[i + 1] = b.y;
-        Up[i] = c.x; Up[i + 1] = c.y;
-        Rh[i] = d.x; Rh[i + 1] = d.y;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < K; ++i) {
-        const int r = f + (i < k ? i : k - 1);
-        Lo[i] = lo[r];
-        Di[i] = di[r];
-        Up[i] = up[r];
-        Rh[i] = rhs[r];
-      }
-    }
+    rows(f, k, Lo, Di, Up, Rh);
+
     double cp[K];
     double cprev = 0.0, yprev = 0.0, vprev = 1.0, wprev = 0.0;
 #pragma unroll
@@ -954,6 +927,48 @@ __device__ __forceinline__ Chunk reg_chunk_elim(Lds<NT>& S, const double* __rest
     S.d0[2 * t + 1] = R1[3]; S.d1[2 * t + 1] = 0.0; S.d2[2 * t + 1] = 0.0;
   }
   return ch;
+}
+
+// The same with the rows read from global arrays lo, di, up, rhs.
+template <int NT, int K>
+__device__ __forceinline__ Chunk reg_chunk_elim(Lds<NT>& S, const double* __restrict__ lo,
+                                                const double* __restrict__ di,
+                                                const double* __restrict__ up,
+                                                const double* __restrict__ rhs, int n,
+                                                double (&y)[K], double (&v)[K], double (&w)[K]) {
+  return reg_chunk_elim_rows<NT, K>(
+      S, n, y, v, w,
+      [&](int f, int k, double (&Lo)[K], double (&Di)[K], double (&Up)[K], double (&Rh)[K]) {
+        // every row of the chunk is loaded before the elimination starts
+        // (the K loads of one lane share cache lines; issued together they
+        // are served by one fetch)
+        if (k == K && K % 2 == 0) {
+          // a full chunk: two rows per 16-byte load (8-byte alignment
+          // suffices for global memory on this target; measured: transposed
+          // solve of the gradient -9 %, SGN solve -10 %)
+          typedef double d2a8 __attribute__((ext_vector_type(2), aligned(8)));
+#pragma unroll
+          for (int i = 0; i < K; i += 2) {
+            const d2a8 a = *(const d2a8*)(lo + f + i);
+            const d2a8 b = *(const d2a8*)(di + f + i);
+            const d2a8 c = *(const d2a8*)(up + f + i);
+            const d2a8 d = *(const d2a8*)(rhs + f + i);
+            Lo[i] = a.x; Lo[i + 1] = a.y;
+            Di[i] = b.x; Di[i + 1] = b.y;
+            Up[i] = c.x; Up[i + 1] = c.y;
+            Rh[i] = d.x; Rh[i + 1] = d.y;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < K; ++i) {
+            const int r = f + (i < k ? i : k - 1);
+            Lo[i] = lo[r];
+            Di[i] = di[r];
+            Up[i] = up[r];
+            Rh[i] = rhs[r];
+          }
+        }
+      });
 }
 
 // Level-1 system of a whole system that is not cyclic (the first row's lower
@@ -1098,71 +1113,6 @@ __global__ __launch_bounds__(NT) void k_adj_r2(AdjSolveArgs P) {
   }
   __syncthreads();
   reg_chunk_write<NT, K>(S, ch, P.lam + o, S.s[0], S.s[1], y, v, w);
-}
-
-// ---------------------------------------------------------------------------
-// Exact tiled solve of a batch of tridiagonal systems held in global rows
-// (lo[i] x[i-1] + di[i] x[i] + up[i] x[i+1] = rhs[i]; cyclic when periodic,
-// end couplings already zero when not): each tile of at most NT * K rows is
-// eliminated in registers.  REDUCE: the tile writes its two reduced rows
-// (first and last unknown, coupled to the neighbouring tiles) for the
-// per-instance reduced solve.  Otherwise the tile takes its end unknowns
-// from that solve (or solves them itself when it is the whole system) and
-// writes its solution.
-// ---------------------------------------------------------------------------
-struct TriArgs {
-  const InstDesc* __restrict__ inst;
-  const TileDesc* __restrict__ tiles;
-  const double* __restrict__ dt;
-  const double* __restrict__ lo;
-  const double* __restrict__ di;
-  const double* __restrict__ up;
-  const double* __restrict__ rhs;
-  double* __restrict__ x;
-  double* __restrict__ rlo;  // reduced rows (2 per tile at red_off + 2 tidx)
-  double* __restrict__ rdi;
-  double* __restrict__ rup;
-  double* __restrict__ rrhs;
-  const double* __restrict__ rx;  // reduced solution
-};
-
-template <int NT, int K, bool REDUCE>
-__global__ __launch_bounds__(NT) void k_tri_tiles(TriArgs P) {
-  __shared__ Lds<NT> S;
-  const TileDesc td = P.tiles[blockIdx.x];
-  const InstDesc I = P.inst[td.inst];
-  if (!(P.dt[td.inst] > 0.0)) return;  // frozen: x is not used
-  const int64_t o = I.off + td.start;
-  double y[K], v[K], w[K];
-  const Chunk ch = reg_chunk_elim<NT, K>(S, P.lo + o, P.di + o, P.up + o, P.rhs + o, td.len, y,
-                                         v, w);
-  __syncthreads();
-  level1_interior_fast<NT>(S, 2 * ch.active);
-  if (threadIdx.x == 0) {
-    double R0[4], R1[4];
-    tile_rows<NT>(S, 2 * ch.active, R0, R1);
-    if (REDUCE) {
-      const int r = I.red_off + 2 * td.tidx;
-      P.rlo[r] = R0[0]; P.rdi[r] = R0[1]; P.rup[r] = R0[2]; P.rrhs[r] = R0[3];
-      P.rlo[r + 1] = R1[0]; P.rdi[r + 1] = R1[1]; P.rup[r + 1] = R1[2]; P.rrhs[r + 1] = R1[3];
-    } else if (I.ntiles == 1) {
-      const bool cyclic = I.bc == 0;
-      if (!cyclic) {
-        R0[0] = 0.0;
-        R1[2] = 0.0;
-      }
-      double z0, zl;
-      solve_ends(R0, R1, cyclic, z0, zl);
-      S.s[0] = z0;
-      S.s[1] = zl;
-    } else {
-      S.s[0] = P.rx[I.red_off + 2 * td.tidx];
-      S.s[1] = P.rx[I.red_off + 2 * td.tidx + 1];
-    }
-  }
-  if (REDUCE) return;
-  __syncthreads();
-  reg_chunk_write<NT, K>(S, ch, P.x + o, S.s[0], S.s[1], y, v, w);
 }
 
 }  // namespace hsgn

@@ -24,6 +24,7 @@
 #pragma once
 
 #include "hsgn_kernels.hpp"
+#include "hsgn_adjoint.hpp"
 
 namespace hsgn {
 
@@ -213,14 +214,14 @@ __global__ __launch_bounds__(NT) void k_speed_ex(const InstDesc* __restrict__ in
 
 // ---------------------------------------------------------------------------
 // Standard SGN equations, elliptic-hyperbolic form (Sec. 4.3-4.4), flat
-// bottom, Heun's method.  Per stage: k_sgn_rows assembles the tridiagonal
+// bottom, Heun's method.  Per stage: k_sgn_tri forms the tridiagonal
 // system of phi,
 //   h_i phi_i - (H_{i+1/2}(phi_{i+1} - phi_i) - H_{i-1/2}(phi_i - phi_{i-1})) / (3 dx^2)
 //     = h*_i = -(G_{i+1} - G_{i-1}) / (6 dx^3),
 //   H_{i+1/2} = (h_i^3 + h_{i+1}^3) / 2,
 //   G_j = g h_j^3 (h_{j+1} - 2 h_j + h_{j-1}) + (h_j^3 / 2)(u_{j+1} - u_{j-1})^2,
-// (zero-gradient phi at transmissive ends; cyclic when periodic); the
-// batched tridiagonal solve gives phi; k_sgn_update applies
+// (zero-gradient phi at transmissive ends; cyclic when periodic) and solves
+// it exactly on the two-pass tiling; k_sgn_update applies
 //   L_h = -Dhat_x(q),  L_q = -Dhat_x(q u + g h^2 / 2) + h phi
 // with Rusanov fluxes (speed max(|u| + sqrt(g h))) on the linear
 // reconstruction of (h, q).  m and W are carried unchanged.
@@ -236,10 +237,6 @@ struct SgnArgs {
   double* __restrict__ o_q;
   double* __restrict__ o_m;
   double* __restrict__ o_W;
-  double* __restrict__ lo;          // rows of the phi system (k_sgn_rows)
-  double* __restrict__ di;
-  double* __restrict__ up;
-  double* __restrict__ rhs;
   const double* __restrict__ phi;   // solution (k_sgn_update)
   const InstDesc* __restrict__ inst;
   const TileDesc* __restrict__ tiles;
@@ -268,57 +265,157 @@ __device__ __forceinline__ void sgn_stage(double (*X)[SL], const double* __restr
   }
 }
 
-template <int NT, int KX>
-__global__ __launch_bounds__(NT) void k_sgn_rows(SgnArgs A) {
-  constexpr int TL = NT * KX;
-  constexpr int SL = TL + 4;
-  __shared__ double X[2][SL];   // h, q; staged index s <-> tile cell s - 2
-  __shared__ double GH[2][SL];  // G_j and h_j^3 at staged cells 1 .. len + 2
-  const TileDesc td = A.tiles[blockIdx.x];
-  const InstDesc I = A.inst[td.inst];
-  if (!(A.dt[td.inst] > 0.0)) return;  // frozen: the solve skips the instance
+// Solve of the phi system on the two-pass tiling (tiles of at most NT * K
+// rows), with the rows formed in the solve: the tile stages h and q of its
+// cells and two ghost cells per side, each thread forms the rows of its
+// chunk (H, G and h^3 from the staged cells, the expressions above) and
+// eliminates them in registers, and the tile continues as an exact tiled
+// solve.  REDUCE: the tile writes its two reduced rows for the per-instance
+// reduced solve (k_rsolve).  Otherwise the tile takes its end unknowns from
+// that solve (or solves them itself when it is the whole instance) and
+// writes phi.  The rows never go through global memory.
+struct SgnTriArgs {
+  const InstDesc* __restrict__ inst;
+  const TileDesc* __restrict__ tiles;
+  const double* __restrict__ dt;
+  const double* __restrict__ h;  // stage operand
+  const double* __restrict__ q;
+  double* __restrict__ phi;
+  double* __restrict__ rlo;  // reduced rows (2 per tile at red_off + 2 tidx)
+  double* __restrict__ rdi;
+  double* __restrict__ rup;
+  double* __restrict__ rrhs;
+  const double* __restrict__ rx;  // reduced solution
+  int32_t* __restrict__ status;
+};
+
+template <int NT, int K>
+struct SgnTriLds {
+  static constexpr int SL = NT * K + 4;          // staged cells: rows and two ghosts per side
+  static constexpr int SP = SL + (SL >> 3) + 1;  // padded (one pad double after every 8)
+  union {
+    double X[2][SP];  // h, q; staged index s <-> tile cell s - 2
+    Lds<NT> S;        // the level-1 system, once every chunk has its rows
+  } u;
+};
+
+// Four workgroups per CU (at most 128 registers per lane; 37 KB of LDS
+// each): measured 15 % faster than the 136 registers, three workgroups per
+// CU, that the compiler picks by itself.
+template <int NT, int K, bool REDUCE>
+__global__ __launch_bounds__(NT, 4) void k_sgn_tri(SgnTriArgs P) {
+  using LT = SgnTriLds<NT, K>;
+  __shared__ LT L;
+  const TileDesc td = P.tiles[blockIdx.x];
+  const InstDesc I = P.inst[td.inst];
+  if (!(P.dt[td.inst] > 0.0)) return;  // frozen: phi is not used
   const int t = threadIdx.x, len = td.len;
-  sgn_stage<NT, SL>(X, A.in_h, A.in_q, I, td);
-  __syncthreads();
-  const double g = I.g;
-  bool bad = false;
 #pragma unroll
-  for (int r = 0; r < (SL + NT - 1) / NT; ++r) {
-    const int j = t + r * NT;
-    if (j >= 1 && j <= len + 2) {
-      const double hj = X[0][j];
-      const double h3 = hj * hj * hj;
-      const double du = X[1][j + 1] / X[0][j + 1] - X[1][j - 1] / X[0][j - 1];
-      GH[0][j] = g * h3 * (X[0][j + 1] - 2.0 * hj + X[0][j - 1]) + 0.5 * h3 * du * du;
-      GH[1][j] = h3;
-      bad |= !(hj > 0.0);
+  for (int r = 0; r < (LT::SL + NT - 1) / NT; ++r) {
+    const int si = t + r * NT;
+    if (si < len + 4) {
+      int c = td.start - 2 + si;
+      if (I.bc == 0) c = c < 0 ? c + I.n : (c >= I.n ? c - I.n : c);
+      else c = c < 0 ? 0 : (c > I.n - 1 ? I.n - 1 : c);
+      L.u.X[0][spad(si)] = P.h[I.off + c];
+      L.u.X[1][spad(si)] = P.q[I.off + c];
     }
   }
   __syncthreads();
-  const double c3 = 1.0 / (3.0 * I.dx * I.dx);
-  const double c6 = 1.0 / (6.0 * I.dx * I.dx * I.dx);
-  const int64_t base = I.off + td.start;
+  const Chunk ch = chunk_of(len, NT, t);
+  double Lo[K], Di[K], Up[K], Rh[K];
+  bool bad = false;
+  if (t < ch.active) {
+    const int k = ch.k, f = ch.first;
+    const double g = I.g;
+    const double c3 = 1.0 / (3.0 * I.dx * I.dx);
+    const double c6 = 1.0 / (6.0 * I.dx * I.dx * I.dx);
+    // staged cells f .. f + K + 3 (the stencils of chunk rows 0 .. K - 1;
+    // past the chunk's last stencil cell f + k + 3 the last one repeats)
+    double hv[K + 4], uv[K + 4], h3[K + 4], G[K + 4];
 #pragma unroll
-  for (int r = 0; r < KX; ++r) {
-    const int i = t + r * NT;
-    if (i < len) {
-      const int k = i + 2;
-      const double Hm = 0.5 * (GH[1][k - 1] + GH[1][k]);
-      const double Hp = 0.5 * (GH[1][k] + GH[1][k + 1]);
-      double l = -c3 * Hm, u = -c3 * Hp, d = X[0][k] + c3 * (Hm + Hp);
-      const double rh = -(GH[0][k + 1] - GH[0][k - 1]) * c6;
+    for (int i = 0; i < K + 4; ++i) {
+      const int si = f + (i < k + 4 ? i : k + 3);
+      hv[i] = L.u.X[0][spad(si)];
+      uv[i] = L.u.X[1][spad(si)] / hv[i];
+      h3[i] = hv[i] * hv[i] * hv[i];
+    }
+#pragma unroll
+    for (int i = 1; i < K + 3; ++i) {
+      const double du = uv[i + 1] - uv[i - 1];
+      G[i] = g * h3[i] * (hv[i + 1] - 2.0 * hv[i] + hv[i - 1]) + 0.5 * h3[i] * du * du;
+    }
+#pragma unroll
+    for (int ii = 0; ii < K; ++ii) {
+      const int a = ii + 2;  // chunk row ii <-> staged cell f + ii + 2
+      const double Hm = 0.5 * (h3[a - 1] + h3[a]);
+      const double Hp = 0.5 * (h3[a] + h3[a + 1]);
+      double l = -c3 * Hm, u = -c3 * Hp, d = hv[a] + c3 * (Hm + Hp);
+      const double rh = -(G[a + 1] - G[a - 1]) * c6;
       if (I.bc != 0) {  // zero-gradient phi at a transmissive end
-        const int c = td.start + i;
+        const int c = td.start + f + ii;
         if (c == 0) { d += l; l = 0.0; }
         if (c == I.n - 1) { d += u; u = 0.0; }
       }
-      A.lo[base + i] = l;
-      A.di[base + i] = d;
-      A.up[base + i] = u;
-      A.rhs[base + i] = rh;
+      Lo[ii] = l;
+      Di[ii] = d;
+      Up[ii] = u;
+      Rh[ii] = rh;
+      if (ii < k) bad |= !(hv[a] > 0.0);
+    }
+    if (k < K) {  // the elimination takes the chunk's last row from row K - 1
+      double l = Lo[0], d = Di[0], u = Up[0], rh = Rh[0];
+#pragma unroll
+      for (int ii = 1; ii < K - 1; ++ii)
+        if (ii == k - 1) { l = Lo[ii]; d = Di[ii]; u = Up[ii]; rh = Rh[ii]; }
+      Lo[K - 1] = l;
+      Di[K - 1] = d;
+      Up[K - 1] = u;
+      Rh[K - 1] = rh;
     }
   }
-  if (bad) atomicOr(&A.status[td.inst], kFlagNonPhys);
+  __syncthreads();  // the staged cells are dead: the union holds the level-1 system
+  Lds<NT>& S = L.u.S;
+  double y[K], v[K], w[K];
+  reg_chunk_elim_rows<NT, K>(
+      S, len, y, v, w,
+      [&](int, int, double (&lo)[K], double (&di)[K], double (&up)[K], double (&rh)[K]) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          lo[i] = Lo[i];
+          di[i] = Di[i];
+          up[i] = Up[i];
+          rh[i] = Rh[i];
+        }
+      });
+  __syncthreads();
+  level1_interior_fast<NT>(S, 2 * ch.active);
+  if (threadIdx.x == 0) {
+    double R0[4], R1[4];
+    tile_rows<NT>(S, 2 * ch.active, R0, R1);
+    if (REDUCE) {
+      const int r = I.red_off + 2 * td.tidx;
+      P.rlo[r] = R0[0]; P.rdi[r] = R0[1]; P.rup[r] = R0[2]; P.rrhs[r] = R0[3];
+      P.rlo[r + 1] = R1[0]; P.rdi[r + 1] = R1[1]; P.rup[r + 1] = R1[2]; P.rrhs[r + 1] = R1[3];
+    } else if (I.ntiles == 1) {
+      const bool cyclic = I.bc == 0;
+      if (!cyclic) {
+        R0[0] = 0.0;
+        R1[2] = 0.0;
+      }
+      double z0, zl;
+      solve_ends(R0, R1, cyclic, z0, zl);
+      S.s[0] = z0;
+      S.s[1] = zl;
+    } else {
+      S.s[0] = P.rx[I.red_off + 2 * td.tidx];
+      S.s[1] = P.rx[I.red_off + 2 * td.tidx + 1];
+    }
+  }
+  if (REDUCE) return;
+  __syncthreads();
+  reg_chunk_write<NT, K>(S, ch, P.phi + I.off + td.start, S.s[0], S.s[1], y, v, w);
+  if (bad) atomicOr(&P.status[td.inst], kFlagNonPhys);
 }
 
 template <int NT, int KX, int STAGE>
