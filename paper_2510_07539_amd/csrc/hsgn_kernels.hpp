@@ -434,8 +434,12 @@ __device__ __forceinline__ Chunk chunk_of(int n_t, int NT, int t) {
 // Otherwise: tile = whole instance (solve its ends here) or one of several
 // tiles (ends come from the reduced solve), then back-substitute and store.
 // ---------------------------------------------------------------------------
+// The finishing pass of stage 1 runs at two workgroups per CU (at most 256
+// registers; left to itself the compiler takes up to 302 and one): measured
+// 25 % faster with a bed.  The other variants measured slower so bounded
+// (stage 2's finishing pass spills), and keep the compiler's choice.
 template <int NT, int KMAX, bool BED, int STAGE, bool REDUCE>
-__global__ __launch_bounds__(NT) void k_stage(StageArgs A) {
+__global__ __launch_bounds__(NT, (STAGE == 1 && !REDUCE) ? 2 : 1) void k_stage(StageArgs A) {
   __shared__ Lds<NT> S;
   __shared__ double nb_beta[2][NT], nb_S[2][NT], nb_qd[2][NT], nb_phi[2][NT], nb_T[2][NT],
       nb_b[2][NT];
