@@ -318,8 +318,10 @@ int hsgn_step_timed(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_coun
  * call then returns that flag's error code (precedence and message as for
  * hsgn_status) before the reverse sweep, with d_loss written and the
  * gradients not.
- * The recompute of a segment runs on a second stream of the library while
- * the previous segment is swept in reverse (two tape buffers).  The adjoint
+ * The forward pass writes the tapes of the last two segments itself (one
+ * per tape buffer); every earlier segment is recomputed from its checkpoint
+ * on a second stream of the library while the following segment is swept
+ * in reverse.  The adjoint
  * workspace (22 + 16 K doubles per cell, plus 4 (nsteps/K + 1) doubles per
  * cell of checkpoints) is kept until hsgn_destroy.
  * Synchronises the stream twice: after the initial state (to plan) and

@@ -1489,23 +1489,26 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   rc = reset_and_plan(c);  // flags, speed bound and solver plan of the initial state
   if (rc) return rc;
   hipLaunchKernelGGL(k_fill_f64, dim3(nbi), dim3(256), 0, c->stream, (int64_t)c->n_inst, d_loss, 0.0);
-  // the last segment writes its tape (and the final state) directly, so the
-  // reverse sweep starts without recomputing it
-  const int s_last = (nseg - 1) * K;
+  // The last two segments (one per tape buffer) write their tapes, their
+  // checkpoints and the final state directly, so neither is recomputed: the
+  // reverse sweep of the last one starts at once, and the recompute stream
+  // first recomputes the third segment from the end.
+  const int n_fwd_tape = std::min(nseg, 2);
+  const int s_tape = (nseg - n_fwd_tape) * K;
   for (int s = 0; s < nsteps; ++s) {
-    if (grad && s % K == 0) {
+    if (grad && s % K == 0 && s <= s_tape) {  // later checkpoints are written by the steps
       double* dst[4] = {ckpt(s / K, 0), ckpt(s / K, 1), ckpt(s / K, 2), ckpt(s / K, 3)};
       rc = copy_state(c, dst, c->buf[c->cur]);
       if (rc) return rc;
     }
     const double* hnew;
-    if (grad && s >= s_last) {
-      const int k = s - s_last, ksl = nsteps - s_last;
+    if (grad && s >= s_tape) {
+      const int seg = s / K, k = s - seg * K, ks = std::min(K, nsteps - seg * K);
       double *un[4], *u1[4], *out[4];
       for (int f = 0; f < 4; ++f) {
-        un[f] = k == 0 ? ckpt(nseg - 1, f) : tape(nseg - 1, k, f);
-        u1[f] = tape(nseg - 1, k, 4 + f);
-        out[f] = (k + 1 < ksl) ? tape(nseg - 1, k + 1, f) : ckpt(nseg, f);
+        un[f] = k == 0 ? ckpt(seg, f) : tape(seg, k, f);
+        u1[f] = tape(seg, k, 4 + f);
+        out[f] = (k + 1 < ks) ? tape(seg, k + 1, f) : ckpt(seg + 1, f);
       }
       rc = enqueue_step_io(c, un, u1, out);
       hnew = out[0];
@@ -1588,15 +1591,16 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   for (int seg = nseg - 1; seg >= 0; --seg) {
     const int s0 = seg * K;
     const int ks = std::min(K, nsteps - s0);
-    // the previous segment is recomputed while this one is swept in reverse;
-    // its tape buffer was last read by the reverse sweep of segment seg + 1
-    if (seg >= 1) {
+    // the previous segment is recomputed (unless the forward pass wrote its
+    // tape) while this one is swept in reverse; its tape buffer was last
+    // read by the reverse sweep of segment seg + 1
+    if (seg >= 1 && seg - 1 < nseg - n_fwd_tape) {
       if (seg + 1 <= nseg - 1) HIPCHK(c, hipStreamWaitEvent(a.rstream, a.ev_rev[(seg + 1) % 2], 0));
       rc = recompute(seg - 1);
       if (rc) return rc;
       HIPCHK(c, hipEventRecord(a.ev_rec[(seg - 1) % 2], a.rstream));
     }
-    if (seg < nseg - 1) HIPCHK(c, hipStreamWaitEvent(c->stream, a.ev_rec[seg % 2], 0));
+    if (seg < nseg - n_fwd_tape) HIPCHK(c, hipStreamWaitEvent(c->stream, a.ev_rec[seg % 2], 0));
     double* cks[4] = {ckpt(seg, 0), ckpt(seg, 1), ckpt(seg, 2), ckpt(seg, 3)};
     auto un_of = [&](int k, int f) { return k == 0 ? cks[f] : tape(seg, k, f); };
     for (int k = ks - 1; k >= 0; --k) {

@@ -107,16 +107,18 @@ struct TileLds1 {  // R1
   } u;
 };
 template <int NT>
-struct TileLds3 {  // R3
-  double he[NT], qe[NT], me[NT], we[NT], bb[NT], hb[NT];
+struct TileLds3 {  // R3: 15 arrays (30 KB at NT = 256), so five workgroups fit a CU
+  union {
+    struct { double he[NT], qe[NT], me[NT], we[NT], bb[NT], hb[NT]; };  // U_E, bed, hbar
+    double pf[5][NT];  // face partials, one stencil cell at a time (after the reverse faces)
+  };
   double phi[NT], tt[NT];
   double fa[NT], dba[NT];
   double lam[NT];   // solution of the transposed system
   double db2a[NT];  // bed-slope source adjoint
   union {
-    struct { double fq[NT], fm[NT], fw[NT]; } face;     // fluxes
-    struct { double fl[3][NT], fr[3][NT]; } rface;      // face adjoints
-    double pf[5][NT];                                   // face partials, one stencil cell at a time
+    struct { double fq[NT], fm[NT], fw[NT]; } face;  // fluxes
+    struct { double fr[3][NT]; } rface;              // adjoints of each cell's right face
   } u;
 };
 
@@ -569,10 +571,7 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
   }
   if (grec_ok) {  // no barrier needed: the union last held fluxes
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      L.u.rface.fl[k][t] = FLv[k];
-      L.u.rface.fr[k][t] = FRv[k];
-    }
+    for (int k = 0; k < 3; ++k) L.u.rface.fr[k][t] = FRv[k];
     L.db2a[t] = DbA;
   }
   __syncthreads();
@@ -591,9 +590,8 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
       const int s = f - 1 - I.lo0;
       aq += L.u.rface.fr[0][s]; am += L.u.rface.fr[1][s]; aw += L.u.rface.fr[2][s];
     }
-    if (per || f <= I.n - 1) {  // cell right of the face: this is its left face
-      const int s = f - I.lo0;
-      aq += L.u.rface.fl[0][s]; am += L.u.rface.fl[1][s]; aw += L.u.rface.fl[2][s];
+    if (per || f <= I.n - 1) {  // cell right of the face (this thread's): its left face
+      aq += FLv[0]; am += FLv[1]; aw += FLv[2];
     }
     const int cs[4] = {slot(I, f - 2), slot(I, f - 1), slot(I, f), slot(I, f + 1)};
     double h[4], q[4], m[4], wv[4], b[4];
@@ -667,10 +665,12 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
   double ea[5] = {EA0[0], EA0[2], EA0[1], 0.0, 0.0};  // h, q, m, W, b
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    __syncthreads();  // the previous round (or the face adjoints) is read
+    // the previous round is read; before round 0, the reverse faces have
+    // read the staged tile, whose storage pf takes over
+    __syncthreads();
     if (rf_ok) {
 #pragma unroll
-      for (int fl = 0; fl < 5; ++fl) L.u.pf[fl][t] = pa[fl][k];
+      for (int fl = 0; fl < 5; ++fl) L.pf[fl][t] = pa[fl][k];
     }
     __syncthreads();
     if (core) {
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(NT) void k_adj_r3(AdjTileArgs P) {
         if (!face_ok(I, f) || vcl(I, f - 2 + k) != j) continue;
         const int s = f - I.lo0;
 #pragma unroll
-        for (int fl = 0; fl < 5; ++fl) ea[fl] += L.u.pf[fl][s];
+        for (int fl = 0; fl < 5; ++fl) ea[fl] += L.pf[fl][s];
       }
     }
   }
