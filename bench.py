@@ -30,15 +30,15 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # hash of the sources of its kernels and reported as null once they change.
 TRAFFIC = [
     {"kernel": "win2", "workload": "batched_bar", "solver": "auto_small",
-     "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp"], "hash": "1929140f522917c8",
-     "fetch_bytes": 2677900575, "write_bytes": 1412305931, "bytes_per_launch": 4090206506},
+     "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp"], "hash": "a983b3da7451e2ed",
+     "fetch_bytes": 2633455912, "write_bytes": 1391520768, "bytes_per_launch": 4024976680},
     {"kernel": "ex2", "workload": "batched_flat", "scheme": "explicit",
-     "sources": ["hsgn_kernels.hpp", "hsgn_explicit.hpp"], "hash": "7edb7460c755b98f",
-     "fetch_bytes": 2232878435, "write_bytes": 1118349045, "bytes_per_launch": 3351227480},
+     "sources": ["hsgn_kernels.hpp", "hsgn_explicit.hpp"], "hash": "0a9200e94776fd50",
+     "fetch_bytes": 2232887832, "write_bytes": 1118343168, "bytes_per_launch": 3351231000},
     {"kernel": "sgn_solve", "workload": "batched_flat", "scheme": "sgn",
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp",
-                 "hsgn_explicit.hpp"], "hash": "161c9434df60ff3e",
-     "fetch_bytes": 2207025579, "write_bytes": 276548192, "bytes_per_launch": 2483573771},
+                 "hsgn_explicit.hpp"], "hash": "2a32ffd0fe38f785",
+     "fetch_bytes": 1144332313, "write_bytes": 427278677, "bytes_per_launch": 1571610990},
 ]
 
 def src_hash(sources):
