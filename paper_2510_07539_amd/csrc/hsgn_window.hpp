@@ -7,15 +7,18 @@
 // moves to the right-hand side).  The system is diagonally dominant, so the
 // influence of that replacement on the core decays geometrically with the
 // distance L; the kernel computes that influence exactly at both core edges
-// (from the spike columns of the window solve) and flags the instance
-// (status bit 4) if the resulting bound exceeds 2^-56 of the local depth.
-// Instances that fit in one window are solved exactly (no truncation).
+// (the derivatives of the window solve with respect to the two edge
+// guesses) and flags the instance (status bit 4) if the resulting bound
+// exceeds 2^-56 of the local depth.  Instances that fit in one window are
+// solved exactly (no truncation).
 //
 // Each of the NT threads owns exactly K consecutive window rows (K is a
 // compile-time constant); rows past the window's real length are identity
 // rows, decoupled from the rest.  Inputs are staged through LDS with
-// coalesced loads.  Everything else (sweep, rows, solve) is the same
-// arithmetic as the two-pass kernel in hsgn_kernels.hpp.
+// coalesced loads.  The sweep and the rows are the same arithmetic as the
+// two-pass kernel in hsgn_kernels.hpp; the solve eliminates each thread's
+// chunk in registers and solves the resulting level-1 system (two rows per
+// thread) in LDS.
 #pragma once
 
 #include "hsgn_kernels.hpp"
