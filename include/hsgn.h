@@ -179,7 +179,13 @@ int hsgn_run(hsgn_ctx* ctx, int32_t nsteps, int32_t block);
  *    system is solved, and the tiles finish (no truncation anywhere).
  *  HSGN_SOLVER_AUTO_SMALL: AUTO with 2048-row windows (256 threads x 8 rows).
  * The plan is made from the state loaded by hsgn_set_state (speed bound
- * and maximum depth per instance); hsgn_set_solver re-plans at once. */
+ * and maximum depth per instance); hsgn_set_solver re-plans at once.
+ * With scheme = HSGN_SCHEME_SGN the modes plan the phi solve: AUTO and
+ * AUTO_SMALL take 4096-row windows (halo from the phi rows' decay at the
+ * deepest cell), truncated at their edges with phi = 0 beyond them and
+ * certified to 2^-56 of max |phi| (the rows are diagonally dominant by h,
+ * so max |phi| <= max |rhs| / min h bounds the replaced values; otherwise
+ * HSGN_FLAG_WINDOW); EXACT solves every instance on the two-pass tiling. */
 #define HSGN_SOLVER_AUTO 0
 #define HSGN_SOLVER_EXACT 1
 #define HSGN_SOLVER_AUTO_SMALL 2

@@ -418,6 +418,180 @@ __global__ __launch_bounds__(NT, 4) void k_sgn_tri(SgnTriArgs P) {
   if (bad) atomicOr(&P.status[td.inst], kFlagNonPhys);
 }
 
+// Windowed single-pass solve of the phi system (instances planned into
+// windows, as the depth system of the semi-implicit step): a window solves
+// rows [ws, ws + wl) of its instance and writes phi on its core
+// [cs, cs + cl).  Beyond a truncated window edge the unknown phi is replaced
+// by 0, so its coupling leaves the row.  The phi rows are diagonally
+// dominant by h_i (diagonal minus couplings), so max |phi| <= max |rhs| /
+// min h, and the replacement changes a core row by at most the row's
+// derivative with respect to the replaced value times that bound.  The
+// window computes those derivatives at both core edges (through the 2x2 end
+// solve) and flags the instance (kFlagWindow) unless their sum is below
+// 2^-56: the truncation then moves phi by less than 2^-56 of max |phi|.
+struct SgnWinArgs {
+  const InstDesc* __restrict__ inst;
+  const WinDesc* __restrict__ win;
+  const double* __restrict__ dt;
+  const double* __restrict__ h;  // stage operand
+  const double* __restrict__ q;
+  double* __restrict__ phi;
+  int32_t* __restrict__ status;
+};
+
+template <int NT, int K>
+__global__ __launch_bounds__(NT, 4) void k_sgn_win(SgnWinArgs P) {
+  using LT = SgnTriLds<NT, K>;
+  __shared__ LT L;
+  __shared__ double E[8];  // couplings moved out at the edges, end unknowns, derivatives
+  const WinDesc wd = P.win[blockIdx.x];
+  const InstDesc I = P.inst[wd.inst];
+  if (!(P.dt[wd.inst] > 0.0)) return;  // frozen: phi is not used
+  const int t = threadIdx.x, wl = wd.wl, n = I.n;
+  const bool truncL = (wd.flags & 1) != 0, truncR = (wd.flags & 2) != 0;
+  if (t == 0) {
+    E[0] = 0.0;
+    E[1] = 0.0;
+  }
+  // h and q of window rows -2 .. wl + 1 (staged index = row + 2)
+#pragma unroll
+  for (int r = 0; r < (LT::SL + NT - 1) / NT; ++r) {
+    const int si = t + r * NT;
+    if (si < wl + 4) {
+      const int c = wrap_any(wd.ws - 2 + si, n, I.bc);
+      L.u.X[0][spad(si)] = P.h[I.off + c];
+      L.u.X[1][spad(si)] = P.q[I.off + c];
+    }
+  }
+  __syncthreads();
+  const Chunk ch = chunk_of(wl, NT, t);
+  const int k = ch.k, f = ch.first;
+  double Lo[K], Di[K], Up[K], Rh[K];
+  bool bad = false;
+  if (t < ch.active) {
+    const double g = I.g;
+    const double c3 = 1.0 / (3.0 * I.dx * I.dx);
+    const double c6 = 1.0 / (6.0 * I.dx * I.dx * I.dx);
+    double hv[K + 4], uv[K + 4], h3[K + 4], G[K + 4];
+#pragma unroll
+    for (int i = 0; i < K + 4; ++i) {
+      const int si = f + (i < k + 4 ? i : k + 3);
+      hv[i] = L.u.X[0][spad(si)];
+      uv[i] = L.u.X[1][spad(si)] / hv[i];
+      h3[i] = hv[i] * hv[i] * hv[i];
+    }
+#pragma unroll
+    for (int i = 1; i < K + 3; ++i) {
+      const double du = uv[i + 1] - uv[i - 1];
+      G[i] = g * h3[i] * (hv[i + 1] - 2.0 * hv[i] + hv[i - 1]) + 0.5 * h3[i] * du * du;
+    }
+#pragma unroll
+    for (int ii = 0; ii < K; ++ii) {
+      const int a = ii + 2;  // chunk row ii <-> window row f + ii <-> staged cell f + ii + 2
+      const double Hm = 0.5 * (h3[a - 1] + h3[a]);
+      const double Hp = 0.5 * (h3[a] + h3[a + 1]);
+      double l = -c3 * Hm, u = -c3 * Hp, d = hv[a] + c3 * (Hm + Hp);
+      const double rh = -(G[a + 1] - G[a - 1]) * c6;
+      const int p = f + ii;
+      if (I.bc != 0) {  // zero-gradient phi at a transmissive end of the instance
+        const int c = wd.ws + p;
+        if (c == 0) { d += l; l = 0.0; }
+        if (c == n - 1) { d += u; u = 0.0; }
+      }
+      if (ii < k) {
+        if (truncL && p == 0) {  // phi beyond the left edge taken as 0
+          E[0] = l;
+          l = 0.0;
+        }
+        if (truncR && p == wl - 1) {
+          E[1] = u;
+          u = 0.0;
+        }
+        bad |= !(hv[a] > 0.0);
+      }
+      Lo[ii] = l;
+      Di[ii] = d;
+      Up[ii] = u;
+      Rh[ii] = rh;
+    }
+    if (k < K) {  // the elimination takes the chunk's last row from row K - 1
+      double l = Lo[0], d = Di[0], u = Up[0], rh = Rh[0];
+#pragma unroll
+      for (int ii = 1; ii < K - 1; ++ii)
+        if (ii == k - 1) { l = Lo[ii]; d = Di[ii]; u = Up[ii]; rh = Rh[ii]; }
+      Lo[K - 1] = l;
+      Di[K - 1] = d;
+      Up[K - 1] = u;
+      Rh[K - 1] = rh;
+    }
+  }
+  __syncthreads();  // the staged cells are dead: the union holds the level-1 system
+  Lds<NT>& S = L.u.S;
+  double y[K], v[K], w[K];
+  reg_chunk_elim_rows<NT, K>(
+      S, wl, y, v, w,
+      [&](int, int, double (&lo)[K], double (&di)[K], double (&up)[K], double (&rh)[K]) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          lo[i] = Lo[i];
+          di[i] = Di[i];
+          up[i] = Up[i];
+          rh[i] = Rh[i];
+        }
+      });
+  __syncthreads();
+  const int n1 = 2 * ch.active;
+  level1_interior_fast<NT>(S, n1);
+  if (t == 0) {
+    // the window's end unknowns (no coupling beyond the ends is left) and
+    // their derivatives with respect to the two replaced values: the left
+    // one enters the first row's right-hand side as -E[0], the right one
+    // the last row's as -E[1]
+    double R0[4], R1[4];
+    tile_rows<NT>(S, n1, R0, R1);
+    const double m00 = R0[1], m01 = R0[2], m10 = R1[0], m11 = R1[1];
+    const double idet = 1.0 / (m00 * m11 - m01 * m10);
+    E[2] = (m11 * R0[3] - m01 * R1[3]) * idet;  // z0
+    E[3] = (m00 * R1[3] - m10 * R0[3]) * idet;  // zl
+    E[4] = -E[0] * m11 * idet;                  // d z0 / d (left value)
+    E[5] = E[0] * m10 * idet;                   // d zl / d (left value)
+    E[6] = E[1] * m01 * idet;                   // d z0 / d (right value)
+    E[7] = -E[1] * m00 * idet;                  // d zl / d (right value)
+  }
+  __syncthreads();
+  if (t < ch.active) {
+    const double z0 = E[2], zl = E[3];
+    const int j0 = 2 * t, j1 = 2 * t + 1;
+    double zf, zb, Vf, Wf, Vb, Wb;  // chunk ends and their derivatives by (z0, zl)
+    if (j0 == 0) { zf = z0; Vf = 1.0; Wf = 0.0; }
+    else { zf = S.d0[j0] + S.d1[j0] * z0 + S.d2[j0] * zl; Vf = S.d1[j0]; Wf = S.d2[j0]; }
+    if (j1 == n1 - 1) { zb = zl; Vb = 0.0; Wb = 1.0; }
+    else { zb = S.d0[j1] + S.d1[j1] * z0 + S.d2[j1] * zl; Vb = S.d1[j1]; Wb = S.d2[j1]; }
+    const int c0 = wd.cs - wd.ws, c1 = c0 + wd.cl;  // the core's window rows
+    const bool cert = truncL || truncR;
+    double sens = 0.0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      if (i < k) {
+        const int p = f + i;
+        double x, s0, sl;  // row value and its derivatives by (z0, zl)
+        if (i == 0) { x = zf; s0 = Vf; sl = Wf; }
+        else if (i == k - 1) { x = zb; s0 = Vb; sl = Wb; }
+        else {
+          x = y[i] + v[i] * zf + w[i] * zb;
+          s0 = v[i] * Vf + w[i] * Vb;
+          sl = v[i] * Wf + w[i] * Wb;
+        }
+        if (p >= c0 && p < c1) P.phi[I.off + wd.cs + (p - c0)] = x;
+        if (cert && (p == c0 || p == c1 - 1))
+          sens = fmax(sens, fabs(s0 * E[4] + sl * E[5]) + fabs(s0 * E[6] + sl * E[7]));
+      }
+    }
+    if (!(sens <= 1.3877787807814457e-17)) atomicOr(&P.status[wd.inst], kFlagWindow);  // 2^-56
+  }
+  if (bad) atomicOr(&P.status[wd.inst], kFlagNonPhys);
+}
+
 template <int NT, int KX, int STAGE>
 __global__ __launch_bounds__(NT) void k_sgn_update(SgnArgs A) {
   constexpr int TL = NT * KX;

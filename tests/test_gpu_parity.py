@@ -730,16 +730,34 @@ def _sgn_mix():
     return WL.concat("sgn mix", [a, b, c])
 
 
-def test_sgn_parity_mix():
-    compare(_sgn_mix(), 40, label="SGN Heun", scheme=SGNS)
+SGN_SOLVERS = ["auto", "exact"]  # windowed phi solve where planned / two-pass everywhere
 
 
-def test_sgn_edge_sizes():
+@pytest.mark.parametrize("solver", SGN_SOLVERS)
+def test_sgn_parity_mix(solver):
+    """The phi solve in both forms: "auto" plans windows (single pass, the
+    instances longer than a window truncated at certified edges), "exact"
+    the two-pass tiled solve for every instance."""
+    wl = _sgn_mix()
+    s = _solver().from_workload(wl, scheme=SGNS, solver=solver)
+    info = s.plan_info()
+    s.close()
+    note("  SGN plan [%s]: %d windows, %d two-pass tiles, halo max %d" % (
+        solver, info["windows"], info["exact_tiles"], int(info["halo"].max())))
+    if solver == "auto":
+        assert info["windows"] > wl.n_inst  # some instance spans several windows
+    else:
+        assert info["windows"] == 0
+    compare(wl, 40, label="SGN Heun", scheme=SGNS, solver=solver)
+
+
+@pytest.mark.parametrize("solver", SGN_SOLVERS)
+def test_sgn_edge_sizes(solver):
     parts = []
     for n in (4, 5, 7, 1023, 1024, 1025, 4096, 4097):
         for bc in (0, 1):
             parts.append(WL.solitary(N=n, L=n * 0.25, t_end=0.0, bc=bc))
-    compare(WL.concat("sgn edge sizes", parts), 20, label="SGN sizes", scheme=SGNS)
+    compare(WL.concat("sgn edge sizes", parts), 20, label="SGN sizes", scheme=SGNS, solver=solver)
 
 
 def test_sgn_graph_replay_equals_eager_and_t_end():
@@ -774,11 +792,14 @@ def test_sgn_rejects_bed_adjoint_and_autotune():
     s.close()
 
 
-def test_sgn_batched_flat_full_size_sampled():
+@pytest.mark.parametrize("solver", SGN_SOLVERS)
+def test_sgn_batched_flat_full_size_sampled(solver):
     wl = WL.batched_flat()
     insts = list(range(0, wl.n_inst, wl.n_inst // 16))
-    compare(wl, 20, use_run=True, block=10, insts=insts, label="SGN batched flat full size",
-            scheme=SGNS)
+    sizes = wl.sizes()
+    insts.append(int(np.argmax(sizes)))  # the most windows
+    compare(wl, 20, use_run=True, block=10, insts=sorted(set(insts)),
+            label="SGN batched flat full size", scheme=SGNS, solver=solver)
 
 
 def test_dam_break_full_run():
