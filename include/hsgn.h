@@ -236,6 +236,16 @@ int hsgn_autotune_classes(hsgn_ctx* ctx, int32_t nsteps, int32_t max_classes, in
                           int32_t* h_class_of, int32_t* h_keys, double* h_ms, int32_t* h_kept,
                           double* h_whole);
 
+/* Safety factor of the halo estimates (default 2): the windowed solves size
+ * their halos from the decay of the depth rows (the phi rows with the SGN
+ * scheme) estimated at `margin` times the coupling of the loaded state's
+ * deepest cell (the semi-implicit estimate also at its speed bound).  A
+ * smaller factor gives shorter halos, fewer window rows, and more instances
+ * flagged: every window still certifies its truncation (HSGN_FLAG_WINDOW,
+ * HSGN_EWINDOW).  0 < margin <= 64, else HSGN_EINVAL.  Re-plans at once;
+ * the class autotuner's contexts take the same factor. */
+int hsgn_set_halo_margin(hsgn_ctx* ctx, double margin);
+
 /* Launch of the window stages:
  *  HSGN_LAUNCH_GRID (the default): one workgroup per window, consecutive
  *    windows of an instance dealt to one XCD; the hardware dispatcher

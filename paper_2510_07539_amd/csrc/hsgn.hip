@@ -38,7 +38,7 @@ constexpr int kTileMax = kNT * kKMAX;
 constexpr int kNTR = 256;     // threads of the reduced-system solve
 constexpr int kWK = 8;        // rows per thread of the windowed kernel
 static_assert(kWK == hsgn::kPersistRows, "the persistent kernels are built for kWK rows");
-constexpr double kWinMargin = 2.0;  // safety factor on the decay estimate
+constexpr double kWinMargin = 2.0;  // default safety factor on the decay estimate
 constexpr int kAdjNT = 256;    // threads (cell positions) per reverse-stage tile
 
 using hsgn::InstDesc;
@@ -124,6 +124,7 @@ struct hsgn_ctx {
   // window-stage launch: one workgroup per window (HSGN_LAUNCH_GRID) or the
   // persistent kernel walking per-XCD work queues (HSGN_LAUNCH_PERSISTENT)
   int32_t launch = HSGN_LAUNCH_GRID;
+  double halo_margin = kWinMargin;  // safety factor of the halo estimates
   // 2 x 9 queue counters of the persistent kernel: the first set for the
   // library's stream, the second for the adjoint's recompute stream (zero
   // between launches: every launch resets its own)
@@ -500,12 +501,13 @@ int enqueue_step_io(hsgn_ctx* c, double* const* un, double* const* u1, double* c
 // (g h + (2 lambda / 3) / beta_1) at the deepest cell, times a margin.  The
 // halo makes rho^L <= 2^-60.  The kernel verifies the truncation on every
 // tile and flags the instance if it is not negligible.
-int halo_width(const hsgn_params& p, double smax, double hmax, double tau_factor) {
+int halo_width(const hsgn_params& p, double smax, double hmax, double tau_factor,
+               double margin) {
   const double dt = p.dt_fixed > 0 ? p.dt_fixed : p.cfl * p.dx / smax;
   const double tau = tau_factor * dt;
   const double b1 = 1.0 + p.lambda * tau * tau / (hmax * hmax);
   const double beta = p.g * hmax + (2.0 * p.lambda / 3.0) / b1;
-  const double R = kWinMargin * (tau / p.dx) * (tau / p.dx) * beta;
+  const double R = margin * (tau / p.dx) * (tau / p.dx) * beta;
   if (!(R > 0.0) || !std::isfinite(R)) return 1 << 30;
   const double q = 1.0 + 0.5 / R;
   const double rho = q - std::sqrt(q * q - 1.0);
@@ -519,11 +521,12 @@ int halo_width(const hsgn_params& p, double smax, double hmax, double tau_factor
 // Halo of the windowed phi solve of the SGN scheme: a phi row has the
 // diagonal h + c3 (H- + H+) and the couplings -c3 H-+ (c3 H = h^3 / (3 dx^2)
 // at a uniform depth), so at the deepest cell the inverse decays per cell by
-// rho = q - sqrt(q^2 - 1), q = 1 + h / (2 c3 H); the estimate doubles c3 H
-// there (the depth may grow by a quarter before it fails).  The halo makes
-// rho^L <= 2^-60; the kernel certifies every window.
-int sgn_halo_width(const hsgn_params& p, double hmax) {
-  const double c3H = 2.0 * hmax * hmax * hmax / (3.0 * p.dx * p.dx);
+// rho = q - sqrt(q^2 - 1), q = 1 + h / (2 c3 H); the estimate multiplies c3 H
+// there by the margin (by default 2: the depth may grow by a quarter before
+// it fails).  The halo makes rho^L <= 2^-60; the kernel certifies every
+// window.
+int sgn_halo_width(const hsgn_params& p, double hmax, double margin) {
+  const double c3H = margin * hmax * hmax * hmax / (3.0 * p.dx * p.dx);
   if (!(c3H > 0.0) || !std::isfinite(c3H)) return 1 << 30;
   const double q = 1.0 + hmax / (2.0 * c3H);
   const double rho = q - std::sqrt(q * q - 1.0);
@@ -581,9 +584,9 @@ int make_plan(hsgn_ctx* c) {
     // the halo estimate of the loaded state (reported for every instance)
     const bool have_state = !c->h_smax.empty() && c->h_smax[j] > 0 && c->h_hmax[j] > 0;
     const int L = !have_state ? 0
-                  : sgn ? sgn_halo_width(p, c->h_hmax[j])
+                  : sgn ? sgn_halo_width(p, c->h_hmax[j], c->halo_margin)
                         : halo_width(p, c->h_smax[j], c->h_hmax[j],
-                                     c->order == 1 ? 1.0 : hsgn::kGamma);
+                                     c->order == 1 ? 1.0 : hsgn::kGamma, c->halo_margin);
     c->h_halo[j] = L;
     if (mj != HSGN_SOLVER_EXACT && have_state) {
       auto add = [&](int ws, int wl, int cs, int cl, int flags) {
@@ -1278,6 +1281,18 @@ int hsgn_set_instance_solvers(hsgn_ctx* c, const int32_t* h_modes) {
   return leave(c);
 }
 
+int hsgn_set_halo_margin(hsgn_ctx* c, double margin) {
+  if (!c) return HSGN_EINVAL;
+  if (!(margin > 0.0 && margin <= 64.0))
+    return fail(c, HSGN_EINVAL, "hsgn_set_halo_margin: margin %g outside (0, 64]", margin);
+  c->halo_margin = margin;
+  int rc = enter(c);
+  if (rc) return rc;
+  rc = make_plan(c);
+  if (rc) return rc;
+  return leave(c);
+}
+
 int hsgn_set_launch(hsgn_ctx* c, int32_t launch) {
   if (!c) return HSGN_EINVAL;
   if (launch != HSGN_LAUNCH_GRID && launch != HSGN_LAUNCH_PERSISTENT)
@@ -1754,6 +1769,7 @@ int tune_class(hsgn_ctx* c, const std::vector<int>& idx, int32_t nsteps, double 
     if (rc) rc = fail(c, rc, "hsgn_autotune_classes: sub-context init failed");
   }
   if (!rc) {
+    sub->halo_margin = c->halo_margin;
     rc = hsgn_set_state(sub, tmp, tmp + nc, tmp + 2 * (size_t)nc, tmp + 3 * (size_t)nc,
                         tmp + 5 * (size_t)nc);
     if (!rc) rc = hsgn_autotune(sub, nsteps, ms, kept);

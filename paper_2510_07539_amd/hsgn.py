@@ -83,6 +83,8 @@ def lib():
                                             C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                             C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                             C.POINTER(C.c_double)]
+        L.hsgn_set_halo_margin.restype = C.c_int
+        L.hsgn_set_halo_margin.argtypes = [vp, C.c_double]
         L.hsgn_set_launch.restype = C.c_int
         L.hsgn_set_launch.argtypes = [vp, C.c_int32]
         L.hsgn_autotune_launch.restype = C.c_int
@@ -150,6 +152,11 @@ class Solver:
         self._check(lib().hsgn_autotune(self._h, int(nsteps), ms, C.byref(mode)), "hsgn_autotune")
         names = {v: k for k, v in SOLVERS.items()}
         return names[mode.value], {names[m]: ms[m] for m in range(3)}
+
+    def set_halo_margin(self, margin):
+        """Safety factor of the windowed solves' halo estimates (default 2);
+        re-plans at once."""
+        self._check(lib().hsgn_set_halo_margin(self._h, float(margin)), "hsgn_set_halo_margin")
 
     def set_launch(self, launch):
         """Window-stage launch: "grid" (one workgroup per window) or

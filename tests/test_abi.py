@@ -44,6 +44,8 @@ def test_null_arguments_are_rejected_without_a_device():
     assert L.hsgn_adjoint(None, 1, 1, 1, None, None, None, None, None, None) == -1
     assert L.hsgn_set_solver(None, 0) == -1
     assert L.hsgn_set_launch(None, 1) == -1
+    L.hsgn_set_halo_margin.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    assert L.hsgn_set_halo_margin(None, 1.0) == -1
     assert L.hsgn_autotune_launch(None, 1, None, None) == -1
     L.hsgn_destroy(None)
 

@@ -760,6 +760,52 @@ def test_sgn_edge_sizes(solver):
     compare(WL.concat("sgn edge sizes", parts), 20, label="SGN sizes", scheme=SGNS, solver=solver)
 
 
+@pytest.mark.parametrize("scheme", [0, SGNS])
+def test_halo_margin_short_halos_are_flagged(scheme):
+    """hsgn_set_halo_margin: with a far too small safety factor the halos
+    shrink to a few rows, and a window whose truncation then reaches its
+    core must flag its instance (HSGN_EWINDOW, status bit 4) instead of
+    returning a truncated result; instances solved in one window are not
+    flagged; back at the default factor the same state steps without a
+    flag and matches the oracle."""
+    from paper_2510_07539_amd.hsgn import HSGN_EWINDOW
+    Solver = _solver()
+    if scheme == SGNS:
+        wl = WL.batched_flat(n_inst=6, seed=19, n_lo=513, n_hi=9000)
+    else:
+        wl = WL.batched_bar(n_inst=6, seed=19, n_lo=513, n_hi=9000)
+    s = Solver.from_workload(wl, scheme=scheme)
+    full = s.plan_info()
+    s.set_halo_margin(1e-4)
+    info = s.plan_info()
+    note("  halos at the default factor %s, at 1e-4 %s" % (list(full["halo"]), list(info["halo"])))
+    assert (info["halo"] <= full["halo"]).all() and info["halo"].max() < full["halo"].max()
+    single = wl.sizes() <= 4096  # one window of 4096 rows: exact, never flagged
+    assert not single.all() and (info["mode"] == 0).all()
+    s.step(1)
+    rc, flags = s.status()
+    assert rc == HSGN_EWINDOW, rc
+    # an instance of two windows keeps a wide overlap whatever the halo (each
+    # window covers 4096 of its rows), so it may pass; the longest, of three
+    # windows with 8-row halos, must not
+    longest = int(np.argmax(wl.sizes()))
+    assert flags[longest] & 4, flags
+    for j in range(wl.n_inst):
+        if single[j]:
+            assert not flags[j] & 4, (j, flags)
+    s.close()
+    s = Solver.from_workload(wl, scheme=scheme)
+    s.set_halo_margin(2.0)
+    s.step(5)
+    (h, q, m, W), _ = s.get_state()
+    rc, _ = s.status()
+    assert rc == 0
+    U = [x.cpu().numpy() for x in (h, q, m, W)]
+    s.close()
+    for j in range(wl.n_inst):
+        check_instance(j, U, wl, 5, scheme=scheme)
+
+
 def test_sgn_graph_replay_equals_eager_and_t_end():
     Solver = _solver()
     wl = _sgn_mix()
