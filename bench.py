@@ -304,6 +304,8 @@ def main():
                     help="tune: the library times every mode on the workload and keeps the fastest")
     ap.add_argument("--launch", default="tune", choices=["tune", "grid", "persistent"],
                     help="window-stage launch; tune: the library times both and keeps the faster")
+    ap.add_argument("--halo-margin", type=float, default=2.0,
+                    help="safety factor of the windowed solves' halo estimates")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--table-out", default=None,
                     help="write the autotuner's table (JSON) to this file")
@@ -353,6 +355,8 @@ def main():
     else:
         s = Solver.from_workload(wl, solver=None if args.solver == "tune" else args.solver,
                                  order=args.order)
+    if args.halo_margin != 2.0:
+        s.set_halo_margin(args.halo_margin)
     tuned = None
     if args.table_in and not explicit:
         # a stored autotuner table: each instance takes its class's mode
@@ -487,6 +491,7 @@ def main():
                    "solver": tuned["kept"] if tuned else args.solver, "autotune": tuned,
                    "window_launches": plan["window_launches"],
                    "launch": launch, "launch_ms_per_step": launch_ms,
+                   "halo_margin": args.halo_margin,
                    "windows": plan["windows"], "window_rows": plan["window_rows"],
                    "two_pass_tiles": plan["exact_tiles"]},
         "roofline": roof,
