@@ -197,8 +197,9 @@ int hsgn_set_solver(hsgn_ctx* ctx, int32_t mode);
  * as it was.  h_ms (host, 3 doubles or NULL): milliseconds per step of each
  * mode, indexed by the mode's value; h_mode (host or NULL): the mode kept.
  * The modes agree with each other to rounding.  Allocates a copy of the
- * state for its duration; synchronises the stream.  Only the semi-implicit
- * step has solver modes (else HSGN_EINVAL). */
+ * state for its duration; synchronises the stream.  Semi-implicit scheme
+ * only (else HSGN_EINVAL; the SGN scheme's two forms of the phi solve are
+ * chosen with hsgn_set_solver). */
 int hsgn_autotune(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_mode);
 
 /* Per-instance solver modes: h_modes (host, n_inst values of

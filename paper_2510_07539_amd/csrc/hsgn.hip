@@ -1242,7 +1242,7 @@ int hsgn_autotune(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_mode) {
   if (!c) return HSGN_EINVAL;
   if (nsteps < 1) return fail(c, HSGN_EINVAL, "hsgn_autotune: nsteps < 1");
   if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
-    return fail(c, HSGN_EINVAL, "hsgn_autotune: only the semi-implicit step has solver modes");
+    return fail(c, HSGN_EINVAL, "hsgn_autotune: the tuner times the semi-implicit step only");
   int rc = enter(c);
   if (rc) return rc;
   const int modes[3] = {HSGN_SOLVER_AUTO, HSGN_SOLVER_EXACT, HSGN_SOLVER_AUTO_SMALL};
@@ -1266,8 +1266,8 @@ int hsgn_set_instance_solvers(hsgn_ctx* c, const int32_t* h_modes) {
   if (!c) return HSGN_EINVAL;
   if (!h_modes) return fail(c, HSGN_EINVAL, "hsgn_set_instance_solvers: h_modes is NULL");
   if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
-    return fail(c, HSGN_EINVAL, "hsgn_set_instance_solvers: only the semi-implicit step has "
-                "solver modes");
+    return fail(c, HSGN_EINVAL, "hsgn_set_instance_solvers: per-instance modes are for the semi-implicit "
+                "step only");
   for (int j = 0; j < c->n_inst; ++j)
     if (h_modes[j] != HSGN_SOLVER_AUTO && h_modes[j] != HSGN_SOLVER_EXACT &&
         h_modes[j] != HSGN_SOLVER_AUTO_SMALL)
@@ -1312,7 +1312,7 @@ int hsgn_autotune_launch(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_l
   if (!c) return HSGN_EINVAL;
   if (nsteps < 1) return fail(c, HSGN_EINVAL, "hsgn_autotune_launch: nsteps < 1");
   if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
-    return fail(c, HSGN_EINVAL, "hsgn_autotune_launch: only the semi-implicit step has windows");
+    return fail(c, HSGN_EINVAL, "hsgn_autotune_launch: the window launch of the semi-implicit step only");
   if (!c->d_queue)
     return fail(c, HSGN_EINVAL, "hsgn_autotune_launch: this context has no work queues");
   int rc = enter(c);
@@ -1793,8 +1793,7 @@ extern "C" int hsgn_autotune_classes(hsgn_ctx* c, int32_t nsteps, int32_t max_cl
   if (nsteps < 1 || max_classes < 1 || !h_nclass)
     return fail(c, HSGN_EINVAL, "hsgn_autotune_classes: bad arguments");
   if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
-    return fail(c, HSGN_EINVAL, "hsgn_autotune_classes: only the semi-implicit step has solver "
-                "modes");
+    return fail(c, HSGN_EINVAL, "hsgn_autotune_classes: the tuner times the semi-implicit step only");
   int rc = enter(c);
   if (rc) return rc;
   // classes in order of first appearance
