@@ -26,20 +26,20 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # and WRITE_SIZE in separate runs, `bench.py --probe [--solver auto_small |
 # --scheme explicit | --scheme sgn]`), scaled by the same counters on a plain
 # 512 MiB copy (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0), in bytes per launch
-# (the SGN solve: per stage, its three kernels).  Each entry is keyed by the
-# hash of the code of its kernels' sources (comments and blank lines left
-# out) and reported as null once that code changes.
+# (the SGN solve: per stage, every kernel of the phi solve).  Each entry is
+# keyed by the hash of the code of its kernels' sources (comments and blank
+# lines left out) and reported as null once that code changes.
 TRAFFIC = [
     {"kernel": "win2", "workload": "batched_bar", "solver": "auto_small",
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp"], "hash": "b9695bf0b02b34f1",
      "fetch_bytes": 2633455912, "write_bytes": 1391520768, "bytes_per_launch": 4024976680},
     {"kernel": "ex2", "workload": "batched_flat", "scheme": "explicit",
-     "sources": ["hsgn_kernels.hpp", "hsgn_explicit.hpp"], "hash": "fc26a8267dd9e7fd",
+     "sources": ["hsgn_kernels.hpp", "hsgn_explicit.hpp"], "hash": "2e6dc71f10ea1fd9",
      "fetch_bytes": 2232887832, "write_bytes": 1118343168, "bytes_per_launch": 3351231000},
     {"kernel": "sgn_solve", "workload": "batched_flat", "scheme": "sgn",
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp",
-                 "hsgn_explicit.hpp"], "hash": "7d863e9d185367ce",
-     "fetch_bytes": 1144332313, "write_bytes": 427278677, "bytes_per_launch": 1571610990},
+                 "hsgn_explicit.hpp", "hsgn_sgn.hpp"], "hash": "d8e7d54109550310",
+     "fetch_bytes": 676269416, "write_bytes": 273330176, "bytes_per_launch": 949599592},
 ]
 
 def src_hash(sources):

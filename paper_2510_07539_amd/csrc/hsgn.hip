@@ -29,6 +29,7 @@
 #include "hsgn_persist.hpp"
 #include "hsgn_adjoint.hpp"
 #include "hsgn_explicit.hpp"
+#include "hsgn_sgn.hpp"
 
 namespace {
 
