@@ -432,11 +432,11 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
                                         const int t) {
   // Register budget: 256 per lane (two waves per SIMD).  Stage 1 fits it
   // when it also (i) addresses the staged loads with 32-bit offsets from
-  // per-instance base pointers, (ii) forms the bed's rest-moment jump in
-  // the m round from the depths it keeps, and (iii) reads neighbour beds
-  // from the staged bed instead of carrying them in the records.  For
-  // stage 2 these choices measured slower (its spills move, not vanish),
-  // so it keeps the plain forms.  Both give the same values.
+  // per-instance base pointers and (ii) reads neighbour beds from the
+  // staged bed instead of carrying them in the records (kLean).  For stage
+  // 2 these two measured slower, so it keeps the plain forms and instead
+  // parks m-dagger and W-dagger in LDS through the solve (kStash below).
+  // Both forms give the same values.
   constexpr bool kLean = STAGE == 1;
   const StageArgs& A = W.s;
   const WinDesc wd = W.win[bid];
@@ -619,36 +619,18 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
   put_round(0);
   if (STAGE == 2) load_round(1);
   __syncthreads();
-  // round h (+ bed): face depths, the bed's rest-moment jump (plain form),
-  // depths of rows p0 - 1 .. p0 + K
-  double hL[K + 1], hR[K + 1], dmh[K + 1], hf[K + 2];
+  // round h: face depths, depths of rows p0 - 1 .. p0 + K
+  double hL[K + 1], hR[K + 1], hf[K + 2];
   unsigned badf = 0;  // bit f: a face depth of face f is not positive
   if (act) {
     save_side(0);
-    double xh[K + 4], xb[K + 4];
+    double xh[K + 4];
     read_x(xh, ebuf(0));
-    if (BED && useb && !kLean) {
-      read_x(xb, L.u.st.b);
-    } else {
-#pragma unroll
-      for (int i = 0; i < K + 4; ++i) xb[i] = 0.0;
-    }
 #pragma unroll
     for (int f = 0; f <= K; ++f) {
       hL[f] = xh[f + 1] + P.sl * (xh[f + 2] - xh[f]);
       hR[f] = xh[f + 2] - P.sl * (xh[f + 3] - xh[f + 1]);
       if (!(hL[f] > 0.0) || !(hR[f] > 0.0)) badf |= 1u << f;
-      dmh[f] = 0.0;
-      if (BED && !kLean) {
-        const double zf = 0.5 * ((xh[f + 1] + xb[f + 1]) + (xh[f + 2] + xb[f + 2]));
-        const double rm = (zf - xb[f]) * (zf - xb[f]);
-        const double r0 = (zf - xb[f + 1]) * (zf - xb[f + 1]);
-        const double r1 = (zf - xb[f + 2]) * (zf - xb[f + 2]);
-        const double r2 = (zf - xb[f + 3]) * (zf - xb[f + 3]);
-        const double mhL = r0 + P.sl * (r1 - rm);
-        const double mhR = r1 - P.sl * (r2 - r0);
-        dmh[f] = mhR - mhL;
-      }
     }
 #pragma unroll
     for (int i = 0; i < K + 2; ++i) hf[i] = xh[i + 1];
@@ -687,13 +669,14 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
   __syncthreads();
   // round m: m-dagger before the relaxation term; with a bed the m-diffusion
   // subtracts the jump of the face-local rest moment (zeta_f - b)^2, formed
-  // here in the lean form
+  // here from the depths kept since the h round and the staged bed (held
+  // from the h round instead, the jumps spilled registers in stage 2)
   double mdp[K], em[K];
   if (act) {
     save_side(2);
     double xm[K + 4], xb[K + 4], Fm[K + 1];
     read_x(xm, ebuf(2));
-    if (BED && useb && kLean) {
+    if (BED && useb) {
       read_x(xb, L.u.st.b);
     } else {
 #pragma unroll
@@ -704,7 +687,7 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
       const double mL = xm[f + 1] + P.sl * (xm[f + 2] - xm[f]);
       const double mR = xm[f + 2] - P.sl * (xm[f + 3] - xm[f + 1]);
       double jm = mR - mL;
-      if (BED && kLean) {
+      if (BED) {
         const double zf = 0.5 * ((hf[f] + xb[f + 1]) + (hf[f + 1] + xb[f + 2]));
         const double rm = (zf - xb[f]) * (zf - xb[f]);
         const double r0 = (zf - xb[f + 1]) * (zf - xb[f + 1]);
@@ -713,8 +696,6 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
         const double mhL = r0 + P.sl * (r1 - rm);
         const double mhR = r1 - P.sl * (r2 - r0);
         jm = jm - (mhR - mhL);
-      } else if (BED) {
-        jm = jm - dmh[f];
       }
       Fm[f] = 0.5 * (mL * uL[f] + mR * uR[f] - ap[f] * jm);
     }
@@ -722,7 +703,7 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
     for (int j = 0; j < K; ++j) {
       double md = old_of(xm, j) - P.tdx * (Fm[j + 1] - Fm[j]);
       if (BED) {
-        const double db = kLean ? xb[j + 3] - xb[j + 1] : bed_row(j + 2) - bed_row(j);
+        const double db = xb[j + 3] - xb[j + 1];
         md -= P.tau * 1.5 * eq[j] * (db * i2dx);
       }
       mdp[j] = md;
@@ -853,6 +834,7 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
   __syncthreads();  // nb region is reused by the level-1 system below
 
   // ---- rows and chunk elimination (K rows per thread, all real or identity)
+  constexpr bool kStash = STAGE == 2 && BED;
   double cp[K], y[K], v[K], w[K];
   double loE = 0.0, upE = 0.0;  // couplings moved to the right-hand side
   if (act) {
@@ -874,6 +856,13 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
         Rb.b = bed_row(j + 2);
       }
       make_row<BED>(Lb, Cb, Rb, L.u.st.ho[spad(p0 + 3 + j)], P, lo, di, up, rhs);
+      if (kStash) {
+        // m-dagger and W-dagger wait in this row's slots of the old-depth and
+        // bed buffers (read by no one after the rows) until the
+        // back-substitution, instead of in registers through the solve
+        L.u.st.ho[spad(p0 + 3 + j)] = rec[j].Wd;
+        L.u.st.b[spad(p0 + 3 + j)] = rec[j].md;
+      }
       if (t == 0 && j == 0) {
         if (physL) {
           di += lo;
@@ -1126,8 +1115,10 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
         const double qn = rec[j].qd - P.tau * force;
         const double ih = frcp(h);
         const double ih2 = ih * ih;
-        const double mn = rec[j].md * frcp(1.0 + P.lt2 * ih2);
-        const double Wn = rec[j].Wd - P.lam * P.tau * mn * ih2;
+        const double md = kStash ? L.u.st.b[spad(p0 + 3 + j)] : rec[j].md;
+        const double Wd = kStash ? L.u.st.ho[spad(p0 + 3 + j)] : rec[j].Wd;
+        const double mn = md * frcp(1.0 + P.lt2 * ih2);
+        const double Wn = Wd - P.lam * P.tau * mn * ih2;
         bad |= !(h > 0.0) || !isfinite(qn) || !isfinite(mn) || !isfinite(Wn);
         on[0][j] = h;
         on[1][j] = qn;
