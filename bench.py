@@ -38,7 +38,7 @@ TRAFFIC = [
      "fetch_bytes": 2232887832, "write_bytes": 1118343168, "bytes_per_launch": 3351231000},
     {"kernel": "sgn_solve", "workload": "batched_flat", "scheme": "sgn",
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp",
-                 "hsgn_explicit.hpp", "hsgn_sgn.hpp"], "hash": "090d67620c932aa2",
+                 "hsgn_explicit.hpp", "hsgn_sgn.hpp"], "hash": "750031ac7d6becb8",
      "fetch_bytes": 676269416, "write_bytes": 273330176, "bytes_per_launch": 949599592},
 ]
 

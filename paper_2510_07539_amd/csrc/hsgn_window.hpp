@@ -430,13 +430,12 @@ struct WinLds {
 template <int NT, int K, bool BED, int STAGE>
 __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L, const int bid,
                                         const int t) {
-  // Register budget: 256 per lane (two waves per SIMD).  Stage 1 fits it
-  // when it also (i) addresses the staged loads with 32-bit offsets from
-  // per-instance base pointers and (ii) reads neighbour beds from the
-  // staged bed instead of carrying them in the records (kLean).  For stage
-  // 2 these two measured slower, so it keeps the plain forms and instead
-  // parks m-dagger and W-dagger in LDS through the solve (kStash below).
-  // Both forms give the same values.
+  // Register budget: 256 per lane (two waves per SIMD).  Both stages
+  // address the staged loads with 32-bit offsets from per-instance base
+  // pointers.  Stage 1 also reads neighbour beds from the staged bed instead
+  // of carrying them in the records (kLean); stage 2 carries them (measured
+  // faster) and parks m-dagger and W-dagger in LDS through the solve
+  // (kStash below).  Both forms give the same values.
   constexpr bool kLean = STAGE == 1;
   const StageArgs& A = W.s;
   const WinDesc wd = W.win[bid];
@@ -495,11 +494,11 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
     return f == 0 ? A.un_h : f == 1 ? A.un_q : f == 2 ? A.un_m : A.un_W;
   };
   double va[NR], vb[NR], vc[NR];
-  int cidx[NR];  // instance-relative cells of the staged elements (lean form)
+  int cidx[NR];  // instance-relative cells of the staged elements
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int i = t + r * NT;
-    cidx[r] = (kLean && i < SLn) ? cell_of(i) : 0;
+    cidx[r] = i < SLn ? cell_of(i) : 0;
   }
   // loads of round f into (xa, xb, xc): U^n, U(1) and the bed
   auto load_into = [&](int f, double* xa, double* xb, double* xc) {
@@ -509,16 +508,9 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
     for (int r = 0; r < NR; ++r) {
       const int i = t + r * NT;
       if (i < SLn) {
-        if constexpr (kLean) {
-          xa[r] = (un + base)[cidx[r]];
-          if (STAGE == 2) xb[r] = (u1 + base)[cidx[r]];
-          if (BED && f == 0 && useb) xc[r] = (A.b + base)[cidx[r]];
-        } else {
-          const int64_t gi = base + cell_of(i);
-          xa[r] = un[gi];
-          if (STAGE == 2) xb[r] = u1[gi];
-          if (BED && f == 0 && useb) xc[r] = A.b[gi];
-        }
+        xa[r] = (un + base)[cidx[r]];
+        if (STAGE == 2) xb[r] = (u1 + base)[cidx[r]];
+        if (BED && f == 0 && useb) xc[r] = (A.b + base)[cidx[r]];
       }
     }
   };
@@ -818,11 +810,8 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
   // their records are never used, so the slot after row jl takes recR, the
   // right neighbour of row jl, and the rows and the back-substitution below
   // read rec[j + 1] for every j < K - 1 without a per-row select.  Only the
-  // wave holding that thread takes this branch.  (Stage 1 only: stage 2,
-  // which keeps the per-row selects, measured 1.8 % slower this way, its
-  // register allocation being different.)
-  constexpr bool kNoSel = STAGE == 1;
-  if (kNoSel && act) {
+  // wave holding that thread takes this branch.
+  if (act) {
     const int jl = wd.wl - 1 - p0;
     if (jl < K - 1) {
 #pragma unroll
@@ -845,7 +834,7 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
     for (int j = 0; j < K; ++j) {
       const bool real = j <= jl;
       const Rec Lr = (j == 0) ? recL : rec[j > 0 ? j - 1 : 0];
-      const Rec Rr = (j == K - 1 || (!kNoSel && j == jl)) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
+      const Rec Rr = (j == K - 1) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
       double lo, di, up, rhs;
       // lean form: the beds of the row and its neighbours come from the
       // staged bed (the records carry no copy of it)
@@ -1100,7 +1089,7 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
       const int p = p0 + j;
       if (p >= c0 && p < c1) {
         const Rec Lr = (j == 0) ? recL : rec[j > 0 ? j - 1 : 0];
-        const Rec Rr = (j == K - 1 || (!kNoSel && j == jl)) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
+        const Rec Rr = (j == K - 1) ? recR : rec[j + 1 < K ? j + 1 : K - 1];
         const double hm = (j == 0) ? hl_nb : hb[j > 0 ? j - 1 : 0];
         const double hp = (j == K - 1) ? hr_nb : ((j == jl && physR) ? hb[j] : hb[j + 1 < K ? j + 1 : K - 1]);
         const double h = hb[j];
