@@ -30,13 +30,13 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # keyed by the hash of the code of its kernels' sources (comments and blank
 # lines left out) and reported as null once that code changes.
 TRAFFIC = [
-    {"kernel": "win2", "workload": "batched_bar", "solver": "auto_small",
+    {"kernel": "win2", "workload": "batched_bar", "solver": "auto_small", "halo_margin": 2.0,
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp"], "hash": "247e7ed8cedeba31",
      "fetch_bytes": 2462066164, "write_bytes": 1097801632, "bytes_per_launch": 3559867796},
     {"kernel": "ex2", "workload": "batched_flat", "scheme": "explicit",
      "sources": ["hsgn_kernels.hpp", "hsgn_explicit.hpp"], "hash": "2e6dc71f10ea1fd9",
      "fetch_bytes": 2232887832, "write_bytes": 1118343168, "bytes_per_launch": 3351231000},
-    {"kernel": "sgn_solve", "workload": "batched_flat", "scheme": "sgn",
+    {"kernel": "sgn_solve", "workload": "batched_flat", "scheme": "sgn", "halo_margin": 2.0,
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp",
                  "hsgn_explicit.hpp", "hsgn_sgn.hpp"], "hash": "750031ac7d6becb8",
      "fetch_bytes": 676269416, "write_bytes": 273330176, "bytes_per_launch": 949599592},
@@ -116,14 +116,17 @@ def make_workload(name):
     raise SystemExit("unknown workload " + name)
 
 
-def per_instance_rate(wl, n_sample, steps, order=2):
-    """Same kernels, one context per instance, eager launches in a host loop."""
+def per_instance_rate(wl, n_sample, steps, order=2, halo_margin=2.0):
+    """Same kernels, one context per instance, eager launches in a host loop
+    (at the batched run's halo margin; no halo retry, whose status read
+    after every call would serialise the host loop)."""
     import numpy as np
     import torch
     from paper_2510_07539_amd.hsgn import Solver
     idx = np.linspace(0, wl.n_inst - 1, n_sample).astype(int)
     solvers = [Solver.from_workload(wl.subset([int(j)]), order=order) for j in idx]
     for s in solvers:
+        s.set_halo_margin(halo_margin)
         s.step(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -185,13 +188,14 @@ def cpu_baseline(wl, budget_s=15.0, n_sample=1024, max_steps=200, order=2):
                       (sub.n_inst, sub.n_cells, steps, len(rates), chunk, el)}
 
 
-def scheme_comparison(si_steps=20):
+def scheme_comparison(si_steps=20, halo_margin=2.0, halo_retry=False):
     """The paper's cost comparison on MI355X: the semi-implicit step (CFL 0.9
     on |u| + sqrt(g h)) against the explicit Heun step (CFL 0.4 on |u| + c)
     and the standard SGN solver (Heun, CFL 0.9), all advancing the flat
     batch to the same physical time T, one lambda at a time (the SGN run
     does not depend on lambda).  T = si_steps * 0.9 dx / max(|u| + sqrt(g h)) of the initial
-    state; each run stops once every instance has reached T (t_end clamp)."""
+    state; each run stops once every instance has reached T (t_end clamp).
+    The windowed schemes run at the given halo margin and retry setting."""
     import numpy as np
     import torch
     from paper_2510_07539_amd import workloads as WL
@@ -209,6 +213,9 @@ def scheme_comparison(si_steps=20):
                                   ("sgn", SCHEME_SGN, 0.9)):
             s = Solver.from_workload(sub, solver="auto_small" if scheme == 0 else None,
                                      scheme=scheme, cfl=cfl)
+            if scheme != SCHEME_EXPLICIT:
+                s.set_halo_margin(halo_margin)
+                s.set_halo_retry(halo_retry)
             try:
                 def to_T():
                     steps = 0
@@ -304,8 +311,12 @@ def main():
                     help="tune: the library times every mode on the workload and keeps the fastest")
     ap.add_argument("--launch", default="tune", choices=["tune", "grid", "persistent"],
                     help="window-stage launch; tune: the library times both and keeps the faster")
-    ap.add_argument("--halo-margin", type=float, default=2.0,
-                    help="safety factor of the windowed solves' halo estimates")
+    ap.add_argument("--halo-margin", type=float, default=1.0,
+                    help="safety factor of the windowed solves' halo estimates (the "
+                         "library's default is 2)")
+    ap.add_argument("--no-halo-retry", dest="halo_retry", action="store_false",
+                    help="no halo retry (on by default: a block whose windows flag runs "
+                         "again from its initial state with twice the margin)")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--table-out", default=None,
                     help="write the autotuner's table (JSON) to this file")
@@ -355,8 +366,10 @@ def main():
     else:
         s = Solver.from_workload(wl, solver=None if args.solver == "tune" else args.solver,
                                  order=args.order)
-    if args.halo_margin != 2.0:
+    if args.scheme != "explicit":  # the explicit scheme has no windows
         s.set_halo_margin(args.halo_margin)
+        if args.halo_retry:
+            s.set_halo_retry(True)
     tuned = None
     if args.table_in and not explicit:
         # a stored autotuner table: each instance takes its class's mode
@@ -408,6 +421,7 @@ def main():
         s.run(block, block=block)
         graph_warm = block
     legs = []
+    leg_retries = []
     for _ in range(max(args.legs, 1)):
         s.set_state(*init_state)
         torch.cuda.synchronize()
@@ -418,6 +432,7 @@ def main():
             s.step(args.steps)
         torch.cuda.synchronize()
         legs.append(time.perf_counter() - t0)
+        leg_retries.append(s.halo_state()[1])
     el = float(np.median(legs))
     rc, flags = s.status()
     if rc != 0:
@@ -451,6 +466,7 @@ def main():
                 tr.get("solver", solver_used) == solver_used and
                 tr.get("scheme", args.scheme) == args.scheme and
                 tr.get("launch", "grid") == launch and
+                tr.get("halo_margin", args.halo_margin) == args.halo_margin and
                 src_hash(tr["sources"]) == tr["hash"]):
             traffic = tr["bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -491,7 +507,10 @@ def main():
                    "solver": tuned["kept"] if tuned else args.solver, "autotune": tuned,
                    "window_launches": plan["window_launches"],
                    "launch": launch, "launch_ms_per_step": launch_ms,
-                   "halo_margin": args.halo_margin,
+                   "halo_margin": None if args.scheme == "explicit" else args.halo_margin,
+                   "halo_retry": bool(args.halo_retry) and args.scheme != "explicit",
+                   "halo_margin_final": None if args.scheme == "explicit" else s.halo_state()[0],
+                   "timed_legs_blocks_run_again": leg_retries,
                    "windows": plan["windows"], "window_rows": plan["window_rows"],
                    "two_pass_tiles": plan["exact_tiles"]},
         "roofline": roof,
@@ -499,16 +518,18 @@ def main():
         "kernel_ms_per_step": {k: round(v[0] / args.timed_steps, 4) for k, v in kt.items() if v[1]},
     }
     if not args.no_per_instance and wl.n_inst > 1 and not explicit:
-        r, pel, ns = per_instance_rate(wl, 32, 3, order=args.order)
+        r, pel, ns = per_instance_rate(wl, 32, 3, order=args.order, halo_margin=args.halo_margin)
         out["per_instance"] = {"value": r, "unit": "cell-stage updates/s",
                                "sample": "%d instances spread over the batch, one context each, "
-                                         "eager launches, 3 steps" % ns}
+                                         "eager launches, 3 steps, halo margin %g without "
+                                         "retry" % (ns, args.halo_margin)}
         out["batched_over_per_instance"] = value / r
     s.close()
     if not args.no_adjoint and args.workload == "batched_bar" and args.order == 2:
         out["adjoint"] = adjoint_cost()
     if not args.no_compare and args.workload == "batched_bar" and args.order == 2:
-        out["scheme_comparison"] = scheme_comparison()
+        out["scheme_comparison"] = scheme_comparison(halo_margin=args.halo_margin,
+                                                     halo_retry=args.halo_retry)
     if not args.no_cpu and not explicit:
         out["cpu_baseline"] = cpu_baseline(wl, order=args.order)
     print(json.dumps(out))

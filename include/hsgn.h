@@ -247,6 +247,26 @@ int hsgn_autotune_classes(hsgn_ctx* ctx, int32_t nsteps, int32_t max_classes, in
  * the class autotuner's contexts take the same factor. */
 int hsgn_set_halo_margin(hsgn_ctx* ctx, double margin);
 
+/* Halo retry, for callers that run with a small halo margin: enable = 1
+ * turns it on, 0 (the default) off (else HSGN_EINVAL).  When on, hsgn_step
+ * (each call) and hsgn_run (each graph block, and the eager remainder)
+ * copy the mutable state first (the four fields, times, speed bounds,
+ * status and step counts: 4 doubles per cell, allocated on first use and
+ * kept until hsgn_destroy), then read the status flags, which synchronises
+ * the stream.  If a windowed solve flagged its truncation
+ * (HSGN_FLAG_WINDOW), the copy is restored, the halo margin doubled (at
+ * most 64; it keeps the new value), the solver re-planned and the block run
+ * again, so every window of the result certifies its truncation as with
+ * the default margin.  Other flags, and a window flag at margin 64, are
+ * left for hsgn_status.  No effect with the explicit scheme (no windows).
+ * The windowed solves of hsgn_adjoint do not retry. */
+int hsgn_set_halo_retry(hsgn_ctx* ctx, int32_t enable);
+
+/* Current halo margin (h_margin, host, or NULL) and the number of blocks
+ * run again by the halo retry since the state was loaded (h_retries, host,
+ * or NULL). */
+int hsgn_halo_state(hsgn_ctx* ctx, double* h_margin, int32_t* h_retries);
+
 /* Launch of the window stages:
  *  HSGN_LAUNCH_GRID (the default): one workgroup per window, consecutive
  *    windows of an instance dealt to one XCD; the hardware dispatcher

@@ -126,6 +126,15 @@ struct hsgn_ctx {
   // persistent kernel walking per-XCD work queues (HSGN_LAUNCH_PERSISTENT)
   int32_t launch = HSGN_LAUNCH_GRID;
   double halo_margin = kWinMargin;  // safety factor of the halo estimates
+  // halo retry (hsgn_set_halo_retry): a copy of the mutable state taken at
+  // the start of every block of steps, restored when a window could not
+  // certify its truncation; the block then runs again with twice the margin
+  bool halo_retry = false;
+  int32_t n_retry = 0;                  // blocks run again since the state was loaded
+  double* rb_state = nullptr;           // 4 x ncell: h, q, m, W
+  double* rb_t = nullptr;               // n_inst times
+  unsigned long long* rb_sp = nullptr;  // 3 x n_inst: speed bounds, depth maxima
+  int32_t* rb_st = nullptr;             // 2 x n_inst: status, step counts
   // 2 x 9 queue counters of the persistent kernel: the first set for the
   // library's stream, the second for the adjoint's recompute stream (zero
   // between launches: every launch resets its own)
@@ -192,7 +201,8 @@ void free_all(hsgn_ctx* c) {
                   c->d_rdi,
                   c->d_rup, c->d_rrhs, c->d_rx, c->d_scp, c->d_sy, c->d_sv, c->d_sw,
                   c->d_ex_tiles, c->d_ex_tiles_multi, c->d_ex_multi, c->d_win, c->d_hmax,
-                  c->d_xtiles, c->d_sgn, c->d_queue};
+                  c->d_xtiles, c->d_sgn, c->d_queue, c->rb_state, c->rb_t, c->rb_sp,
+                  c->rb_st};
   for (void* p : ptrs)
     if (p) hipFree(p);
   for (int i = 0; i < 3; ++i)
@@ -788,6 +798,97 @@ int build_layout(hsgn_ctx* c, int32_t n_inst, const int64_t* offsets, const hsgn
   return rc;
 }
 
+// The graph of `block` steps from the current buffer rotation, captured on
+// first use (capture executes nothing, so the rotation is restored after it).
+int graph_of(hsgn_ctx* c, int block, hipGraphExec_t* out) {
+  for (auto& g : c->graphs)
+    if (g.block == block && g.cur == c->cur) {
+      *out = g.exec;
+      return HSGN_OK;
+    }
+  const int cur0 = c->cur, nxt0 = c->nxt;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int erc = HSGN_OK;
+  for (int s = 0; s < block && erc == HSGN_OK; ++s) erc = enqueue_step(c);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  c->cur = cur0;
+  c->nxt = nxt0;
+  if (erc) return erc;
+  if (e != hipSuccess) return fail(c, HSGN_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(c, HSGN_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  c->graphs.push_back({block, c->cur, exec});
+  *out = exec;
+  return HSGN_OK;
+}
+
+// Copy the mutable state (the current buffers' four fields, times, speed
+// bounds, depth maxima, status flags, step counts) to the retry copy
+// (to_copy) or back (!to_copy), on the library's stream.
+int retry_copy(hsgn_ctx* c, bool to_copy) {
+  const size_t nc = (size_t)c->ncell, ni = (size_t)c->n_inst;
+  auto cp = [&](void* keep, void* live, size_t bytes) {
+    return hipMemcpyAsync(to_copy ? keep : live, to_copy ? live : keep, bytes,
+                          hipMemcpyDeviceToDevice, c->stream);
+  };
+  for (int f = 0; f < 4; ++f)
+    HIPCHK(c, cp(c->rb_state + f * nc, c->buf[c->cur][f], nc * sizeof(double)));
+  HIPCHK(c, cp(c->rb_t, c->d_t, ni * sizeof(double)));
+  HIPCHK(c, cp(c->rb_sp, c->d_smax, ni * sizeof(unsigned long long)));
+  HIPCHK(c, cp(c->rb_sp + ni, c->d_umax, ni * sizeof(unsigned long long)));
+  HIPCHK(c, cp(c->rb_sp + 2 * ni, c->d_hmax, ni * sizeof(unsigned long long)));
+  HIPCHK(c, cp(c->rb_st, c->d_status, ni * sizeof(int32_t)));
+  HIPCHK(c, cp(c->rb_st + ni, c->d_nstep, ni * sizeof(int32_t)));
+  return HSGN_OK;
+}
+
+constexpr double kMaxMargin = 64.0;  // the largest halo margin (hsgn_set_halo_margin)
+
+// Enqueue a block of steps (chunk).  With the halo retry on (semi-implicit
+// and SGN schemes, whose windows certify their truncation), the mutable
+// state is copied first and the status read after the block (synchronising
+// the stream); if a window flagged its truncation, the copy is restored,
+// the halo margin doubled (up to kMaxMargin) and the solver re-planned, and
+// the block runs again.  Other flags, and a window flag at the largest
+// margin, are left for hsgn_status.
+template <class Chunk>
+int run_retrying(hsgn_ctx* c, Chunk chunk) {
+  if (!c->halo_retry || c->scheme == HSGN_SCHEME_EXPLICIT) return chunk();
+  const size_t nc = (size_t)c->ncell, ni = (size_t)c->n_inst;
+  int rc = HSGN_OK;
+  if (!c->rb_state) {
+    rc = dmalloc(c, &c->rb_state, 4 * nc);
+    if (!rc) rc = dmalloc(c, &c->rb_t, ni);
+    if (!rc) rc = dmalloc(c, &c->rb_sp, 3 * ni);
+    if (!rc) rc = dmalloc(c, &c->rb_st, 2 * ni);
+    if (rc) return rc;
+  }
+  std::vector<int32_t> flags(ni);
+  for (;;) {
+    const int cur0 = c->cur, nxt0 = c->nxt;
+    rc = retry_copy(c, true);
+    if (!rc) rc = chunk();
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(flags.data(), c->d_status, ni * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bool win = false;
+    for (size_t j = 0; j < ni; ++j) win |= (flags[j] & hsgn::kFlagWindow) != 0;
+    if (!win || c->halo_margin >= kMaxMargin) return HSGN_OK;
+    c->cur = cur0;
+    c->nxt = nxt0;
+    rc = retry_copy(c, false);
+    if (rc) return rc;
+    c->halo_margin = std::min(kMaxMargin, 2.0 * c->halo_margin);
+    ++c->n_retry;
+    rc = make_plan(c);
+    if (rc) return rc;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -914,6 +1015,7 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
 // current state, and make the solver plan from them (synchronises the stream).
 static int reset_and_plan(hsgn_ctx* c) {
   double** U = c->buf[c->cur];
+  c->n_retry = 0;
   const int nb = (c->n_inst + 255) / 256;
   hipLaunchKernelGGL(hsgn::k_fill_i32, dim3(nb), dim3(256), 0, c->stream, c->n_inst, c->d_status,
                      0);
@@ -1038,7 +1140,12 @@ int hsgn_step(hsgn_ctx* c, int32_t nsteps) {
   if (!c) return HSGN_EINVAL;
   if (nsteps < 0) return fail(c, HSGN_EINVAL, "hsgn_step: nsteps < 0");
   int rc = enter(c);
-  for (int s = 0; s < nsteps && rc == HSGN_OK; ++s) rc = enqueue_step(c);
+  if (rc) return rc;
+  rc = run_retrying(c, [&]() {
+    int r = HSGN_OK;
+    for (int s = 0; s < nsteps && r == HSGN_OK; ++s) r = enqueue_step(c);
+    return r;
+  });
   if (rc) return rc;
   return leave(c);
 }
@@ -1050,33 +1157,37 @@ int hsgn_run(hsgn_ctx* c, int32_t nsteps, int32_t block) {
   int rc = enter(c);
   if (rc) return rc;
   int done = 0;
-  if (nsteps >= block) {
-    hipGraphExec_t exec = nullptr;
-    for (auto& g : c->graphs)
-      if (g.block == block && g.cur == c->cur) exec = g.exec;
-    if (!exec) {
-      const int cur0 = c->cur, nxt0 = c->nxt;
-      HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-      int erc = HSGN_OK;
-      for (int s = 0; s < block && erc == HSGN_OK; ++s) erc = enqueue_step(c);
-      hipGraph_t graph = nullptr;
-      hipError_t e = hipStreamEndCapture(c->stream, &graph);
-      c->cur = cur0;  // capture does not execute: restore the rotation
-      c->nxt = nxt0;
-      if (erc) return erc;
-      if (e != hipSuccess) return fail(c, HSGN_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-      e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      hipGraphDestroy(graph);
-      if (e != hipSuccess)
-        return fail(c, HSGN_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-      c->graphs.push_back({block, c->cur, exec});
-    }
-    for (; done + block <= nsteps; done += block)
-      HIPCHK(c, hipGraphLaunch(exec, c->stream));
-  }
-  for (; done < nsteps && rc == HSGN_OK; ++done) rc = enqueue_step(c);
+  for (; done + block <= nsteps && rc == HSGN_OK; done += block)
+    rc = run_retrying(c, [&]() {
+      hipGraphExec_t exec = nullptr;
+      int r = graph_of(c, block, &exec);
+      if (r == HSGN_OK) HIPCHK(c, hipGraphLaunch(exec, c->stream));
+      return r;
+    });
+  if (rc) return rc;
+  if (done < nsteps)
+    rc = run_retrying(c, [&]() {
+      int r = HSGN_OK;
+      for (int s = done; s < nsteps && r == HSGN_OK; ++s) r = enqueue_step(c);
+      return r;
+    });
   if (rc) return rc;
   return leave(c);
+}
+
+int hsgn_set_halo_retry(hsgn_ctx* c, int32_t enable) {
+  if (!c) return HSGN_EINVAL;
+  if (enable != 0 && enable != 1)
+    return fail(c, HSGN_EINVAL, "hsgn_set_halo_retry: enable must be 0 or 1");
+  c->halo_retry = enable == 1;
+  return HSGN_OK;
+}
+
+int hsgn_halo_state(hsgn_ctx* c, double* h_margin, int32_t* h_retries) {
+  if (!c) return HSGN_EINVAL;
+  if (h_margin) *h_margin = c->halo_margin;
+  if (h_retries) *h_retries = c->n_retry;
+  return HSGN_OK;
 }
 
 int hsgn_step_timed(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_count) {
@@ -1284,7 +1395,7 @@ int hsgn_set_instance_solvers(hsgn_ctx* c, const int32_t* h_modes) {
 
 int hsgn_set_halo_margin(hsgn_ctx* c, double margin) {
   if (!c) return HSGN_EINVAL;
-  if (!(margin > 0.0 && margin <= 64.0))
+  if (!(margin > 0.0 && margin <= kMaxMargin))
     return fail(c, HSGN_EINVAL, "hsgn_set_halo_margin: margin %g outside (0, 64]", margin);
   c->halo_margin = margin;
   int rc = enter(c);

@@ -87,6 +87,10 @@ def lib():
         L.hsgn_set_halo_margin.argtypes = [vp, C.c_double]
         L.hsgn_set_launch.restype = C.c_int
         L.hsgn_set_launch.argtypes = [vp, C.c_int32]
+        L.hsgn_set_halo_retry.restype = C.c_int
+        L.hsgn_set_halo_retry.argtypes = [vp, C.c_int32]
+        L.hsgn_halo_state.restype = C.c_int
+        L.hsgn_halo_state.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.hsgn_autotune_launch.restype = C.c_int
         L.hsgn_autotune_launch.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.hsgn_step_noalloc.restype = C.c_int
@@ -157,6 +161,19 @@ class Solver:
         """Safety factor of the windowed solves' halo estimates (default 2);
         re-plans at once."""
         self._check(lib().hsgn_set_halo_margin(self._h, float(margin)), "hsgn_set_halo_margin")
+
+    def set_halo_retry(self, enable=True):
+        """Halo retry: a block whose windows could not certify their
+        truncation is run again from a copy of its initial state with twice
+        the halo margin (hsgn_run and hsgn_step then synchronise)."""
+        self._check(lib().hsgn_set_halo_retry(self._h, 1 if enable else 0), "hsgn_set_halo_retry")
+
+    def halo_state(self):
+        """(current halo margin, blocks run again since the state was loaded)."""
+        m = C.c_double()
+        r = C.c_int32()
+        self._check(lib().hsgn_halo_state(self._h, C.byref(m), C.byref(r)), "hsgn_halo_state")
+        return m.value, r.value
 
     def set_launch(self, launch):
         """Window-stage launch: "grid" (one workgroup per window) or

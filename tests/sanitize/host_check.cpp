@@ -154,6 +154,17 @@ void run_context(const char* name, const Batch& B, bool tune) {
     hsgn_step(c, 1);
     const int rs = hsgn_status(c, flags.data());
     std::printf("%-40s rc=%d\n", "hsgn_status (short halos)", rs);
+    expect("hsgn_set_state (again)", hsgn_set_state(c, gh, gq, gm, gW, gt), HSGN_OK, c);
+    expect("hsgn_set_halo_retry", hsgn_set_halo_retry(c, 1), HSGN_OK, c);
+    expect("hsgn_run (retrying)", hsgn_run(c, 5, 2), HSGN_OK, c);
+    expect("hsgn_step (retrying)", hsgn_step(c, 3), HSGN_OK, c);
+    double margin = 0.0;
+    int32_t retries = -1;
+    expect("hsgn_halo_state", hsgn_halo_state(c, &margin, &retries), HSGN_OK, c);
+    std::printf("%-40s margin %g, %d blocks run again\n", "", margin, retries);
+    expect("hsgn_status (after retries)", hsgn_status(c, flags.data()), HSGN_OK, c);
+    expect("hsgn_set_halo_retry (bad)", hsgn_set_halo_retry(c, 2), HSGN_EINVAL, c);
+    expect("hsgn_set_halo_retry (off)", hsgn_set_halo_retry(c, 0), HSGN_OK, c);
     expect("hsgn_set_halo_margin (bad)", hsgn_set_halo_margin(c, -1.0), HSGN_EINVAL, c);
     expect("hsgn_set_halo_margin (default)", hsgn_set_halo_margin(c, 2.0), HSGN_OK, c);
   }

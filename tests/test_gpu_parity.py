@@ -76,11 +76,15 @@ def check_instance(j, U, wl, nsteps, tol=TOL, seed=0, state_sens=False, order=2,
 
 
 def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", solver="auto",
-            order=2, scheme=0, cfl=None, state_sens=False):
+            order=2, scheme=0, cfl=None, state_sens=False, margin=None, retry=False):
     note("parity %s [%s, order %d, scheme %d]: %s, %d instances, %d cells, %d steps" % (
         label, solver, order, scheme, wl.name, wl.n_inst, wl.n_cells, nsteps))
     Solver = _solver()
     s = Solver.from_workload(wl, solver=solver, order=order, scheme=scheme, cfl=cfl)
+    if margin is not None:
+        s.set_halo_margin(margin)
+    if retry:
+        s.set_halo_retry(True)
     info = s.plan_info()
     note("  plan: %d windows, %d two-pass tiles, halo max %d" % (
         info["windows"], info["exact_tiles"], int(info["halo"].max())))
@@ -91,6 +95,8 @@ def compare(wl, nsteps, use_run=False, block=50, insts=None, tol=TOL, label="", 
     (h, q, m, W), t = s.get_state()
     rc, flags = s.status()
     assert rc == 0, ("status", rc, np.nonzero(flags))
+    if margin is not None or retry:
+        note("  halo margin %.3g, blocks run again %d" % s.halo_state())
     U = [x.cpu().numpy() for x in (h, q, m, W)]
     tg = t.cpu().numpy()
     s.close()
@@ -262,13 +268,14 @@ def test_long_periodic_scaled(solver):
     compare(wl, 20, label="long periodic scaled", solver=solver)
 
 
-@pytest.mark.parametrize("solver", SOLVERS)
-def test_batched_full_size_sampled(solver):
+@pytest.mark.parametrize("solver,margin", [(m, None) for m in SOLVERS] + [("auto_small", 1.0)])
+def test_batched_full_size_sampled(solver, margin):
     """The full batched workload (4096 instances) in the launch configuration
     the benchmark times (graph-captured blocks; the autotuner keeps
-    auto_small there), and in the other two solver modes; instances sampled
-    for the oracle: the smallest and largest, both ends of the batch, the
-    first of each lambda, and the longest instance of each lambda (the most
+    auto_small there, at halo margin 1 with the halo retry), and in the
+    three solver modes at the default margin; instances sampled for the
+    oracle: the smallest and largest, both ends of the batch, the first of
+    each lambda, and the longest instance of each lambda (the most
     windows)."""
     wl = WL.batched_bar()
     sizes = wl.sizes()
@@ -279,7 +286,7 @@ def test_batched_full_size_sampled(solver):
         pick.append(int(sel[0]))
         pick.append(int(sel[np.argmax(sizes[sel])]))
     compare(wl, 100, use_run=True, block=100, insts=sorted(set(pick)),
-            label="C3 full, sampled", solver=solver)
+            label="C3 full, sampled", solver=solver, margin=margin, retry=margin is not None)
 
 
 def test_default_auxiliary_variables():
@@ -804,6 +811,45 @@ def test_halo_margin_short_halos_are_flagged(scheme):
     s.close()
     for j in range(wl.n_inst):
         check_instance(j, U, wl, 5, scheme=scheme)
+
+
+@pytest.mark.parametrize("scheme", [0, SGNS])
+def test_halo_retry_recovers_short_halos(scheme):
+    """hsgn_set_halo_retry: at the far too small factor of the test above,
+    with the retry on, a block whose windows flag is run again from a copy
+    of its initial state with twice the margin until every window certifies
+    its truncation; the result carries no flag and matches the oracle, in
+    one eager call and in graph blocks with an eager remainder.  The grown
+    margin is kept: after a reload the same steps need no retry."""
+    Solver = _solver()
+    if scheme == SGNS:
+        wl = WL.batched_flat(n_inst=6, seed=19, n_lo=513, n_hi=9000)
+    else:
+        wl = WL.batched_bar(n_inst=6, seed=19, n_lo=513, n_hi=9000)
+    for mode in ("step", "run"):
+        s = Solver.from_workload(wl, scheme=scheme)
+        s.set_halo_margin(1e-4)
+        s.set_halo_retry(True)
+        if mode == "step":
+            s.step(5)
+        else:
+            s.run(5, block=2)
+        rc, flags = s.status()
+        assert rc == 0, (mode, rc, flags)
+        margin, retries = s.halo_state()
+        note("  %s: halo margin 1e-4 -> %.3g after %d blocks run again" % (mode, margin, retries))
+        assert retries >= 1 and margin > 1e-4
+        (h, q, m, W), _ = s.get_state()
+        U = [x.cpu().numpy() for x in (h, q, m, W)]
+        for j in range(wl.n_inst):
+            check_instance(j, U, wl, 5, scheme=scheme)
+        # reload: the kept margin certifies the same steps at once
+        s.set_state(torch.from_numpy(wl.h).cuda(), torch.from_numpy(wl.q).cuda(),
+                    torch.from_numpy(wl.m).cuda(), torch.from_numpy(wl.W).cuda())
+        s.step(5)
+        assert s.status()[0] == 0
+        assert s.halo_state() == (margin, 0)
+        s.close()
 
 
 def test_sgn_graph_replay_equals_eager_and_t_end():
