@@ -24,15 +24,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # HBM traffic of the dominant kernels measured with rocprofv3 --pmc (FETCH_SIZE
 # and WRITE_SIZE in separate runs, `bench.py --probe [--solver auto_small |
-# --scheme explicit | --scheme sgn]`), scaled by the same counters on a plain
-# 512 MiB copy (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0), in bytes per launch
-# (the SGN solve: per stage, every kernel of the phi solve).  Each entry is
-# keyed by the hash of the code of its kernels' sources (comments and blank
-# lines left out) and reported as null once that code changes.
+# --scheme explicit | --scheme sgn] [--halo-margin 2]`), scaled by the same
+# counters on a plain 512 MiB copy (FETCH_SIZE x 1.9998, WRITE_SIZE x 1.0), in
+# bytes per launch (the SGN solve: per stage, every kernel of the phi solve).
+# Each entry is keyed by the workload, solver mode or scheme, halo margin, and
+# the hash of the code of its kernels' sources (comments and blank lines left
+# out), and reported as null once that code changes.
 TRAFFIC = [
     {"kernel": "win2", "workload": "batched_bar", "solver": "auto_small", "halo_margin": 2.0,
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp"], "hash": "247e7ed8cedeba31",
      "fetch_bytes": 2462066164, "write_bytes": 1097801632, "bytes_per_launch": 3559867796},
+    {"kernel": "win2", "workload": "batched_bar", "solver": "auto_small", "halo_margin": 1.0,
+     "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp"], "hash": "247e7ed8cedeba31",
+     "fetch_bytes": 2461959906, "write_bytes": 1097593899, "bytes_per_launch": 3559553805},
     {"kernel": "ex2", "workload": "batched_flat", "scheme": "explicit",
      "sources": ["hsgn_kernels.hpp", "hsgn_explicit.hpp"], "hash": "2e6dc71f10ea1fd9",
      "fetch_bytes": 2232887832, "write_bytes": 1118343168, "bytes_per_launch": 3351231000},
@@ -40,6 +44,10 @@ TRAFFIC = [
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp",
                  "hsgn_explicit.hpp", "hsgn_sgn.hpp"], "hash": "750031ac7d6becb8",
      "fetch_bytes": 676269416, "write_bytes": 273330176, "bytes_per_launch": 949599592},
+    {"kernel": "sgn_solve", "workload": "batched_flat", "scheme": "sgn", "halo_margin": 1.0,
+     "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp",
+                 "hsgn_explicit.hpp", "hsgn_sgn.hpp"], "hash": "750031ac7d6becb8",
+     "fetch_bytes": 646755101, "write_bytes": 273320395, "bytes_per_launch": 920075496},
 ]
 
 def src_hash(sources):
