@@ -859,7 +859,14 @@ int run_retrying(hsgn_ctx* c, Chunk chunk) {
   if (!c->halo_retry || c->scheme == HSGN_SCHEME_EXPLICIT) return chunk();
   const size_t nc = (size_t)c->ncell, ni = (size_t)c->n_inst;
   int rc = HSGN_OK;
-  if (!c->rb_state) {
+  if (!c->rb_state || !c->rb_t || !c->rb_sp || !c->rb_st) {  // first use, or a failed one
+    void* old[4] = {c->rb_state, c->rb_t, c->rb_sp, c->rb_st};
+    for (void* q : old)
+      if (q) (void)hipFree(q);
+    c->rb_state = nullptr;
+    c->rb_t = nullptr;
+    c->rb_sp = nullptr;
+    c->rb_st = nullptr;
     rc = dmalloc(c, &c->rb_state, 4 * nc);
     if (!rc) rc = dmalloc(c, &c->rb_t, ni);
     if (!rc) rc = dmalloc(c, &c->rb_sp, 3 * ni);
