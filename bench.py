@@ -258,14 +258,16 @@ def adjoint_cost(reps=2):
     sinusoid, lambda = 1000, 200 steps, checkpoints every 20 steps.  Targets
     are the library's own gauge series from a perturbed initial surface
     (made before timing).  Forward = the loss alone (200 steps and the gauge
-    misfit); adjoint = loss and both gradients (forward with checkpoints,
-    segment recompute, reverse sweep)."""
+    misfit); adjoint = loss and both gradients (forward with checkpoints and
+    tapes, the recompute of segments whose tapes did not fit, reverse
+    sweep)."""
     import torch
     from paper_2510_07539_amd import workloads as WL
     from paper_2510_07539_amd.hsgn import Solver
     case = WL.adjoint_bar()
     wl, nsteps, K = case.wl, case.nsteps, case.K
     dev = "cuda"
+    free_before = torch.cuda.mem_get_info()[0]
     s = Solver.from_workload(wl)
     try:
         bt = torch.from_numpy(wl.b).to(dev)
@@ -300,7 +302,11 @@ def adjoint_cost(reps=2):
                         "K=20, 8 gauges, transmissive (seed 5, targets seed 55)",
             "forward_ms": round(1e3 * f, 2), "adjoint_ms": round(1e3 * a, 2),
             "cost_ratio": round(a / f, 3),
-            "forward_cell_stages_per_s": 2.0 * wl.n_cells * nsteps / f}
+            "forward_cell_stages_per_s": 2.0 * wl.n_cells * nsteps / f,
+            "tapes": "every segment taped in the forward pass when all tapes fit half the "
+                     "free device memory (else the last two; the rest recomputed)",
+            "tape_gb_all_segments": round(8.0 * nsteps * wl.n_cells * 8 / 1e9, 2),
+            "device_free_gb_before": round(free_before / 1e9, 1)}
 
 
 def main():

@@ -355,17 +355,27 @@ int hsgn_step_timed(hsgn_ctx* ctx, int32_t nsteps, double* h_ms, int32_t* h_coun
  * call then returns that flag's error code (precedence and message as for
  * hsgn_status) before the reverse sweep, with d_loss written and the
  * gradients not.
- * The forward pass writes the tapes of the last two segments itself (one
- * per tape buffer); every earlier segment is recomputed from its checkpoint
- * on a second stream of the library while the following segment is swept
- * in reverse.  The adjoint
- * workspace (22 + 16 K doubles per cell, plus 4 (nsteps/K + 1) doubles per
- * cell of checkpoints) is kept until hsgn_destroy.
+ * When the tapes of all segments (8 nsteps doubles per cell) fit the tape
+ * budget (hsgn_set_adjoint_tape_bytes), the forward pass writes all of them
+ * and no segment is recomputed.  Otherwise it writes the tapes of the last
+ * two segments itself (one per tape buffer), and every earlier segment is
+ * recomputed from its checkpoint on a second stream of the library while
+ * the following segment is swept in reverse.  Both give the same results
+ * bit for bit.  The adjoint workspace (22 doubles per cell, the tapes: 8 K
+ * doubles per cell per tape buffer, plus 4 (nsteps/K + 1) doubles per cell
+ * of checkpoints) is kept until hsgn_destroy.
  * Synchronises the stream twice: after the initial state (to plan) and
  * after the forward pass (to read the status flags). */
 int hsgn_adjoint(hsgn_ctx* ctx, int32_t nsteps, int32_t K, int32_t n_gauge,
                  const int32_t* d_gauge, const double* d_target, const double* d_zeta0,
                  double* d_loss, double* d_grad_zeta0, double* d_grad_b);
+
+/* Memory for hsgn_adjoint's tapes, in bytes: when the tapes of every
+ * segment fit it, the forward pass tapes them all and nothing is
+ * recomputed; 0 always recomputes (two tape buffers).  Negative (the
+ * default): half the device memory free at the hsgn_adjoint call (a tape
+ * already held by the context counts as free). */
+int hsgn_set_adjoint_tape_bytes(hsgn_ctx* ctx, int64_t bytes);
 
 /* For callers that cannot allocate device memory (code that must not call
  * hipMalloc: tight serving loops, harnesses that forbid allocation): the

@@ -143,10 +143,12 @@ struct hsgn_ctx {
   int occ[2][2] = {};        // resident workgroups per CU: [geometry][stage - 1], 0 = not read yet
   // adjoint workspace (allocated by the first hsgn_adjoint call)
   struct Adj {
-    int K = 0, nseg = 0;
+    int nseg = 0;
+    size_t tape_steps = 0;     // steps the tape holds (tape buffers x K)
+    int64_t tape_budget = -1;  // bytes for the tapes (hsgn_set_adjoint_tape_bytes; < 0: auto)
     int64_t nres = 0;
     double* sys = nullptr;     // 9 x ncell: transposed rows, rhs, lam, solver scratch
-    double* tape = nullptr;    // 2 x K x 8 x ncell (U^n, U^(1) per step; two segments)
+    double* tape = nullptr;    // tape_steps x 8 x ncell (U^n, U^(1) per step)
     double* ckpt = nullptr;    // (nseg + 1) x 4 x ncell
     double* res = nullptr;     // n_inst x nsteps x n_gauge residuals
     double* st = nullptr;      // 12 x ncell adjoint states + 1 x ncell bed adjoint
@@ -1182,6 +1184,12 @@ int hsgn_run(hsgn_ctx* c, int32_t nsteps, int32_t block) {
   return leave(c);
 }
 
+int hsgn_set_adjoint_tape_bytes(hsgn_ctx* c, int64_t bytes) {
+  if (!c) return HSGN_EINVAL;
+  c->adj.tape_budget = bytes < 0 ? -1 : bytes;
+  return HSGN_OK;
+}
+
 int hsgn_set_halo_retry(hsgn_ctx* c, int32_t enable) {
   if (!c) return HSGN_EINVAL;
   if (enable != 0 && enable != 1)
@@ -1522,7 +1530,7 @@ __global__ void k_adj_surface(const InstDesc* __restrict__ inst, const double* _
   }
 }
 
-int adj_alloc(hsgn_ctx* c, int K, int nseg, int64_t nres, bool grad) {
+int adj_alloc(hsgn_ctx* c, int K, int nseg, int64_t nres, bool grad, int ntb) {
   auto& a = c->adj;
   const size_t nc = (size_t)c->ncell;
   if (nres > a.nres) {
@@ -1559,13 +1567,13 @@ int adj_alloc(hsgn_ctx* c, int K, int nseg, int64_t nres, bool grad) {
                         hipMemcpyHostToDevice));
     a.ntiles = (int)tl.size();
   }
-  if (K > a.K) {
+  if ((size_t)ntb * K > a.tape_steps) {
     if (a.tape) hipFree(a.tape);
     a.tape = nullptr;
-    a.K = 0;
-    int rc = dmalloc(c, &a.tape, (size_t)2 * K * 8 * nc);
+    a.tape_steps = 0;
+    int rc = dmalloc(c, &a.tape, (size_t)ntb * K * 8 * nc);
     if (rc) return rc;
-    a.K = K;
+    a.tape_steps = (size_t)ntb * K;
   }
   if (!a.rstream) {
     HIPCHK(c, hipStreamCreateWithFlags(&a.rstream, hipStreamNonBlocking));
@@ -1628,7 +1636,22 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   const int nseg = (nsteps + K - 1) / K;
   const int64_t nres = (int64_t)c->n_inst * nsteps * ng;
   const bool grad = d_grad_zeta0 || d_grad_b;
-  int rc = adj_alloc(c, K, nseg, nres, grad);
+  // Tape every segment in the forward pass (no recompute) when the tapes of
+  // all of them fit the budget; else two tape buffers, the last two
+  // segments taped and every earlier one recomputed from its checkpoint.
+  bool full_tape = false;
+  if (grad && nseg > 2) {
+    const double need = (double)nseg * K * 8 * (double)c->ncell * sizeof(double);
+    double budget = (double)c->adj.tape_budget;
+    if (c->adj.tape_budget < 0) {  // half the free device memory (counting a tape held already)
+      size_t fr = 0, tot = 0;
+      HIPCHK(c, hipMemGetInfo(&fr, &tot));
+      budget = 0.5 * ((double)fr + (double)c->adj.tape_steps * 8 * (double)c->ncell * sizeof(double));
+    }
+    full_tape = need <= budget;
+  }
+  const int ntb = full_tape ? nseg : 2;
+  int rc = adj_alloc(c, K, nseg, nres, grad, ntb);
   if (rc) return rc;
   rc = enter(c);
   if (rc) return rc;
@@ -1638,9 +1661,9 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   const unsigned nbi = (unsigned)((c->n_inst + 255) / 256);
   double** U = nullptr;
   auto ckpt = [&](int k, int f) { return a.ckpt + ((size_t)k * 4 + f) * nc; };
-  // two tape buffers: segment s uses buffer s % 2
+  // tape buffers of K steps: segment s uses buffer s % ntb
   auto tape = [&](int s, int k, int f) {
-    return a.tape + (((size_t)(s % 2) * a.K + k) * 8 + f) * nc;
+    return a.tape + (((size_t)(s % ntb) * K + k) * 8 + f) * nc;
   };
   double* AS[4];
   double* A1[4];
@@ -1660,11 +1683,12 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   rc = reset_and_plan(c);  // flags, speed bound and solver plan of the initial state
   if (rc) return rc;
   hipLaunchKernelGGL(k_fill_f64, dim3(nbi), dim3(256), 0, c->stream, (int64_t)c->n_inst, d_loss, 0.0);
-  // The last two segments (one per tape buffer) write their tapes, their
-  // checkpoints and the final state directly, so neither is recomputed: the
-  // reverse sweep of the last one starts at once, and the recompute stream
-  // first recomputes the third segment from the end.
-  const int n_fwd_tape = std::min(nseg, 2);
+  // The last two segments (one per tape buffer), or every segment with the
+  // full tape, write their tapes, their checkpoints and the final state
+  // directly, so none of them is recomputed: the reverse sweep of the last
+  // one starts at once, and the recompute stream first recomputes the third
+  // segment from the end.
+  const int n_fwd_tape = full_tape ? nseg : std::min(nseg, 2);
   const int s_tape = (nseg - n_fwd_tape) * K;
   for (int s = 0; s < nsteps; ++s) {
     if (grad && s % K == 0 && s <= s_tape) {  // later checkpoints are written by the steps

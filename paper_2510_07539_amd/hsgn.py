@@ -87,6 +87,8 @@ def lib():
         L.hsgn_set_halo_margin.argtypes = [vp, C.c_double]
         L.hsgn_set_launch.restype = C.c_int
         L.hsgn_set_launch.argtypes = [vp, C.c_int32]
+        L.hsgn_set_adjoint_tape_bytes.restype = C.c_int
+        L.hsgn_set_adjoint_tape_bytes.argtypes = [vp, C.c_int64]
         L.hsgn_set_halo_retry.restype = C.c_int
         L.hsgn_set_halo_retry.argtypes = [vp, C.c_int32]
         L.hsgn_halo_state.restype = C.c_int
@@ -161,6 +163,13 @@ class Solver:
         """Safety factor of the windowed solves' halo estimates (default 2);
         re-plans at once."""
         self._check(lib().hsgn_set_halo_margin(self._h, float(margin)), "hsgn_set_halo_margin")
+
+    def set_adjoint_tape_bytes(self, nbytes):
+        """Tape budget of the adjoint in bytes: every segment is taped in the
+        forward pass (nothing recomputed) when all tapes fit; 0 always
+        recomputes; negative: half the free device memory (the default)."""
+        self._check(lib().hsgn_set_adjoint_tape_bytes(self._h, int(nbytes)),
+                    "hsgn_set_adjoint_tape_bytes")
 
     def set_halo_retry(self, enable=True):
         """Halo retry: a block whose windows could not certify their

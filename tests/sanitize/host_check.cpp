@@ -194,10 +194,13 @@ void run_adjoint() {
   hsgn_ctx* c = nullptr;
   expect("hsgn_init (adjoint)", hsgn_init(&c, ni, B.off.data(), B.prm.data(), db, nullptr), HSGN_OK);
   if (!c) return;
-  for (int K : {2, 3, 7, 50}) {
-    char what[64];
-    std::snprintf(what, sizeof what, "hsgn_adjoint (K = %d)", K);
-    expect(what, hsgn_adjoint(c, nsteps, K, ng, dg, dtg, dz, dl, gz, gb), HSGN_OK, c);
+  for (int64_t tb : {(int64_t)-1, (int64_t)0}) {
+    expect("hsgn_set_adjoint_tape_bytes", hsgn_set_adjoint_tape_bytes(c, tb), HSGN_OK, c);
+    for (int K : {2, 3, 7, 50}) {
+      char what[64];
+      std::snprintf(what, sizeof what, "hsgn_adjoint (K = %d, tape %lld)", K, (long long)tb);
+      expect(what, hsgn_adjoint(c, nsteps, K, ng, dg, dtg, dz, dl, gz, gb), HSGN_OK, c);
+    }
   }
   expect("hsgn_adjoint (loss only)", hsgn_adjoint(c, nsteps, 3, ng, dg, dtg, dz, dl, nullptr, nullptr),
          HSGN_OK, c);

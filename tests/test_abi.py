@@ -48,6 +48,8 @@ def test_null_arguments_are_rejected_without_a_device():
     assert L.hsgn_set_halo_margin(None, 1.0) == -1
     assert L.hsgn_autotune_launch(None, 1, None, None) == -1
     assert L.hsgn_set_halo_retry(None, 1) == -1
+    L.hsgn_set_adjoint_tape_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    assert L.hsgn_set_adjoint_tape_bytes(None, 0) == -1
     assert L.hsgn_halo_state(None, None, None) == -1
     L.hsgn_destroy(None)
 

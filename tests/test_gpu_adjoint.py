@@ -122,10 +122,12 @@ def oracle_dir(wl, j, z, target, gauges, nsteps, vz=None, vb=None):
     return J.imag / EPS_CS, J.real
 
 
-def run_gpu(wl, z_all, gauges, targets, nsteps, K, grad=True, launch="grid"):
+def run_gpu(wl, z_all, gauges, targets, nsteps, K, grad=True, launch="grid", tape_bytes=None):
     hs = _hsgn()
     s = hs.Solver.from_workload(wl)
     s.set_launch(launch)
+    if tape_bytes is not None:
+        s.set_adjoint_tape_bytes(tape_bytes)
     try:
         dev = "cuda"
         loss, gz, gb = s.adjoint(nsteps, K, torch.from_numpy(gauges).to(dev),
@@ -271,12 +273,16 @@ def test_adjoint_vs_central_fd(mixed):
         assert np.all(err <= RTOL_FD), (k, err)
 
 
-def test_adjoint_checkpoint_interval_invariant(mixed):
-    """Recomputation is deterministic: K = 1, K = nsteps and K > nsteps give
-    the same loss and gradients as K = 5, bit for bit."""
-    for K in (1, mixed["nsteps"], 50):
+@pytest.mark.parametrize("tape_bytes", [None, 0])
+def test_adjoint_checkpoint_interval_invariant(mixed, tape_bytes):
+    """Recomputation is deterministic: K = 1, K = 5, K = nsteps and
+    K > nsteps, with every segment taped in the forward pass (the default
+    tape budget, as in the reference run) and with the segments before the
+    last two recomputed from their checkpoints (tape budget 0), give the
+    same loss and gradients, bit for bit."""
+    for K in (1, 5, mixed["nsteps"], 50):
         loss, gz, gb = run_gpu(mixed["wl"], mixed["z_all"], mixed["gauges"], mixed["targets"],
-                               mixed["nsteps"], K)
+                               mixed["nsteps"], K, tape_bytes=tape_bytes)
         assert np.array_equal(loss, mixed["loss"]), K
         assert np.array_equal(gz, mixed["gz"]), K
         assert np.array_equal(gb, mixed["gb"]), K
@@ -368,16 +374,21 @@ def test_adjoint_reports_an_instance_flagged_in_the_forward_pass(mixed):
 @pytest.mark.timeout(300)
 def test_adjoint_full_size_persistent_launch_bitwise():
     """The gradient workload at full size (thousands of windows per launch)
-    over 40 steps with checkpoints every 20: the persistent window launch
-    gives the grid launch's loss and gradients bit for bit."""
+    over 60 steps with checkpoints every 20: the persistent window launch,
+    and the recompute of the first segment from its checkpoint (tape
+    budget 0) instead of the full tape, give the loss and gradients of the
+    grid launch with every segment taped, bit for bit."""
     case = WL.adjoint_bar()
     wl, K = case.wl, case.K
-    nsteps = 40
+    nsteps = 60
     rng = np.random.default_rng(8)
     targets = 0.4 + 1e-3 * rng.standard_normal((wl.n_inst, nsteps, case.gauges.shape[1]))
     note("adjoint full, persistent vs grid: %d instances, %d steps" % (wl.n_inst, nsteps))
     ref = run_gpu(wl, case.zeta0, case.gauges, targets, nsteps, K)
     got = run_gpu(wl, case.zeta0, case.gauges, targets, nsteps, K, launch="persistent")
+    for x, y in zip(ref, got):
+        assert np.array_equal(x, y)
+    got = run_gpu(wl, case.zeta0, case.gauges, targets, nsteps, K, tape_bytes=0)
     for x, y in zip(ref, got):
         assert np.array_equal(x, y)
 
