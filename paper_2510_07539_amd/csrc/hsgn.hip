@@ -1650,9 +1650,15 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
     }
     full_tape = need <= budget;
   }
-  const int ntb = full_tape ? nseg : 2;
-  int rc = adj_alloc(c, K, nseg, nres, grad, ntb);
+  int rc = adj_alloc(c, K, nseg, nres, grad, full_tape ? nseg : 2);
+  if (rc == HSGN_ENOMEM && full_tape) {  // the full tape did not fit after all
+    full_tape = false;
+    (void)hipGetLastError();
+    c->err.clear();
+    rc = adj_alloc(c, K, nseg, nres, grad, 2);
+  }
   if (rc) return rc;
+  const int ntb = full_tape ? nseg : 2;
   rc = enter(c);
   if (rc) return rc;
   auto& a = c->adj;
