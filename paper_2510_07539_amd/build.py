@@ -25,6 +25,11 @@ HIPCC_FLAGS = [
 ]
 
 
+# roctx ranges and marks of the entry points (rocprofv3 --marker-trace)
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+LINK_FLAGS = ["-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx"]
+
+
 def build(verbose: bool = False) -> str:
     """Compile libhsgn.so (always recompiles)."""
     tmp = LIB + ".tmp%d" % os.getpid()
@@ -32,7 +37,7 @@ def build(verbose: bool = False) -> str:
     inc = "-I" + os.path.join(ROOT, "include")
     flags = [f for f in HIPCC_FLAGS if f != "-shared"]
     cmds = [["hipcc", *flags, *PERSIST_FLAGS, inc, "-c", SRC_PERSIST, "-o", obj],
-            ["hipcc", *HIPCC_FLAGS, inc, SRC, "-x", "none", obj, "-o", tmp]]
+            ["hipcc", *HIPCC_FLAGS, inc, SRC, "-x", "none", obj, *LINK_FLAGS, "-o", tmp]]
     try:
         for cmd in cmds:
             if verbose:

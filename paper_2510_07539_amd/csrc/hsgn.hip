@@ -23,6 +23,8 @@
 
 #include <cmath>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "hsgn.h"
 #include "hsgn_kernels.hpp"
 #include "hsgn_window.hpp"
@@ -51,6 +53,16 @@ struct GraphEntry {
   int block;
   int cur;
   hipGraphExec_t exec;
+};
+
+// A roctx range over a scope of host code (the entry points, graph blocks,
+// adjoint phases): shown by rocprofv3 --marker-trace, and a no-op call when
+// no tool is attached.
+struct Range {
+  explicit Range(const char* what) { roctxRangePushA(what); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
 };
 
 }  // namespace
@@ -893,6 +905,7 @@ int run_retrying(hsgn_ctx* c, Chunk chunk) {
     if (rc) return rc;
     c->halo_margin = std::min(kMaxMargin, 2.0 * c->halo_margin);
     ++c->n_retry;
+    roctxMarkA("hsgn halo retry: block runs again with twice the margin");
     rc = make_plan(c);
     if (rc) return rc;
   }
@@ -927,6 +940,7 @@ int hsgn_init(hsgn_ctx** out, int32_t n_inst, const int64_t* offsets, const hsgn
       hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
       if (e != hipSuccess) rc = fail(c, HSGN_EHIP, "hipStreamCreate: %s", hipGetErrorString(e));
       c->own_stream = rc == HSGN_OK;
+      if (c->own_stream) roctxNameHipStream("hsgn", c->stream);
     }
   }
   if (rc == HSGN_OK) {
@@ -1147,6 +1161,7 @@ int hsgn_plan_info(hsgn_ctx* c, int32_t* h_mode, int32_t* h_halo, int32_t* h_cou
 
 int hsgn_step(hsgn_ctx* c, int32_t nsteps) {
   if (!c) return HSGN_EINVAL;
+  Range range("hsgn_step");
   if (nsteps < 0) return fail(c, HSGN_EINVAL, "hsgn_step: nsteps < 0");
   int rc = enter(c);
   if (rc) return rc;
@@ -1161,6 +1176,7 @@ int hsgn_step(hsgn_ctx* c, int32_t nsteps) {
 
 int hsgn_run(hsgn_ctx* c, int32_t nsteps, int32_t block) {
   if (!c) return HSGN_EINVAL;
+  Range range("hsgn_run");
   if (nsteps < 0 || block < 1) return fail(c, HSGN_EINVAL, "hsgn_run: bad nsteps/block");
   if (block & 1) block += 1;  // the buffer rotation repeats every 2 steps
   int rc = enter(c);
@@ -1168,6 +1184,7 @@ int hsgn_run(hsgn_ctx* c, int32_t nsteps, int32_t block) {
   int done = 0;
   for (; done + block <= nsteps && rc == HSGN_OK; done += block)
     rc = run_retrying(c, [&]() {
+      Range block_range("hsgn_run graph block");
       hipGraphExec_t exec = nullptr;
       int r = graph_of(c, block, &exec);
       if (r == HSGN_OK) HIPCHK(c, hipGraphLaunch(exec, c->stream));
@@ -1367,6 +1384,7 @@ extern "C" {
 // Autotuner: time the three uniform solver modes and keep the fastest.
 int hsgn_autotune(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_mode) {
   if (!c) return HSGN_EINVAL;
+  Range range("hsgn_autotune");
   if (nsteps < 1) return fail(c, HSGN_EINVAL, "hsgn_autotune: nsteps < 1");
   if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
     return fail(c, HSGN_EINVAL, "hsgn_autotune: the tuner times the semi-implicit step only");
@@ -1437,6 +1455,7 @@ int hsgn_set_launch(hsgn_ctx* c, int32_t launch) {
 // Time the two window-stage launches on the current plan and keep the faster.
 int hsgn_autotune_launch(hsgn_ctx* c, int32_t nsteps, double* h_ms, int32_t* h_launch) {
   if (!c) return HSGN_EINVAL;
+  Range range("hsgn_autotune_launch");
   if (nsteps < 1) return fail(c, HSGN_EINVAL, "hsgn_autotune_launch: nsteps < 1");
   if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
     return fail(c, HSGN_EINVAL, "hsgn_autotune_launch: the window launch of the semi-implicit step only");
@@ -1577,6 +1596,7 @@ int adj_alloc(hsgn_ctx* c, int K, int nseg, int64_t nres, bool grad, int ntb) {
   }
   if (!a.rstream) {
     HIPCHK(c, hipStreamCreateWithFlags(&a.rstream, hipStreamNonBlocking));
+    roctxNameHipStream("hsgn adjoint recompute", a.rstream);
     HIPCHK(c, hipEventCreateWithFlags(&a.ev_fwd, hipEventDisableTiming));
     for (int i = 0; i < 2; ++i) {
       HIPCHK(c, hipEventCreateWithFlags(&a.ev_rec[i], hipEventDisableTiming));
@@ -1608,6 +1628,7 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
                             const double* d_zeta0, double* d_loss, double* d_grad_zeta0,
                             double* d_grad_b) {
   if (!c) return HSGN_EINVAL;
+  Range range("hsgn_adjoint");
   if (nsteps < 1 || K < 1 || ng < 1 || !d_gauge || !d_target || !d_zeta0 || !d_loss)
     return fail(c, HSGN_EINVAL, "hsgn_adjoint: bad arguments");
   if (c->order != 2 || c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)
@@ -1682,6 +1703,8 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   double* GB = a.st + (size_t)12 * nc;
 
   // ---- forward: initial state from the surface, checkpoints, loss
+  roctxMarkA(full_tape ? "hsgn_adjoint forward pass (every segment taped)"
+                       : "hsgn_adjoint forward pass (the last two segments taped)");
   U = c->buf[c->cur];
   hipLaunchKernelGGL(k_state_from_surface, dim3(nbc), dim3(256), 0, c->stream, c->ncell, d_zeta0,
                      c->d_b, U[0], U[1], U[2], U[3]);
@@ -1734,6 +1757,7 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   }
   // (the final state is in checkpoint nseg; it is restored at the end)
   // ---- reverse
+  roctxMarkA("hsgn_adjoint reverse sweep");
   for (int f = 0; f < 4; ++f)
     hipLaunchKernelGGL(k_fill_f64, dim3(nbc), dim3(256), 0, c->stream, (int64_t)c->ncell, AS[f], 0.0);
   hipLaunchKernelGGL(k_fill_f64, dim3(nbc), dim3(256), 0, c->stream, (int64_t)c->ncell, GB, 0.0);
@@ -1939,6 +1963,7 @@ extern "C" int hsgn_autotune_classes(hsgn_ctx* c, int32_t nsteps, int32_t max_cl
                                      int32_t* h_nclass, int32_t* h_class_of, int32_t* h_keys,
                                      double* h_ms, int32_t* h_kept, double* h_whole) {
   if (!c) return HSGN_EINVAL;
+  Range range("hsgn_autotune_classes");
   if (nsteps < 1 || max_classes < 1 || !h_nclass)
     return fail(c, HSGN_EINVAL, "hsgn_autotune_classes: bad arguments");
   if (c->scheme != HSGN_SCHEME_SEMI_IMPLICIT)

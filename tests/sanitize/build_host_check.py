@@ -31,7 +31,7 @@ def build(verbose: bool = False) -> str:
     inc = "-I" + os.path.join(ROOT, "include")
     flags = [f for f in B.HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
     cmds = [["hipcc", *flags, *SAN, *B.PERSIST_FLAGS, inc, "-c", B.SRC_PERSIST, "-o", obj],
-            ["hipcc", *flags, *SAN, inc, DRIVER, B.SRC, "-x", "none", obj, "-o", tmp]]
+            ["hipcc", *flags, *SAN, inc, DRIVER, B.SRC, "-x", "none", obj, *B.LINK_FLAGS, "-o", tmp]]
     try:
         for cmd in cmds:
             if verbose:
