@@ -1703,8 +1703,9 @@ extern "C" int hsgn_adjoint(hsgn_ctx* c, int32_t nsteps, int32_t K, int32_t ng,
   double* GB = a.st + (size_t)12 * nc;
 
   // ---- forward: initial state from the surface, checkpoints, loss
-  roctxMarkA(full_tape ? "hsgn_adjoint forward pass (every segment taped)"
-                       : "hsgn_adjoint forward pass (the last two segments taped)");
+  roctxMarkA(!grad       ? "hsgn_adjoint forward pass (loss only)"
+             : full_tape ? "hsgn_adjoint forward pass (every segment taped)"
+                         : "hsgn_adjoint forward pass (the last two segments taped)");
   U = c->buf[c->cur];
   hipLaunchKernelGGL(k_state_from_surface, dim3(nbc), dim3(256), 0, c->stream, c->ncell, d_zeta0,
                      c->d_b, U[0], U[1], U[2], U[3]);
