@@ -1,0 +1,107 @@
+"""Failure detection, forced on the CPU.
+
+The oracle (the checker of every GPU parity test) must report each failure
+the library flags: a non-positive depth in the initial state, a NaN in the
+bed (OR_ENONPHYS), and the loss of coercivity beta <= 0 (OR_ENONCOERCIVE)
+on instance 84 of the batched bar at step 368, the case the GPU test
+test_coercivity_loss_flagged_at_the_oracle_step checks the library against.
+Invalid instances (lambda <= 0, dx <= 0, an unknown boundary type, fewer
+than 4 cells, orders or schemes that differ between instances, a bed for
+the explicit scheme, a bed flag without bed data) are refused by the
+library's hsgn_init before it touches the GPU.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2510_07539_amd import workloads as WL
+
+
+def _smooth(n=64, dx=0.25, h0=1.0):
+    x = (np.arange(n) + 0.5) * dx
+    h = h0 + 0.1 * np.exp(-((x - 0.5 * n * dx) / (0.1 * n * dx)) ** 2)
+    q = 0.2 * h
+    return x, [h, q, h * h, np.zeros(n)]
+
+
+def test_oracle_negative_depth_in_the_initial_state():
+    _, U = _smooth()
+    U[0][17] = -1e-3
+    U[2][17] = U[0][17] ** 2
+    p = O.make_params(dx=0.25, bc=O.BC_PERIODIC)
+    rc, _, _ = O.run(p, None, U, 0.0, 1)
+    assert rc == O.ENONPHYS
+
+
+def test_oracle_nan_in_the_bed():
+    x, U = _smooth()
+    b = 0.05 * np.sin(2 * np.pi * x / x[-1])
+    p = O.make_params(dx=0.25, bc=O.BC_TRANSMISSIVE, has_b=1)
+    rc, _, _ = O.run(p, b, U, 0.0, 1)
+    assert rc == O.OK
+    b[30] = np.nan
+    rc, _, _ = O.run(p, b, U, 0.0, 1)
+    assert rc == O.ENONPHYS
+
+
+@pytest.mark.slow
+def test_oracle_coercivity_loss_of_bar_instance_84():
+    wl = WL.batched_bar().subset([84], name="bar-84")
+    n, prm, b, U0 = wl.instance(0)
+    p = O.make_params(**prm)
+    rc, _, _ = O.run(p, b, U0, 0.0, 367)
+    assert rc == O.OK
+    rc, _, _ = O.run(p, b, U0, 0.0, 368)
+    assert rc == O.ENONCOERCIVE
+
+
+def _init(sizes, params, with_bed=False):
+    """hsgn_init on the host arguments only (it validates before any HIP
+    call); returns its code."""
+    from paper_2510_07539_amd.hsgn import HsgnParams, lib
+    L = lib()
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    arr = (HsgnParams * len(params))(*params)
+    ctx = ctypes.c_void_p()
+    bed = ctypes.c_void_p(1) if with_bed else None  # never dereferenced: validation fails first
+    return L.hsgn_init(ctypes.byref(ctx), len(sizes),
+                       offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), arr, bed, None)
+
+
+def _p(**kw):
+    from paper_2510_07539_amd.hsgn import HsgnParams
+    d = dict(g=9.81, lam=100.0, dx=0.1, cfl=0.9, mcfl=0.5, dt_fixed=0.0, t_end=0.0, bc=1,
+             has_bathymetry=0, order=2, scheme=0)
+    d.update(kw)
+    s = HsgnParams()
+    for name, _ in HsgnParams._fields_:
+        setattr(s, name, d[name])
+    return s
+
+
+@pytest.mark.parametrize("case", ["lambda<0", "lambda=0", "dx=0", "bc", "3 cells", "orders",
+                                  "schemes", "explicit bed", "bed without b"])
+def test_library_init_rejects_invalid_instances(case):
+    sizes, ps, bed = [64, 64], [_p(), _p()], False
+    if case == "lambda<0":
+        ps[1] = _p(lam=-1.0)
+    elif case == "lambda=0":
+        ps[0] = _p(lam=0.0)
+    elif case == "dx=0":
+        ps[1] = _p(dx=0.0)
+    elif case == "bc":
+        ps[0] = _p(bc=5)
+    elif case == "3 cells":
+        sizes = [64, 3]
+    elif case == "orders":
+        ps[1] = _p(order=1)
+    elif case == "schemes":
+        ps[1] = _p(scheme=1)
+    elif case == "explicit bed":
+        ps = [_p(scheme=1, has_bathymetry=1), _p(scheme=1, has_bathymetry=1)]
+        bed = True
+    elif case == "bed without b":
+        ps[0] = _p(has_bathymetry=1)
+    assert _init(sizes, ps, with_bed=bed) == -1  # HSGN_EINVAL

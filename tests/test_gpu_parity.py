@@ -852,6 +852,30 @@ def test_halo_retry_recovers_short_halos(scheme):
         s.close()
 
 
+@pytest.mark.parametrize("scheme", [0, SGNS])
+def test_two_runs_bitwise_identical(scheme):
+    """Determinism: the same workload in two fresh contexts gives the same
+    state bit for bit (no floating-point atomics: only the speed and depth
+    maxima use atomics, on their bit patterns, which is order-independent),
+    with windows of both widths in one batch."""
+    Solver = _solver()
+    if scheme == SGNS:
+        wl = WL.batched_flat(n_inst=24, seed=31, n_lo=513, n_hi=12000)
+    else:
+        wl = WL.batched_bar(n_inst=24, seed=31, n_lo=513, n_hi=12000)
+    out = []
+    for _ in range(2):
+        s = Solver.from_workload(wl, scheme=scheme)
+        s.run(30, block=10)
+        out.append(s.get_state())
+        assert s.status()[0] == 0
+        s.close()
+    (a, ta), (b, tb) = out
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    assert torch.equal(ta, tb)
+
+
 def test_sgn_graph_replay_equals_eager_and_t_end():
     Solver = _solver()
     wl = _sgn_mix()
