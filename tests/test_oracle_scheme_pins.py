@@ -9,9 +9,10 @@
   momentum right-hand side (the mass flux uses the implicitly updated
   momentum, Sec. 3.1 eq. hSGN_eq-split-I); it pins the face force of the
   depth system, bed terms included, which the tau -> 0 limit cannot see.
-- Linear stability at rest of one two-stage step (the survey's rest-state
-  check; it is what fixes the Rusanov speed |u| + sqrt(g h) over the
-  printed |u|): spectral radius of the step's Jacobian, by complex steps.
+- Linear stability at rest of one two-stage step (still water on a small
+  periodic mesh; it is what fixes the Rusanov speed |u| + sqrt(g h) over
+  the printed |u|): spectral radius of the step's Jacobian, by complex
+  steps.
 - Mode A, the printed lines of Sec. 4.2 (eq. GN_hyp_eq_semi_fully_discrete),
   against the P-form the oracle and the library use: same limit, difference
   O(dx^2) on the solitary wave at lambda = 100; mode A breaks down at
@@ -150,7 +151,7 @@ def rest_spectral_radius(lam, N, dx, h0, bc, bed=False, cfl=0.9):
 
 
 STABLE_CASES = [
-    # (lam, N, dx, h0, bc, bed): the survey's rest-state setting (h0 = 1,
+    # (lam, N, dx, h0, bc, bed): still water on a small mesh (h0 = 1,
     # dx = 0.25), the bar of the batched and gradient workloads
     # (transmissive, dx = 0.04), and the long periodic mesh (h0 = 1, dx = 0.01)
     (1e2, 32, 0.25, 1.0, 0, False),
