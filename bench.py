@@ -523,7 +523,8 @@ def main():
                    "launch": launch, "launch_ms_per_step": launch_ms,
                    "halo_margin": None if args.scheme == "explicit" else args.halo_margin,
                    "halo_retry": bool(args.halo_retry) and args.scheme != "explicit",
-                   "halo_margin_final": None if args.scheme == "explicit" else s.halo_state()[0],
+                   "halo_margin_max_final": (None if args.scheme == "explicit"
+                                             else float(s.halo_state()[0].max())),
                    "timed_legs_blocks_run_again": leg_retries,
                    "windows": plan["windows"], "window_rows": plan["window_rows"],
                    "two_pass_tiles": plan["exact_tiles"]},

@@ -254,17 +254,19 @@ int hsgn_set_halo_margin(hsgn_ctx* ctx, double margin);
  * status and step counts: 4 doubles per cell, allocated on first use and
  * kept until hsgn_destroy), then read the status flags, which synchronises
  * the stream.  If a windowed solve flagged its truncation
- * (HSGN_FLAG_WINDOW), the copy is restored, the halo margin doubled (at
- * most 64; it keeps the new value), the solver re-planned and the block run
- * again, so every window of the result certifies its truncation as with
- * the default margin.  Other flags, and a window flag at margin 64, are
- * left for hsgn_status.  No effect with the explicit scheme (no windows).
- * The windowed solves of hsgn_adjoint do not retry. */
+ * (HSGN_FLAG_WINDOW), the copy is restored, the halo margin of every
+ * flagged instance doubled (at most 64; the instance keeps its new margin,
+ * the others keep theirs), the solver re-planned and the block run again,
+ * so every window of the result certifies its truncation as with the
+ * default margin.  Other flags, and a window flag at margin 64, are left
+ * for hsgn_status.  hsgn_set_halo_margin resets the per-instance margins.
+ * No effect with the explicit scheme (no windows).  The windowed solves of
+ * hsgn_adjoint do not retry. */
 int hsgn_set_halo_retry(hsgn_ctx* ctx, int32_t enable);
 
-/* Current halo margin (h_margin, host, or NULL) and the number of blocks
- * run again by the halo retry since the state was loaded (h_retries, host,
- * or NULL). */
+/* Current halo margin of every instance (h_margin, host, n_inst doubles, or
+ * NULL) and the number of blocks run again by the halo retry since the
+ * state was loaded (h_retries, host, or NULL). */
 int hsgn_halo_state(hsgn_ctx* ctx, double* h_margin, int32_t* h_retries);
 
 /* Launch of the window stages:

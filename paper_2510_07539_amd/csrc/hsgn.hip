@@ -143,6 +143,7 @@ struct hsgn_ctx {
   // certify its truncation; the block then runs again with twice the margin
   bool halo_retry = false;
   int32_t n_retry = 0;                  // blocks run again since the state was loaded
+  std::vector<double> h_margin_inst;    // per-instance margins grown by the retry (empty: none)
   double* rb_state = nullptr;           // 4 x ncell: h, q, m, W
   double* rb_t = nullptr;               // n_inst times
   unsigned long long* rb_sp = nullptr;  // 3 x n_inst: speed bounds, depth maxima
@@ -608,10 +609,11 @@ int make_plan(hsgn_ctx* c) {
     const int Lmax = WN / 4;
     // the halo estimate of the loaded state (reported for every instance)
     const bool have_state = !c->h_smax.empty() && c->h_smax[j] > 0 && c->h_hmax[j] > 0;
+    const double margin = c->h_margin_inst.empty() ? c->halo_margin : c->h_margin_inst[j];
     const int L = !have_state ? 0
-                  : sgn ? sgn_halo_width(p, c->h_hmax[j], c->halo_margin)
+                  : sgn ? sgn_halo_width(p, c->h_hmax[j], margin)
                         : halo_width(p, c->h_smax[j], c->h_hmax[j],
-                                     c->order == 1 ? 1.0 : hsgn::kGamma, c->halo_margin);
+                                     c->order == 1 ? 1.0 : hsgn::kGamma, margin);
     c->h_halo[j] = L;
     if (mj != HSGN_SOLVER_EXACT && have_state) {
       auto add = [&](int ws, int wl, int cs, int cl, int flags) {
@@ -865,9 +867,10 @@ constexpr double kMaxMargin = 64.0;  // the largest halo margin (hsgn_set_halo_m
 // and SGN schemes, whose windows certify their truncation), the mutable
 // state is copied first and the status read after the block (synchronising
 // the stream); if a window flagged its truncation, the copy is restored,
-// the halo margin doubled (up to kMaxMargin) and the solver re-planned, and
-// the block runs again.  Other flags, and a window flag at the largest
-// margin, are left for hsgn_status.
+// the halo margin of each flagged instance doubled (up to kMaxMargin; the
+// other instances keep theirs) and the solver re-planned, and the block
+// runs again.  Other flags, and a window flag at the largest margin, are
+// left for hsgn_status.
 template <class Chunk>
 int run_retrying(hsgn_ctx* c, Chunk chunk) {
   if (!c->halo_retry || c->scheme == HSGN_SCHEME_EXPLICIT) return chunk();
@@ -896,16 +899,21 @@ int run_retrying(hsgn_ctx* c, Chunk chunk) {
     HIPCHK(c, hipMemcpyAsync(flags.data(), c->d_status, ni * sizeof(int32_t),
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    bool win = false;
-    for (size_t j = 0; j < ni; ++j) win |= (flags[j] & hsgn::kFlagWindow) != 0;
-    if (!win || c->halo_margin >= kMaxMargin) return HSGN_OK;
+    // the flagged instances whose margin can still grow
+    if (c->h_margin_inst.empty()) c->h_margin_inst.assign(ni, c->halo_margin);
+    bool grow = false;
+    for (size_t j = 0; j < ni; ++j)
+      grow |= (flags[j] & hsgn::kFlagWindow) != 0 && c->h_margin_inst[j] < kMaxMargin;
+    if (!grow) return HSGN_OK;
     c->cur = cur0;
     c->nxt = nxt0;
     rc = retry_copy(c, false);
     if (rc) return rc;
-    c->halo_margin = std::min(kMaxMargin, 2.0 * c->halo_margin);
+    for (size_t j = 0; j < ni; ++j)
+      if (flags[j] & hsgn::kFlagWindow)
+        c->h_margin_inst[j] = std::min(kMaxMargin, 2.0 * c->h_margin_inst[j]);
     ++c->n_retry;
-    roctxMarkA("hsgn halo retry: block runs again with twice the margin");
+    roctxMarkA("hsgn halo retry: block runs again, flagged instances at twice their margin");
     rc = make_plan(c);
     if (rc) return rc;
   }
@@ -1217,7 +1225,9 @@ int hsgn_set_halo_retry(hsgn_ctx* c, int32_t enable) {
 
 int hsgn_halo_state(hsgn_ctx* c, double* h_margin, int32_t* h_retries) {
   if (!c) return HSGN_EINVAL;
-  if (h_margin) *h_margin = c->halo_margin;
+  if (h_margin)
+    for (int j = 0; j < c->n_inst; ++j)
+      h_margin[j] = c->h_margin_inst.empty() ? c->halo_margin : c->h_margin_inst[j];
   if (h_retries) *h_retries = c->n_retry;
   return HSGN_OK;
 }
@@ -1431,6 +1441,7 @@ int hsgn_set_halo_margin(hsgn_ctx* c, double margin) {
   if (!(margin > 0.0 && margin <= kMaxMargin))
     return fail(c, HSGN_EINVAL, "hsgn_set_halo_margin: margin %g outside (0, 64]", margin);
   c->halo_margin = margin;
+  c->h_margin_inst.clear();  // the retry's per-instance margins start over
   int rc = enter(c);
   if (rc) return rc;
   rc = make_plan(c);

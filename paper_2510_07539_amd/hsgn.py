@@ -173,16 +173,19 @@ class Solver:
 
     def set_halo_retry(self, enable=True):
         """Halo retry: a block whose windows could not certify their
-        truncation is run again from a copy of its initial state with twice
-        the halo margin (hsgn_run and hsgn_step then synchronise)."""
+        truncation is run again from a copy of its initial state, the
+        flagged instances at twice their halo margin (hsgn_run and
+        hsgn_step then synchronise)."""
         self._check(lib().hsgn_set_halo_retry(self._h, 1 if enable else 0), "hsgn_set_halo_retry")
 
     def halo_state(self):
-        """(current halo margin, blocks run again since the state was loaded)."""
-        m = C.c_double()
+        """(halo margin of every instance, blocks run again since the state
+        was loaded)."""
+        m = np.zeros(self.n_inst, dtype=np.float64)
         r = C.c_int32()
-        self._check(lib().hsgn_halo_state(self._h, C.byref(m), C.byref(r)), "hsgn_halo_state")
-        return m.value, r.value
+        self._check(lib().hsgn_halo_state(self._h, m.ctypes.data_as(C.POINTER(C.c_double)),
+                                          C.byref(r)), "hsgn_halo_state")
+        return m, r.value
 
     def set_launch(self, launch):
         """Window-stage launch: "grid" (one workgroup per window) or

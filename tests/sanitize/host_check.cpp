@@ -9,6 +9,7 @@
 // a call returns an unexpected code.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -158,10 +159,12 @@ void run_context(const char* name, const Batch& B, bool tune) {
     expect("hsgn_set_halo_retry", hsgn_set_halo_retry(c, 1), HSGN_OK, c);
     expect("hsgn_run (retrying)", hsgn_run(c, 5, 2), HSGN_OK, c);
     expect("hsgn_step (retrying)", hsgn_step(c, 3), HSGN_OK, c);
-    double margin = 0.0;
+    std::vector<double> margins(ni, 0.0);
     int32_t retries = -1;
-    expect("hsgn_halo_state", hsgn_halo_state(c, &margin, &retries), HSGN_OK, c);
-    std::printf("%-40s margin %g, %d blocks run again\n", "", margin, retries);
+    expect("hsgn_halo_state", hsgn_halo_state(c, margins.data(), &retries), HSGN_OK, c);
+    std::printf("%-40s margins %g .. %g, %d blocks run again\n", "",
+                *std::min_element(margins.begin(), margins.end()),
+                *std::max_element(margins.begin(), margins.end()), retries);
     expect("hsgn_status (after retries)", hsgn_status(c, flags.data()), HSGN_OK, c);
     expect("hsgn_set_halo_retry (bad)", hsgn_set_halo_retry(c, 2), HSGN_EINVAL, c);
     expect("hsgn_set_halo_retry (off)", hsgn_set_halo_retry(c, 0), HSGN_OK, c);
