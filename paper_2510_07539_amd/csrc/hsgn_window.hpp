@@ -495,16 +495,18 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
   };
   double va[NR], vb[NR], vc[NR];
   // instance-relative cells of the staged elements; past the window's
-  // staged cells cell_of repeats the last one, so every load is in bounds.
-  // Stage 2 loads and stages them unguarded (the guards cost more than the
-  // few extra loads); stage 1 keeps the guards (unguarded, its first two
-  // rounds' loads spill registers)
+  // staged cells cell_of repeats the last one, so every load is in bounds
+  // and the loads need no guard (the guards cost more than the few extra
+  // loads), except stage 1's first two rounds, which are loaded together
+  // and spill registers unguarded.  The LDS writes of every round but the
+  // last stay inside the buffers and need no guard either: no row reads
+  // the elements past the staged cells.
   constexpr bool kNoGuard = STAGE == 2;
   int cidx[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int i = t + r * NT;
-    cidx[r] = (kNoGuard || i < SLn) ? cell_of(i) : 0;
+    cidx[r] = cell_of(i);
   }
   // loads of round f into (xa, xb, xc): U^n, U(1) and the bed
   auto load_into = [&](int f, double* xa, double* xb, double* xc) {
@@ -512,7 +514,7 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
     const double* u1 = fld(f, true);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      if (kNoGuard || t + r * NT < SLn) {
+      if (kNoGuard || f >= 2 || t + r * NT < SLn) {
         xa[r] = (un + base)[cidx[r]];
         if (STAGE == 2) xb[r] = (u1 + base)[cidx[r]];
         if (BED && f == 0 && useb) xc[r] = (A.b + base)[cidx[r]];
@@ -527,9 +529,7 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int i = t + r * NT;
-      // elements past the staged cells but inside the buffers (every round
-      // but the last) are written unguarded: no row reads them
-      if ((kNoGuard && r < NR - 1) || i < SLn) {
+      if (r < NR - 1 || i < SLn) {
         double* od = f == 0 ? L.u.st.ho : L.u.st.o;  // the old depth stays until the rows
         if (STAGE == 1) {
           ebuf(f)[spad(i)] = xa[r];
