@@ -42,11 +42,11 @@ TRAFFIC = [
      "fetch_bytes": 2232887832, "write_bytes": 1118343168, "bytes_per_launch": 3351231000},
     {"kernel": "sgn_solve", "workload": "batched_flat", "scheme": "sgn", "halo_margin": 2.0,
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp",
-                 "hsgn_explicit.hpp", "hsgn_sgn.hpp"], "hash": "183c7815aff95a8d",
+                 "hsgn_explicit.hpp", "hsgn_sgn.hpp"], "hash": "901776fdc3f2f538",
      "fetch_bytes": 676269416, "write_bytes": 273330176, "bytes_per_launch": 949599592},
     {"kernel": "sgn_solve", "workload": "batched_flat", "scheme": "sgn", "halo_margin": 1.0,
      "sources": ["hsgn_kernels.hpp", "hsgn_window.hpp", "hsgn_adjoint.hpp",
-                 "hsgn_explicit.hpp", "hsgn_sgn.hpp"], "hash": "183c7815aff95a8d",
+                 "hsgn_explicit.hpp", "hsgn_sgn.hpp"], "hash": "901776fdc3f2f538",
      "fetch_bytes": 646755101, "write_bytes": 273320395, "bytes_per_launch": 920075496},
 ]
 
