@@ -164,9 +164,9 @@ def cpu_model():
 def cpu_baseline(wl, budget_s=15.0, n_sample=1024, max_steps=200, order=2):
     """The oracle (OpenMP over instances, all host threads) on a bounded
     sample: the first n_sample instances, in chunks of 5 steps until the time
-    budget is spent or max_steps are done (past about 370 steps one
-    instance of the batched bar loses coercivity, so the sample stays in the
-    range the benchmark times).  The value is the median of the chunks'
+    budget is spent or max_steps are done (in step 280 an instance of the
+    batched bar becomes non-physical, so the sample stays in the range the
+    benchmark times).  The value is the median of the chunks'
     rates; the mean over the whole sample is reported beside it."""
     import numpy as np
     import oracle as O

@@ -46,6 +46,20 @@ def test_oracle_nan_in_the_bed():
     assert rc == O.ENONPHYS
 
 
+def test_oracle_first_failure_of_the_batch_is_instance_1469_at_step_280():
+    """The first instance of the batched bar to fail: 1469 (N = 566, lambda
+    = 1e4) becomes non-physical in step 280; the GPU test
+    test_nonphysical_instance_flagged_at_the_oracle_step holds the library
+    to that step."""
+    wl = WL.batched_bar().subset([1469], name="bar-1469")
+    n, prm, b, U0 = wl.instance(0)
+    p = O.make_params(**prm)
+    rc, _, _ = O.run(p, b, U0, 0.0, 279)
+    assert rc == O.OK
+    rc, _, _ = O.run(p, b, U0, 0.0, 280)
+    assert rc == O.ENONPHYS
+
+
 @pytest.mark.slow
 def test_oracle_coercivity_loss_of_bar_instance_84():
     wl = WL.batched_bar().subset([84], name="bar-84")

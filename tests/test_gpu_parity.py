@@ -387,6 +387,36 @@ def test_window_certificate_flags_an_insufficient_halo(solver):
     compare(wl, 3, label="far from equilibrium, exact", solver="exact", state_sens=True)
 
 
+@pytest.mark.parametrize("solver", ["auto_small", "exact"])
+def test_nonphysical_instance_flagged_at_the_oracle_step(solver):
+    """Instance 1469 of the batched bar (N = 566, lambda = 1e4), the first of
+    the batch to fail: the oracle's step 280 produces a non-physical state.
+    Run within the full batch (graph blocks of 40 steps, halo margin 1 with
+    the halo retry, as the benchmark runs), the library must flag that
+    instance, and no other, with the non-physical bit in step 280, and
+    none before."""
+    from paper_2510_07539_amd.hsgn import HSGN_ENONPHYS
+    Solver = _solver()
+    wl = WL.batched_bar()
+    j = 1469
+    n, prm, b, U0 = wl.instance(j)
+    p = O.make_params(**prm)
+    assert O.run(p, b, U0, 0.0, 279)[0] == 0 and O.run(p, b, U0, 0.0, 280)[0] == 1
+    s = Solver.from_workload(wl, solver=solver)
+    if solver == "auto_small":
+        s.set_halo_margin(1.0)
+        s.set_halo_retry(True)
+    s.run(240, block=40)
+    s.step(39)
+    rc, flags = s.status()
+    assert rc == 0, (rc, np.nonzero(flags))
+    s.step(1)
+    rc, flags = s.status()
+    assert rc == HSGN_ENONPHYS and flags[j] & 1, (rc, flags[j])
+    assert np.nonzero(flags)[0].tolist() == [j]
+    s.close()
+
+
 @pytest.mark.parametrize("solver", ["auto", "exact"])
 def test_coercivity_loss_flagged_at_the_oracle_step(solver):
     """Instance 84 of the batched bar (N = 586, lambda = 1e3): its solitary
