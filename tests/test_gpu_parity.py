@@ -948,14 +948,18 @@ def test_sgn_rejects_bed_adjoint_and_autotune():
     s.close()
 
 
-@pytest.mark.parametrize("solver", SGN_SOLVERS)
-def test_sgn_batched_flat_full_size_sampled(solver):
+@pytest.mark.parametrize("solver,margin", [(m, None) for m in SGN_SOLVERS] + [("auto", 1.0)])
+def test_sgn_batched_flat_full_size_sampled(solver, margin):
+    """The flat batch with the SGN solver at full size, in both forms of the
+    phi solve at the default halo margin and at margin 1 with the halo retry
+    (the benchmark's configuration); instances sampled for the oracle."""
     wl = WL.batched_flat()
     insts = list(range(0, wl.n_inst, wl.n_inst // 16))
     sizes = wl.sizes()
     insts.append(int(np.argmax(sizes)))  # the most windows
     compare(wl, 20, use_run=True, block=10, insts=sorted(set(insts)),
-            label="SGN batched flat full size", scheme=SGNS, solver=solver)
+            label="SGN batched flat full size", scheme=SGNS, solver=solver,
+            margin=margin, retry=margin is not None)
 
 
 def test_dam_break_full_run():
@@ -1056,14 +1060,16 @@ def test_long_periodic_full_size_properties():
             assert dev[fld] <= max(1e-11 * fmax, 8.0 * sens[fld], 1e-300), ("hqmW"[fld], dev, sens)
 
 
-@pytest.mark.parametrize("solver", SOLVERS)
-def test_long_periodic_full_size_vs_stored_oracle(solver):
+@pytest.mark.parametrize("solver,margin", [(m, None) for m in SOLVERS] + [("auto_small", 1.0)])
+def test_long_periodic_full_size_vs_stored_oracle(solver, margin):
     """C4 at its full size (2^24 cells) after 100 graph-captured steps
     against the oracle's values stored by tests/golden/make_c4_golden.py
     (4096 seeded cells plus both ends of the ring): the state bar (relative
     to the oracle's maxima over all cells) and the per-field bars with the
     oracle's own half-ulp sensitivity at the same cells; the time reached;
-    the sum of h against the oracle's."""
+    the sum of h against the oracle's.  In the three solver modes at the
+    default halo margin, and at margin 1 with the halo retry (the
+    benchmark's configuration)."""
     d = np.load(GOLDEN_C4)
     nsteps = int(d["nsteps"])
     Solver = _solver()
@@ -1071,6 +1077,9 @@ def test_long_periodic_full_size_vs_stored_oracle(solver):
     note("C4 full vs stored oracle [%s]: %d cells, %d steps, %d sampled cells" % (
         solver, wl.n_cells, nsteps, len(d["idx"])))
     s = Solver.from_workload(wl, solver=solver)
+    if margin is not None:
+        s.set_halo_margin(margin)
+        s.set_halo_retry(True)
     s.run(nsteps, block=100)
     rc, _ = s.status()
     assert rc == 0, rc
