@@ -1159,7 +1159,8 @@ __device__ __forceinline__ void win_one(const WinArgs& W, WinLds<NT, K, BED>& L,
       // suffices for global memory on this target); a pair that wraps around
       // a periodic ring, or a last odd cell, is stored one cell at a time
       // (measured: stage 2 -2.8 %; stage 1, whose records live in fewer
-      // registers, +0.7 %, so it keeps single-cell stores)
+      // registers, +0.7 %, and +0.2 % again once the stores were
+      // non-temporal, so it keeps single-cell stores)
       typedef double d2a8 __attribute__((ext_vector_type(2), aligned(8)));
       static_assert(NS % 2 == 0, "paired stores cover the window in NS / 2 rounds");
 #pragma unroll
